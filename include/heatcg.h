@@ -1,0 +1,198 @@
+/*
+ * heatcg.h -- C ABI of libheatcg.so: the explicit 7-point heat update and
+ * Conjugate Gradient on the 7-point Laplacian, for AMD MI355X (gfx950).
+ *
+ * Paper: "Mathematical Details" (Eqs. 1-6, Pseudocode alg:heat3d), the
+ * one-GPU baseline and the Interior / Boundary kernels of the multi-GPU
+ * versions (Pseudocodes alg:1gpu-base, alg:interior-kernel,
+ * alg:boundary-kernel), and the CG case study (Pseudocode alg:spmv).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is a DEVICE pointer on the current HIP device
+ *    (e.g. the data pointer of a contiguous torch CUDA tensor).  The caller
+ *    allocates and owns every buffer; the library keeps no pointer after a
+ *    call returns.
+ *  - 3-D arrays are stored with x fastest and z slowest:
+ *    a[(k*ny + j)*nx + i].  This is the paper's u[k, j, i] ordering.
+ *  - Arguments are validated before any device work.  On a validation
+ *    error nothing is launched and no buffer is touched.
+ *  - Return value: HC_OK (0), a positive soft status, or a negative error.
+ *    hc_strerror() names a code; hc_last_error_message() gives the detail
+ *    of the last failure on the calling thread (e.g. a HIP error string).
+ *  - hc_stream_t is a hipStream_t.  NULL means the device's null stream.
+ */
+#ifndef HEATCG_H
+#define HEATCG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hc_stream_t;
+
+enum hc_status {
+    HC_OK = 0,
+    HC_ENOTCONV = 1,     /* CG reached maxit; x holds the last iterate    */
+    HC_EINVAL = -1,      /* bad pointer, size, dtype, mode or count        */
+    HC_EUNSTABLE = -2,   /* r not finite or outside [0, 1/6]               */
+    HC_EALIAS = -3,      /* input and output buffers overlap               */
+    HC_ENOMEM = -4,      /* device allocation failed                       */
+    HC_EHIP = -5,        /* a HIP runtime call or kernel launch failed     */
+    HC_EBREAKDOWN = -6,  /* CG: p.Ap <= 0 (operator not SPD in practice)   */
+    HC_ENONFINITE = -7   /* CG: a scalar became NaN or infinite            */
+};
+
+enum hc_dtype { HC_F64 = 0, HC_F32 = 1, HC_BF16 = 2 };
+
+enum hc_heat_mode {
+    HC_HEAT_SPLIT = 0, /* Interior kernel on the caller's stream and the
+                          Boundary-plane kernel on a second stream,
+                          joined by events every step                      */
+    HC_HEAT_FUSED = 1, /* one z-marching kernel over every updated plane   */
+    HC_HEAT_PLAIN = 2  /* one thread per node, every neighbour loaded
+                          from memory (the straightforward GPU form)      */
+};
+
+/*
+ * heat_step -- advance the heat equation by `steps` explicit steps.
+ *
+ * Computes, for every interior node and each step (Eq. 4 with a constant
+ * coefficient kappa = alpha and no source, i.e. the 7-point FTCS update):
+ *     u_new = u + r * (((x- + x+) + (y- + y+)) + (z- + z+) - 6 u)
+ * with r = alpha*dt/h^2, followed by a swap of u and u_new (alg:heat3d).
+ *
+ *  u       [in/out] nx*ny*nz FP64, device.  u^0 on entry, u^steps on
+ *          return.  Its outermost layer holds the Dirichlet data and is
+ *          never written (the paper uses zero data, Eq. 5).
+ *  u_new   [scratch] nx*ny*nz FP64, device, must not overlap u.  On entry
+ *          its outermost layer is overwritten with u's; on return it holds
+ *          u^(steps-1) when steps >= 1.
+ *  nx,ny,nz  stored edge lengths including the Dirichlet layer, each >= 3;
+ *          (nx-2)(ny-2)(nz-2) nodes are updated.
+ *  r       finite, 0 <= r <= 1/6 (stability and the discrete maximum
+ *          principle of the 3-D scheme), else HC_EUNSTABLE.
+ *  steps   >= 0; 0 is a no-op.
+ *
+ * Runs the Interior/Boundary split (HC_HEAT_SPLIT, one slab) and BLOCKS
+ * until the result is in u, so kernel faults are reported here.
+ */
+int heat_step(double *u, double *u_new, int nx, int ny, int nz, double r,
+              int steps);
+
+/*
+ * heat_step_ex -- heat_step with the element type, kernel form, slab count
+ * and stream chosen by the caller.  Enqueues the work on `stream` and
+ * returns without waiting (stream order is the only ordering).
+ *
+ *  dtype  HC_F64 (the paper's precision).  Other values are reserved and
+ *         return HC_EINVAL.
+ *  mode   an hc_heat_mode.
+ *  parts  number of equal k-slabs the split form treats as separate
+ *         subdomains (the paper's decomposition along k, Methodology): the
+ *         first and last plane of every slab are Boundary planes, the rest
+ *         Interior.  1 <= parts <= min(64, (nz-2)/2); must be 1 unless
+ *         mode == HC_HEAT_SPLIT.
+ *  stream the stream the work is ordered on.  The Boundary kernels run on
+ *         an internal stream of the same device that joins `stream` at
+ *         every step through events.
+ */
+int heat_step_ex(void *u, void *u_new, int nx, int ny, int nz, double r,
+                 int steps, int dtype, int mode, int parts, hc_stream_t stream);
+
+/*
+ * cg_solve -- solve A x = b with Conjugate Gradient (the CG case study),
+ * A the 7-point Laplacian 6 I - (face neighbours) on an n x n x n box with
+ * zero Dirichlet data outside the box (no ghost layer is stored).
+ *
+ *  b      [in]  n^3 FP64, device.
+ *  x      [in/out] n^3 FP64, device, must not overlap b: the initial guess
+ *         on entry, the last iterate on return.
+ *  tol    > 0: stop once ||r_k||_2 <= tol * ||b||_2 (recursive residual);
+ *         the true residual ||b - A x|| is then recomputed and, if it is
+ *         still above tol * ||b||, the iteration restarts from x (counted
+ *         against maxit).
+ *  maxit  >= 0 iterations in total.
+ *
+ * Blocks until done.  Returns HC_OK, HC_ENOTCONV (maxit reached; x holds
+ * the last iterate and a later call can resume from it), HC_EBREAKDOWN or
+ * HC_ENONFINITE.  ||b|| = 0 sets x = 0 and returns HC_OK.  Uses a
+ * workspace the library allocates per device and keeps until unload;
+ * hc_cg_last_info() returns the iteration count and true relative
+ * residual of the calling thread's last cg_solve.
+ */
+int cg_solve(const double *b, double *x, int n, double tol, int maxit);
+
+/*
+ * cg_solve_ex -- cg_solve on an nx x ny x nz box, with a caller workspace
+ * (work may be NULL: the library's own is used) and stream.
+ *  work_bytes  >= cg_workspace_bytes(nx, ny, nz) when work != NULL.
+ *  iters, true_relres  optional outputs (may be NULL).
+ * Blocks until done (the convergence test reads 64 bytes per batch of
+ * iterations back to the host).
+ */
+int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol,
+                int maxit, void *work, size_t work_bytes, hc_stream_t stream,
+                int *iters, double *true_relres);
+
+/* Bytes of device workspace cg_solve_ex needs (0 for invalid sizes). */
+size_t cg_workspace_bytes(int nx, int ny, int nz);
+
+/* Iteration count and true relative residual of this thread's last CG. */
+void hc_cg_last_info(int *iters, double *true_relres);
+
+/*
+ * hc_lap7_apply -- y = A x with the CG operator above (the SpMV of the CG
+ * case study, Pseudocode alg:spmv, one row per node, matrix-free):
+ *     y = 6 x - (((x- + x+) + (y- + y+)) + (z- + z+)), outside = 0.
+ * x, y: nx*ny*nz FP64 device arrays, not overlapping.  Enqueued on
+ * `stream`, does not wait.
+ */
+int hc_lap7_apply(const double *x, double *y, int nx, int ny, int nz,
+                  hc_stream_t stream);
+
+/*
+ * hc_copy_probe -- dst[0:bytes) = src[0:bytes) with a streaming kernel of
+ * the library's own (the practical HBM ceiling the stencil is compared
+ * with).  bytes must be a multiple of 16 and both pointers 16-byte
+ * aligned and non-overlapping.  Enqueued on `stream`, does not wait.
+ */
+int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream);
+
+/* Name of a status code (static string). */
+const char *hc_strerror(int code);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *hc_last_error_message(void);
+
+/*
+ * Kernel timing for measurement.  While enabled, every launch of the
+ * library's kernels is bracketed by HIP events on the stream it runs on,
+ * and the algorithmic bytes it must move are added up per kernel kind.
+ * hc_prof_enable(1) clears the counters; hc_prof_read waits for the
+ * recorded launches and returns the total duration (ms), the launch count
+ * and the algorithmic bytes of one kernel kind.
+ */
+enum hc_kernel_kind {
+    HC_K_HEAT_INTERIOR = 0,
+    HC_K_HEAT_BOUNDARY = 1,
+    HC_K_HEAT_FUSED = 2,
+    HC_K_HEAT_PLAIN = 3,
+    HC_K_CG_DIRECTION = 4, /* p = r + beta p, A p, p.Ap   */
+    HC_K_CG_UPDATE = 5,    /* x += alpha p, r -= alpha A p, r.r */
+    HC_K_CG_RESIDUAL = 6,  /* r = b - A x, r.r, b.b      */
+    HC_K_LAP7 = 7,
+    HC_K_COPY = 8,
+    HC_K_COUNT = 9
+};
+int hc_prof_enable(int on);
+int hc_prof_read(int kind, double *total_ms, long long *launches,
+                 double *algo_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEATCG_H */

@@ -1,0 +1,159 @@
+"""CPU FP64 oracle for the 7-point heat update and 7-point-Laplacian CG.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product library
+never loads it and shares no code with it; the only thing both sides share
+is the seeded input recipes, which hold none of the method's arithmetic.
+
+The arithmetic lives in ``heatcg_oracle.c`` (plain loops, FP64, compiled
+without floating-point contraction); this module only builds it and marshals
+numpy arrays through ctypes.  Arrays are C-ordered ``(nz, ny, nx)``: x
+fastest, z slowest, as the paper lays out ``u[k, j, i]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "heatcg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-std=c11", "-Wall", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _configure(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    L = ctypes.c_long
+    lib.oracle_heat_sweep_f64.argtypes = [dp, dp, L, L, L, ctypes.c_double]
+    lib.oracle_heat_sweep_f64.restype = None
+    lib.oracle_heat_f64.argtypes = [dp, L, L, L, ctypes.c_double, L]
+    lib.oracle_heat_f64.restype = ctypes.c_int
+    lib.oracle_lap7_apply.argtypes = [dp, dp, L, L, L]
+    lib.oracle_lap7_apply.restype = None
+    lib.oracle_dot.argtypes = [dp, dp, L, L, L]
+    lib.oracle_dot.restype = ctypes.c_double
+    lib.oracle_cg.argtypes = [dp, dp, L, L, L, ctypes.c_double, L,
+                              ctypes.POINTER(L), dp, dp]
+    lib.oracle_cg.restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    _lib = _configure(ctypes.CDLL(_LIB))
+    return _lib
+
+
+class using_library:
+    """Temporarily route every oracle call to another build of the same
+    source (used by the test that plants mistakes in the oracle)."""
+
+    def __init__(self, path: str):
+        self._path = path
+        self._saved = None
+
+    def __enter__(self):
+        global _lib
+        self._saved = _load()
+        _lib = _configure(ctypes.CDLL(self._path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        return False
+
+
+def source_path() -> str:
+    return _SRC
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64_c(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("expected a 3-D (nz, ny, nx) array")
+    return a
+
+
+def heat_sweep(u: np.ndarray, r: float) -> np.ndarray:
+    """One explicit 7-point step (Eq. 4, kappa constant, f = 0); boundary kept."""
+    u = _f64_c(u)
+    out = u.copy()
+    nz, ny, nx = u.shape
+    _load().oracle_heat_sweep_f64(_ptr(u), _ptr(out), nx, ny, nz, float(r))
+    return out
+
+
+def heat(u0: np.ndarray, r: float, steps: int) -> np.ndarray:
+    """``steps`` explicit steps from ``u0`` (not modified); returns u^steps."""
+    u = _f64_c(u0).copy()
+    nz, ny, nx = u.shape
+    rc = _load().oracle_heat_f64(_ptr(u), nx, ny, nz, float(r), int(steps))
+    if rc != 0:
+        raise MemoryError("oracle_heat_f64 returned %d" % rc)
+    return u
+
+
+def lap7_apply(x: np.ndarray) -> np.ndarray:
+    """y = A x, A = 6 I - (face neighbours), zero Dirichlet data outside."""
+    x = _f64_c(x)
+    y = np.empty_like(x)
+    nz, ny, nx = x.shape
+    _load().oracle_lap7_apply(_ptr(x), _ptr(y), nx, ny, nz)
+    return y
+
+
+def dot(a: np.ndarray, b: np.ndarray) -> float:
+    """Compensated dot product in a thread-count-independent order."""
+    a = _f64_c(a)
+    b = _f64_c(b)
+    nz, ny, nx = a.shape
+    return float(_load().oracle_dot(_ptr(a), _ptr(b), nx, ny, nz))
+
+
+class CGResult:
+    __slots__ = ("x", "status", "iters", "relres_true", "history")
+
+    def __init__(self, x, status, iters, relres_true, history):
+        self.x = x
+        self.status = status
+        self.iters = iters
+        self.relres_true = relres_true
+        self.history = history
+
+
+def cg(b: np.ndarray, tol: float, maxit: int, x0: np.ndarray | None = None) -> CGResult:
+    """Textbook CG on the 7-point Laplacian; see ``oracle_cg`` for statuses."""
+    b = _f64_c(b)
+    x = np.zeros_like(b) if x0 is None else _f64_c(x0).copy()
+    nz, ny, nx = b.shape
+    iters = ctypes.c_long(0)
+    rel = ctypes.c_double(0.0)
+    hist = np.full(int(maxit) + 1, np.nan)
+    st = _load().oracle_cg(_ptr(b), _ptr(x), nx, ny, nz, float(tol), int(maxit),
+                           ctypes.byref(iters), ctypes.byref(rel), _ptr(hist))
+    return CGResult(x, int(st), int(iters.value), float(rel.value),
+                    hist[: iters.value + 1].copy())

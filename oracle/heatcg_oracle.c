@@ -1,0 +1,254 @@
+/*
+ * heatcg_oracle.c -- plain, slow, obviously correct CPU reference for the
+ * 7-point explicit heat update and for Conjugate Gradient on the 7-point
+ * Laplacian.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or constant with the
+ * HIP path.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no -ffast-math:
+ * every sum below is evaluated in the order it is written).
+ *
+ * Layout of every 3-D array: a[(k*ny + j)*nx + i], i (x) fastest, k (z)
+ * slowest -- the paper initialises and partitions the domain in the order
+ * k, j, i (Methodology, "Multi-GPU OpenMP Offloading Versions"; the
+ * COMPUTE_SINGLE_GPU pseudocode indexes u[k,j,i]).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX(i, j, k, nx, ny) ((((long)(k)) * (ny) + (j)) * (nx) + (i))
+
+/* ------------------------------------------------------------------------ */
+/* Heat equation, constant coefficient                                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * One explicit (forward-Euler) step of the heat equation on every interior
+ * node, Eq. (4) of "Mathematical Details" with a constant coefficient
+ * (kappa = alpha) and no source (f = 0):
+ *
+ *   u_new = u + r * (sum of the 6 face neighbours - 6 u),  r = alpha dt / h^2
+ *
+ * The neighbour sum is taken in the fixed order
+ *   ((x- + x+) + (y- + y+)) + (z- + z+)
+ * and then 6*u is subtracted; the node value is added last.  Boundary nodes
+ * (the outermost layer) are Dirichlet nodes and are never written.
+ */
+void oracle_heat_sweep_f64(const double *u, double *un, long nx, long ny,
+                           long nz, double r)
+{
+    const long sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 1; k < nz - 1; ++k)
+        for (long j = 1; j < ny - 1; ++j)
+            for (long i = 1; i < nx - 1; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const double c = u[p];
+                const double nsum = ((u[p - sx] + u[p + sx]) +
+                                     (u[p - sy] + u[p + sy])) +
+                                    (u[p - sz] + u[p + sz]);
+                const double lap = nsum - 6.0 * c;
+                un[p] = c + r * lap;
+            }
+}
+
+/*
+ * `steps` explicit steps with ping-pong buffers and a swap after every step,
+ * as in the paper's OpenMP solver (Pseudocode alg:heat3d) and its one-GPU
+ * baseline (alg:1gpu-base).  `u` holds u^0 on entry and u^steps on return.
+ * The step count is an integer (the paper's `while t < T` with a floating
+ * t can take one step more or less).  Returns 0, or -4 when out of memory.
+ */
+int oracle_heat_f64(double *u, long nx, long ny, long nz, double r, long steps)
+{
+    const long n = nx * ny * nz;
+    if (steps <= 0)
+        return 0;
+    double *w = (double *)malloc((size_t)n * sizeof(double));
+    if (!w)
+        return -4;
+    memcpy(w, u, (size_t)n * sizeof(double)); /* boundary of w = boundary of u */
+    double *a = u, *b = w;
+    for (long s = 0; s < steps; ++s) {
+        oracle_heat_sweep_f64(a, b, nx, ny, nz, r);
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != u)
+        memcpy(u, a, (size_t)n * sizeof(double));
+    free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conjugate Gradient on the 7-point Laplacian                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * y = A x for the 7-point operator with zero Dirichlet data outside the box:
+ * (A x)_p = 6 x_p - (((x- + x+) + (y- + y+)) + (z- + z+)), a neighbour that
+ * falls outside [0,nx) x [0,ny) x [0,nz) counts as 0.  This is the SpMV of
+ * the paper's CG case study (Pseudocode alg:spmv, one row per point) with
+ * the 7-point stencil in place of the CSR arrays.
+ */
+void oracle_lap7_apply(const double *x, double *y, long nx, long ny, long nz)
+{
+    const long sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nz; ++k)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const double xm = (i > 0) ? x[p - 1] : 0.0;
+                const double xp = (i < nx - 1) ? x[p + 1] : 0.0;
+                const double ym = (j > 0) ? x[p - sy] : 0.0;
+                const double yp = (j < ny - 1) ? x[p + sy] : 0.0;
+                const double zm = (k > 0) ? x[p - sz] : 0.0;
+                const double zp = (k < nz - 1) ? x[p + sz] : 0.0;
+                const double nsum = ((xm + xp) + (ym + yp)) + (zm + zp);
+                y[p] = 6.0 * x[p] - nsum;
+            }
+}
+
+/* Neumaier-compensated running sum (value s, compensation c). */
+static void neumaier_add(double *s, double *c, double v)
+{
+    const double t = *s + v;
+    if (fabs(*s) >= fabs(v))
+        *c += (*s - t) + v;
+    else
+        *c += (v - t) + *s;
+    *s = t;
+}
+
+/*
+ * Dot product a.b in a fixed order that does not depend on the number of
+ * threads: one compensated sum per z-plane (index order), then a compensated
+ * sum of the plane sums in plane order.
+ */
+double oracle_dot(const double *a, const double *b, long nx, long ny, long nz)
+{
+    const long plane = nx * ny;
+    double *part = (double *)malloc((size_t)nz * sizeof(double));
+    if (!part)
+        return NAN;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nz; ++k) {
+        double s = 0.0, c = 0.0;
+        const double *pa = a + k * plane, *pb = b + k * plane;
+        for (long q = 0; q < plane; ++q)
+            neumaier_add(&s, &c, pa[q] * pb[q]);
+        part[k] = s + c;
+    }
+    double s = 0.0, c = 0.0;
+    for (long k = 0; k < nz; ++k)
+        neumaier_add(&s, &c, part[k]);
+    free(part);
+    return s + c;
+}
+
+/*
+ * Textbook (Hestenes-Stiefel) Conjugate Gradient for A x = b, the method of
+ * the paper's CG case study (SpMV, dot products, vector updates; Saad 2003):
+ *
+ *   r = b - A x;  p = r;  rho = r.r
+ *   loop:  q = A p;  alpha = rho / (p.q);  x += alpha p;  r -= alpha q;
+ *          rho' = r.r;  stop if sqrt(rho') <= tol ||b||;
+ *          beta = rho'/rho;  p = r + beta p;  rho = rho'
+ *
+ * `x` holds the initial guess on entry and the last iterate on return.
+ * `hist` (optional, maxit+1 entries) receives ||r_k|| / ||b|| for k = 0..iters.
+ * On return *iters is the number of completed iterations and *relres_true is
+ * ||b - A x|| / ||b|| recomputed from x.
+ * Returns 0 (converged), 1 (maxit reached), -4 (no memory),
+ * -6 (p.q <= 0: breakdown), -7 (a scalar went non-finite).
+ */
+int oracle_cg(const double *b, double *x, long nx, long ny, long nz, double tol,
+              long maxit, long *iters, double *relres_true, double *hist)
+{
+    const long n = nx * ny * nz;
+    const size_t bytes = (size_t)n * sizeof(double);
+    int status = 1;
+    long it = 0;
+    *iters = 0;
+    *relres_true = 0.0;
+
+    const double bnorm = sqrt(oracle_dot(b, b, nx, ny, nz));
+    if (bnorm == 0.0) {
+        memset(x, 0, bytes);
+        if (hist)
+            hist[0] = 0.0;
+        return 0;
+    }
+
+    double *r = (double *)malloc(bytes), *p = (double *)malloc(bytes),
+           *q = (double *)malloc(bytes);
+    if (!r || !p || !q) {
+        free(r);
+        free(p);
+        free(q);
+        return -4;
+    }
+
+    oracle_lap7_apply(x, q, nx, ny, nz);
+    for (long t = 0; t < n; ++t)
+        r[t] = b[t] - q[t];
+    memcpy(p, r, bytes);
+    double rho = oracle_dot(r, r, nx, ny, nz);
+    if (hist)
+        hist[0] = sqrt(rho) / bnorm;
+
+    if (sqrt(rho) <= tol * bnorm) {
+        status = 0;
+    } else {
+        while (it < maxit) {
+            oracle_lap7_apply(p, q, nx, ny, nz);
+            const double pq = oracle_dot(p, q, nx, ny, nz);
+            if (!isfinite(pq)) {
+                status = -7;
+                break;
+            }
+            if (pq <= 0.0) {
+                status = -6;
+                break;
+            }
+            const double alpha = rho / pq;
+            for (long t = 0; t < n; ++t) {
+                x[t] = x[t] + alpha * p[t];
+                r[t] = r[t] - alpha * q[t];
+            }
+            const double rho_new = oracle_dot(r, r, nx, ny, nz);
+            ++it;
+            if (hist)
+                hist[it] = sqrt(rho_new) / bnorm;
+            if (!isfinite(rho_new)) {
+                status = -7;
+                break;
+            }
+            if (sqrt(rho_new) <= tol * bnorm) {
+                status = 0;
+                break;
+            }
+            const double beta = rho_new / rho;
+            for (long t = 0; t < n; ++t)
+                p[t] = r[t] + beta * p[t];
+            rho = rho_new;
+        }
+    }
+
+    /* true residual b - A x */
+    oracle_lap7_apply(x, q, nx, ny, nz);
+    for (long t = 0; t < n; ++t)
+        r[t] = b[t] - q[t];
+    *relres_true = sqrt(oracle_dot(r, r, nx, ny, nz)) / bnorm;
+    *iters = it;
+    free(r);
+    free(p);
+    free(q);
+    return status;
+}

@@ -1,0 +1,193 @@
+"""Python binding of libheatcg.so: argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module checks
+torch tensors (device, dtype, contiguity, shape), passes their data
+pointers and the current torch stream through ctypes, and turns status
+codes into exceptions.  There is no fallback: if the library is not built,
+every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "cg_solve",
+           "cg_workspace_bytes", "lap7_apply", "copy_probe", "prof_enable",
+           "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libheatcg.so")
+
+HC_OK, HC_ENOTCONV = 0, 1
+HC_F64, HC_F32, HC_BF16 = 0, 1, 2
+MODES = {"split": 0, "fused": 1, "plain": 2}
+KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain": 3,
+           "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8}
+
+_lib = None
+
+
+class HeatCGError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("heatcg error %d: %s" % (code, message))
+        self.code = code
+        self.message = message
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libheatcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libheatcg.so is not built (%s); run __graft_entry__.build() "
+                          "or python -m paper_2608_11882_amd.build" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    llp = ctypes.POINTER(ctypes.c_longlong)
+    sig = {
+        "heat_step": (i, [vp, vp, i, i, i, d, i]),
+        "heat_step_ex": (i, [vp, vp, i, i, i, d, i, i, i, i, vp]),
+        "cg_solve": (i, [vp, vp, i, d, i]),
+        "cg_solve_ex": (i, [vp, vp, i, i, i, d, i, vp, sz, vp, ip, dp]),
+        "cg_workspace_bytes": (sz, [i, i, i]),
+        "hc_cg_last_info": (None, [ip, dp]),
+        "hc_lap7_apply": (i, [vp, vp, i, i, i, vp]),
+        "hc_copy_probe": (i, [vp, vp, sz, vp]),
+        "hc_strerror": (ctypes.c_char_p, [i]),
+        "hc_last_error_message": (ctypes.c_char_p, []),
+        "hc_prof_enable": (i, [i]),
+        "hc_prof_read": (i, [i, dp, llp, dp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def abi():
+    """The raw ctypes library (for tests of the C ABI itself)."""
+    return load()
+
+
+def strerror(code: int) -> str:
+    return load().hc_strerror(int(code)).decode()
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        lib = load()
+        raise HeatCGError(code, "%s: %s" % (lib.hc_strerror(code).decode(),
+                                            lib.hc_last_error_message().decode()))
+    return code
+
+
+def _stream_handle(t, stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t):
+    import torch
+    codes = {torch.float64: HC_F64, torch.float32: HC_F32, torch.bfloat16: HC_BF16}
+    if t.dtype not in codes:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return codes[t.dtype]
+
+
+def _require_cuda_3d(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("expected a CUDA (HIP) tensor")
+        if t.dim() != 3 or not t.is_contiguous():
+            raise ValueError("expected a contiguous 3-D (nz, ny, nx) tensor")
+        if t.shape != ts[0].shape or t.dtype != ts[0].dtype or t.device != ts[0].device:
+            raise ValueError("tensors must share shape, dtype and device")
+
+
+def heat_step(u, u_new, r: float, steps: int, mode: str = "split", parts: int = 1,
+              stream=None) -> None:
+    """Advance ``u`` by ``steps`` explicit 7-point steps (result in ``u``).
+
+    ``u_new`` is scratch of the same shape.  Enqueued on ``stream`` (default:
+    torch's current stream); does not synchronize.
+    """
+    _require_cuda_3d(u, u_new)
+    nz, ny, nx = u.shape
+    lib = load()
+    _check(lib.heat_step_ex(ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(u_new.data_ptr()),
+                            nx, ny, nz, float(r), int(steps), _dtype_code(u), MODES[mode],
+                            int(parts), _stream_handle(u, stream)))
+
+
+def cg_workspace_bytes(nx: int, ny: int, nz: int) -> int:
+    return int(load().cg_workspace_bytes(nx, ny, nz))
+
+
+def cg_solve(b, x, tol: float, maxit: int, work=None, stream=None):
+    """Solve A x = b (7-point Laplacian, zero Dirichlet) in place in ``x``.
+
+    Returns (status, iterations, true relative residual); status is 0
+    (converged) or 1 (maxit reached).  Errors raise HeatCGError.
+    """
+    import torch
+    _require_cuda_3d(b, x)
+    if b.dtype != torch.float64:
+        raise TypeError("cg_solve works in float64")
+    nz, ny, nx = b.shape
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    wptr, wbytes = None, 0
+    if work is not None:
+        if not work.is_cuda or not work.is_contiguous():
+            raise ValueError("work must be a contiguous CUDA tensor")
+        wptr, wbytes = ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size()
+    st = _check(load().cg_solve_ex(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                   nx, ny, nz, float(tol), int(maxit), wptr, wbytes,
+                                   _stream_handle(b, stream), ctypes.byref(it),
+                                   ctypes.byref(rel)))
+    return st, it.value, rel.value
+
+
+def lap7_apply(x, y, stream=None) -> None:
+    """y = A x (7-point Laplacian, zero outside); enqueued, no sync."""
+    import torch
+    _require_cuda_3d(x, y)
+    if x.dtype != torch.float64:
+        raise TypeError("lap7_apply works in float64")
+    nz, ny, nx = x.shape
+    _check(load().hc_lap7_apply(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                nx, ny, nz, _stream_handle(x, stream)))
+
+
+def copy_probe(src, dst, stream=None) -> None:
+    """dst = src with the library's streaming copy kernel; enqueued, no sync."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("expected contiguous CUDA tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(load().hc_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                nbytes, _stream_handle(src, stream)))
+
+
+def prof_enable(on: bool = True) -> None:
+    _check(load().hc_prof_enable(1 if on else 0))
+
+
+def prof_read(kind: str):
+    """(total_ms, launches, algorithmic_bytes) for one kernel kind."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_longlong(0)
+    b = ctypes.c_double(0.0)
+    _check(load().hc_prof_read(KERNELS[kind], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+    return ms.value, n.value, b.value

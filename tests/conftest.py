@@ -1,0 +1,29 @@
+"""Shared pytest configuration.
+
+Tests marked ``gpu`` run the HIP library on an MI355X through its C ABI;
+everything else runs on the CPU (oracle pins, input recipes, host-side
+argument validation, symbol exports).
+"""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line(
+        "markers", "gpu: needs an MI355X; calls the HIP library through its C ABI")
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP binding, with a device present (fails loudly otherwise)."""
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a visible GPU"
+    import paper_2608_11882_amd as hc
+    hc.load()  # raises if the HIP library is not built
+    return hc
