@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+One step = one full pass of the hot path over the benchmark inputs:
+  * heat: the 512^3 FP64 field (U[0,1] + central Gaussian hot spot, zero
+    Dirichlet data), r = 1/6.5, 1000 explicit 7-point steps, Interior
+    kernel on the caller's stream and Boundary planes on a second stream;
+  * CG: the 7-point Laplacian on 256^3 unknowns, b = A x* for a seeded
+    x* ~ U[-1,1], x0 = 0, relative residual 1e-10, FP64.
+Inputs are resident in HBM before the timed region; each step restarts both
+solves from the same inputs.  The headline value is the heat sweep's
+GLUP/s (1000 * 510^3 lattice-point updates per step over the heat phase's
+time); CG's time-to-1e-10 is reported beside it.
+
+Also reported: the dominant kernel's roofline (algorithmic bytes per launch
+over its average HIP-event duration, against 8 TB/s), the HBM traffic that
+rocprofv3 counters measured for it (when they were taken on the kernel as it
+is now), a copy-probe ceiling, the other heat kernel forms, and the CPU
+oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLUP/s + achieved HBM GB/s (7-pt heat 512³ FP64 vs FP32); CG time-to-1e-10"
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_interior_f64_512_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2608_11882_amd", "csrc", "heat_kernels.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(launch_bytes):
+    """Per-launch HBM bytes from the committed rocprofv3 counter summary,
+    or None when the counters were taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(u0_host, r, b_host, gpu_cg_iters, budget_s):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    n = u0_host.shape[0]
+    lups_per_step = (n - 2) ** 3
+    t = time.perf_counter()
+    oracle.heat(u0_host, r, 1)
+    one = time.perf_counter() - t
+    steps = max(1, int(0.6 * budget_s / max(one, 1e-3)))
+    log("cpu baseline: heat %d steps on %d^3" % (steps, n))
+    t = time.perf_counter()
+    oracle.heat(u0_host, r, steps)
+    heat_s = time.perf_counter() - t
+    glups = steps * lups_per_step / heat_s / 1e9
+    t = time.perf_counter()
+    oracle.cg(b_host, 1e-30, 2)
+    two = time.perf_counter() - t
+    iters = max(2, int(0.4 * budget_s / max(two / 2, 1e-3)))
+    log("cpu baseline: cg %d iterations on %d^3" % (iters, b_host.shape[0]))
+    t = time.perf_counter()
+    oracle.cg(b_host, 1e-30, iters)
+    cg_s = time.perf_counter() - t
+    per_it = cg_s / iters
+    return {
+        "value": glups,
+        "unit": "GLUP/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": ("heat: %d of the 1000 steps on the same 512^3 FP64 field (%.3g LUP, %.1f s); "
+                   "cg: %d iterations on the same 256^3 system (%.1f s, %.3f s/iteration, "
+                   "so about %.0f s for the GPU's %d iterations to 1e-10)"
+                   % (steps, steps * lups_per_step, heat_s, iters, cg_s, per_it,
+                      per_it * gpu_cg_iters, gpu_cg_iters)),
+        "cg_s_per_iteration": per_it,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU time budget of the oracle baseline (0 skips it)")
+    ap.add_argument("--heat-steps", type=int, default=1000, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2608_11882_amd as hc
+    from paper_2608_11882_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    hc.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    hcfg, ccfg = inputs.HEAT_LARGE, inputs.CG_LARGE
+    n, r, nsteps = hcfg["n"], hcfg["r"], args.heat_steps
+    m, tol, maxit = ccfg["n"], ccfg["tol"], ccfg["maxit"]
+
+    log("inputs: heat %d^3, cg %d^3" % (n, m))
+    u0_host = inputs.heat_large_f64(seed=hcfg["seed"], n=n)
+    u_init = torch.from_numpy(u0_host).to(dev)
+    u = torch.empty_like(u_init)
+    un = torch.empty_like(u_init)
+    xs_host = inputs.manufactured_solution(m, seed=ccfg["seed"])
+    xs = torch.from_numpy(xs_host).to(dev)
+    b = torch.empty_like(xs)
+    hc.lap7_apply(xs, b)
+    x = torch.zeros_like(b)
+    work = torch.empty(hc.cg_workspace_bytes(m, m, m), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        u.copy_(u_init)
+        x.zero_()
+        e0.record()
+        hc.heat_step(u, un, r, nsteps, mode="split")
+        e1.record()
+        st, it, rel = hc.cg_solve(b, x, tol, maxit, work=work)
+        e2.record()
+        return e0, e1, e2, st, it, rel
+
+    for w in range(args.warmup):
+        log("warmup %d/%d" % (w + 1, args.warmup))
+        step()
+    torch.cuda.synchronize()
+
+    hc.prof_enable(True)
+    records = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        records.append(step())
+        log("step %d/%d enqueued" % (k + 1, args.steps))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    int_ms, int_n, int_bytes = hc.prof_read("heat_interior")
+    bnd_ms, bnd_n, _ = hc.prof_read("heat_boundary")
+    cga_ms, cga_n, cga_b = hc.prof_read("cg_direction")
+    cgb_ms, cgb_n, cgb_b = hc.prof_read("cg_update")
+    hc.prof_enable(False)
+
+    heat_ms = [e0.elapsed_time(e1) for e0, e1, _, _, _, _ in records]
+    cg_ms = [e1.elapsed_time(e2) for _, e1, e2, _, _, _ in records]
+    statuses = {rec[3] for rec in records}
+    cg_iters = records[-1][4]
+    cg_rel = records[-1][5]
+    lups = nsteps * (n - 2) ** 3
+    heat_s_total = sum(heat_ms) / 1e3
+    glups = args.steps * lups / heat_s_total / 1e9
+    algo_step = 8.0 * (n ** 3 + (n - 2) ** 3)
+    heat_gbs = args.steps * nsteps * algo_step / heat_s_total / 1e9
+    ok_heat = bool(torch.isfinite(u).all().item()) and float(u.min()) >= 0.0
+
+    # dominant kernel: the Interior sweep
+    launch_bytes = int_bytes / max(int_n, 1)
+    launch_ms = int_ms / max(int_n, 1)
+    achieved = launch_bytes / (launch_ms / 1e3) / 1e9
+    traffic = measured_traffic(launch_bytes)
+
+    # copy-probe ceiling and the other kernel forms (outside the timed region)
+    log("copy probe and kernel-form comparison")
+    probe = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hc.copy_probe(u_init, un)
+        e1.record()
+        torch.cuda.synchronize()
+        probe.append(2 * u_init.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    copy_gbs = statistics.median(probe)
+    variants = {}
+    for mode in ("split", "fused", "plain"):
+        u.copy_(u_init)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hc.heat_step(u, un, r, 100, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        variants[mode] = round(100 * (n - 2) ** 3 / (e0.elapsed_time(e1) / 1e3) / 1e9, 2)
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        b_host = b.cpu().numpy()
+        cpu = cpu_baseline(u0_host, r, b_host, cg_iters, args.cpu_seconds)
+
+    by, zd, xcd, pf = hc.get_tiling()
+    out = {
+        "metric": METRIC,
+        "value": round(glups, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "heat 7-point FP64 512^3 r=1/6.5 x1000 steps (Interior/Boundary split) "
+                        "+ CG 7-point Laplacian FP64 256^3 to relres 1e-10",
+            "heat_grid": [n, n, n], "heat_steps": nsteps, "heat_r": r,
+            "cg_grid": [m, m, m], "cg_tol": tol, "parallelism": "single-gpu",
+            "tiling": {"by": by, "zdepth": zd, "xcd": xcd, "pf": pf},
+        },
+        "heat": {
+            "glups": round(glups, 3),
+            "algo_hbm_gbs": round(heat_gbs, 1),
+            "pct_of_hbm_peak": round(100 * heat_gbs / PEAK_HBM_GBS, 2),
+            "pct_of_copy_probe": round(100 * heat_gbs / copy_gbs, 2),
+            "ms_per_time_step": round(sum(heat_ms) / len(heat_ms) / nsteps, 5),
+            "run_ms": [round(t, 3) for t in heat_ms],
+            "variability": round((max(heat_ms) - min(heat_ms)) / statistics.median(heat_ms), 4),
+            "boundary_kernel_avg_us": round(1e3 * bnd_ms / max(bnd_n, 1), 2),
+            "kernel_forms_glups_100_steps": variants,
+            "result_ok": ok_heat,
+        },
+        "cg": {
+            "time_to_tol_s": round(statistics.median(cg_ms) / 1e3, 5),
+            "run_ms": [round(t, 3) for t in cg_ms],
+            "iterations": cg_iters,
+            "true_relres": cg_rel,
+            "status": sorted(statuses),
+            "us_per_iteration": round(1e3 * statistics.median(cg_ms) / max(cg_iters, 1), 2),
+            "algo_hbm_gbs": round(64.0 * m ** 3 * cg_iters / (statistics.median(cg_ms) / 1e3) / 1e9, 1),
+            "direction_kernel_avg_us": round(1e3 * cga_ms / max(cga_n, 1), 2),
+            "update_kernel_avg_us": round(1e3 * cgb_ms / max(cgb_n, 1), 2),
+        },
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "roofline": {
+            "kernel": "heat_interior_f64",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "algo_bytes_per_launch": launch_bytes,
+            "avg_launch_us": round(launch_ms * 1e3, 3),
+            "launches": int_n,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,7 +93,7 @@ int heat_step(double *u, double *u_new, int nx, int ny, int nz, double r,
  *  parts  number of equal k-slabs the split form treats as separate
  *         subdomains (the paper's decomposition along k, Methodology): the
  *         first and last plane of every slab are Boundary planes, the rest
- *         Interior.  1 <= parts <= min(64, (nz-2)/2); must be 1 unless
+ *         Interior.  1 <= parts <= min(32, nz-2); must be 1 unless
  *         mode == HC_HEAT_SPLIT.
  *  stream the stream the work is ordered on.  The Boundary kernels run on
  *         an internal stream of the same device that joins `stream` at
@@ -160,6 +160,20 @@ int hc_lap7_apply(const double *x, double *y, int nx, int ny, int nz,
  * aligned and non-overlapping.  Enqueued on `stream`, does not wait.
  */
 int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream);
+
+/*
+ * Tile shape of the z-marching heat kernels, for the whole process (the
+ * knob an autotuner turns; the result does not depend on it, bit for bit).
+ *  by      rows of 64 nodes per block (one wavefront each): 4, 8 or 16
+ *  zdepth  planes each block walks in z: 16, 32 or 64 (64 not with by 16)
+ *  xcd     1: deal consecutive tiles to the same XCD (shared L2), 0: not
+ *  pf      planes of loads kept in flight ahead of the computed one: 1, 2
+ *          or 3 (at most 2 with by 16)
+ * Returns HC_EINVAL for other combinations.  Default: by 4, zdepth 32,
+ * xcd 1, pf 2.
+ */
+int hc_heat_set_tiling(int by, int zdepth, int xcd, int pf);
+void hc_heat_get_tiling(int *by, int *zdepth, int *xcd, int *pf);
 
 /* Name of a status code (static string). */
 const char *hc_strerror(int code);

@@ -50,6 +50,8 @@ def _configure(lib):
     lib.oracle_cg.argtypes = [dp, dp, L, L, L, ctypes.c_double, L,
                               ctypes.POINTER(L), dp, dp]
     lib.oracle_cg.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     return lib
 
 
@@ -85,6 +87,11 @@ class using_library:
 
 def source_path() -> str:
     return _SRC
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().oracle_threads())
 
 
 def _ptr(a: np.ndarray):

@@ -17,10 +17,14 @@
  * COMPUTE_SINGLE_GPU pseudocode indexes u[k,j,i]).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define IDX(i, j, k, nx, ny) ((((long)(k)) * (ny) + (j)) * (nx) + (i))
+
+/* Number of OpenMP threads the loops below run on. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Heat equation, constant coefficient                                       */

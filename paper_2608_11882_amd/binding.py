@@ -13,7 +13,8 @@ import os
 
 __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "cg_solve",
            "cg_workspace_bytes", "lap7_apply", "copy_probe", "prof_enable",
-           "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV"]
+           "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV", "set_tiling",
+           "get_tiling"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -63,6 +64,8 @@ def load():
         "hc_last_error_message": (ctypes.c_char_p, []),
         "hc_prof_enable": (i, [i]),
         "hc_prof_read": (i, [i, dp, llp, dp]),
+        "hc_heat_set_tiling": (i, [i, i, i, i]),
+        "hc_heat_get_tiling": (None, [ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -178,6 +181,17 @@ def copy_probe(src, dst, stream=None) -> None:
         raise ValueError("size mismatch")
     _check(load().hc_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                 nbytes, _stream_handle(src, stream)))
+
+
+def set_tiling(by: int = 4, zdepth: int = 32, xcd: int = 1, pf: int = 2) -> None:
+    """Tile shape of the z-marching heat kernels (results do not depend on it)."""
+    _check(load().hc_heat_set_tiling(int(by), int(zdepth), int(xcd), int(pf)))
+
+
+def get_tiling():
+    v = [ctypes.c_int(0) for _ in range(4)]
+    load().hc_heat_get_tiling(*[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)
 
 
 def prof_enable(on: bool = True) -> None:

@@ -1,0 +1,601 @@
+// abi.cpp -- the exported C ABI of libheatcg.so (declared in heatcg.h):
+// argument validation, per-device streams and events, the time-step loop
+// with its Interior/Boundary fork-join, the CG driver and kernel timing.
+
+#include "../../include/heatcg.h"
+#include "hc_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace {
+
+using hc::KernelKind;
+
+thread_local std::string g_msg;
+thread_local int g_cg_iters = 0;
+thread_local double g_cg_relres = 0.0;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_msg = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(HC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HC_TRY(call, what)                         \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ---- tile shape of the heat kernels (settable for tuning) -------------------
+std::mutex g_tiling_mu;
+hc::HeatTiling g_tiling = {4, 32, 1, 2};
+
+hc::HeatTiling current_tiling() {
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    return g_tiling;
+}
+
+// ---- per-device state -------------------------------------------------------
+struct DevState {
+    bool ready = false;
+    hipStream_t aux = nullptr;   // the Boundary kernels' stream
+    hipEvent_t ev_main = nullptr, ev_aux = nullptr;
+    void *cg_work = nullptr;
+    size_t cg_work_size = 0;
+    hc::CGScalars *host_sc = nullptr;  // pinned
+};
+
+constexpr int kMaxDev = 64;
+std::mutex g_dev_mu;
+DevState g_dev[kMaxDev];
+
+int device_state(DevState **out) {
+    int dev = 0;
+    HC_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDev) return fail(HC_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DevState &d = g_dev[dev];
+    if (!d.ready) {
+        HC_TRY(hipStreamCreateWithFlags(&d.aux, hipStreamNonBlocking), "hipStreamCreate");
+        HC_TRY(hipEventCreateWithFlags(&d.ev_main, hipEventDisableTiming), "hipEventCreate");
+        HC_TRY(hipEventCreateWithFlags(&d.ev_aux, hipEventDisableTiming), "hipEventCreate");
+        void *h = nullptr;
+        HC_TRY(hipHostMalloc(&h, sizeof(hc::CGScalars), hipHostMallocDefault), "hipHostMalloc");
+        d.host_sc = static_cast<hc::CGScalars *>(h);
+        d.ready = true;
+    }
+    *out = &d;
+    return HC_OK;
+}
+
+// ---- kernel timing -------------------------------------------------------------
+struct Pending {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+double g_prof_ms[hc::K_COUNT];
+long long g_prof_n[hc::K_COUNT];
+double g_prof_bytes[hc::K_COUNT];
+
+hipEvent_t pool_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with timing events while profiling is enabled.
+class Timed {
+  public:
+    Timed(KernelKind kind, hipStream_t s, double bytes) : kind_(kind), s_(s), bytes_(bytes) {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (!g_prof_on) return;
+        a_ = pool_event();
+        b_ = pool_event();
+        if (a_ && b_ && hipEventRecord(a_, s_) == hipSuccess) on_ = true;
+    }
+    void done() {
+        if (!on_) return;
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (hipEventRecord(b_, s_) == hipSuccess) g_pending.push_back({(int)kind_, a_, b_, bytes_});
+        on_ = false;
+    }
+
+  private:
+    KernelKind kind_;
+    hipStream_t s_;
+    double bytes_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+    bool on_ = false;
+};
+
+// ---- validation helpers ----------------------------------------------------------
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+// The pointer must be device memory (or managed memory) of the current
+// device whose allocation holds `bytes` bytes from it.  Anything the runtime
+// cannot vouch for is rejected, so no kernel is ever launched on a buffer
+// that could make it fault.
+int check_device_buffer(const void *p, size_t bytes, const char *name) {
+    int dev = 0;
+    HC_TRY(hipGetDevice(&dev), "hipGetDevice");
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HC_EINVAL, "%s is not a device pointer (%s)", name, hipGetErrorString(e));
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(HC_EINVAL, "%s is not device memory (memory type %d)", name, (int)attr.type);
+    if (attr.type == hipMemoryTypeDevice && attr.device != dev)
+        return fail(HC_EINVAL, "%s lives on device %d, current device is %d", name, attr.device, dev);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, const_cast<void *>(p));
+    if (e != hipSuccess || base == nullptr) {
+        (void)hipGetLastError();
+        return fail(HC_EINVAL, "%s: the size of its allocation is unknown", name);
+    }
+    const uintptr_t end = reinterpret_cast<uintptr_t>(base) + size;
+    if (reinterpret_cast<uintptr_t>(p) + bytes > end)
+        return fail(HC_EINVAL, "%s: its allocation holds %zu bytes from the pointer, %zu needed",
+                    name, (size_t)(end - reinterpret_cast<uintptr_t>(p)), bytes);
+    return HC_OK;
+}
+
+int check_dims(int nx, int ny, int nz, int min_edge, size_t elem, size_t *bytes) {
+    if (nx < min_edge || ny < min_edge || nz < min_edge)
+        return fail(HC_EINVAL, "edges (%d, %d, %d) must each be >= %d", nx, ny, nz, min_edge);
+    const double n = (double)nx * ny * nz;
+    if (n * elem > 9.0e15) return fail(HC_EINVAL, "array of %.3g nodes is too large", n);
+    *bytes = (size_t)nx * ny * nz * elem;
+    return HC_OK;
+}
+
+// ---- heat: k-range tables ------------------------------------------------------
+void push_range(hc::ZTable &t, int kb, int ke, int depth) {
+    if (ke < kb) return;
+    const int i = t.n++;
+    t.kb[i] = kb;
+    t.ke[i] = ke;
+    t.depth[i] = depth;
+    t.first[i + 1] = t.first[i] + (ke - kb + depth) / depth;
+}
+
+hc::ZTable empty_table() {
+    hc::ZTable t;
+    std::memset(&t, 0, sizeof t);
+    return t;
+}
+
+// Slab s of `parts` covers the updated planes [a_s, b_s] (k-decomposition).
+void slab(int nz, int parts, int s, int *a, int *b) {
+    const long long m = nz - 2;
+    *a = 1 + (int)((s * m) / parts);
+    *b = (int)(((s + 1) * m) / parts);
+}
+
+// Bytes a z-marching launch over `t` must move: every stored node of the
+// planes it reads (kb-1 .. ke+1 of each range, counted once) plus every
+// node it writes.
+double tile_algo_bytes(const hc::ZTable &t, int nx, int ny, int nz, size_t elem) {
+    std::vector<char> rd(nz, 0);
+    long long written = 0;
+    for (int q = 0; q < t.n; ++q) {
+        for (int k = t.kb[q] - 1; k <= t.ke[q] + 1; ++k) rd[k] = 1;
+        written += t.ke[q] - t.kb[q] + 1;
+    }
+    long long planes = 0;
+    for (char c : rd) planes += c;
+    return (double)elem * ((double)planes * nx * ny + (double)written * (nx - 2) * (ny - 2));
+}
+
+int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps, int mode,
+             int parts, hipStream_t s) {
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    const hc::HeatTiling til = current_tiling();
+    const double plain_bytes = 8.0 * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
+
+    hc::ZTable tin = empty_table(), tbd = empty_table();
+    if (mode == HC_HEAT_SPLIT) {
+        for (int q = 0; q < parts; ++q) {
+            int a, b;
+            slab(nz, parts, q, &a, &b);
+            push_range(tin, a + 1, b - 1, til.zdepth);
+        }
+        for (int q = 0; q < parts; ++q) {
+            int a, b;
+            slab(nz, parts, q, &a, &b);
+            push_range(tbd, a, a, 1);
+            if (b != a) push_range(tbd, b, b, 1);
+        }
+    } else if (mode == HC_HEAT_FUSED) {
+        push_range(tin, 1, nz - 2, til.zdepth);
+    }
+    const long long nb_in = hc::heat_tile_blocks(nx, ny, til.by, tin);
+    const long long nb_bd = hc::heat_tile_blocks(nx, ny, til.by, tbd);
+    if (nb_in > 2147483647LL || nb_bd > 2147483647LL)
+        return fail(HC_EINVAL, "grid too large for this tile shape");
+    const double bytes_in = tile_algo_bytes(tin, nx, ny, nz, 8);
+    const double bytes_bd = tile_algo_bytes(tbd, nx, ny, nz, 8);
+
+    HC_TRY(hc::launch_copy_faces_f64(u, un, nx, ny, nz, s), "copy_faces launch");
+    const bool split = (mode == HC_HEAT_SPLIT) && tbd.n > 0;
+    if (split) {
+        HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
+        HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
+    }
+    double *a = u, *b = un;
+    for (int st = 0; st < steps; ++st) {
+        if (mode == HC_HEAT_PLAIN) {
+            Timed tm(hc::K_HEAT_PLAIN, s, plain_bytes);
+            HC_TRY(hc::launch_heat_plain_f64(a, b, nx, ny, nz, r, s), "heat_plain launch");
+            tm.done();
+        } else if (mode == HC_HEAT_FUSED) {
+            Timed tm(hc::K_HEAT_FUSED, s, bytes_in);
+            HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_FUSED, a, b, nx, ny, nz, r, tin, til, s),
+                   "heat_fused launch");
+            tm.done();
+        } else {
+            if (tin.n > 0) {
+                Timed tm(hc::K_HEAT_INTERIOR, s, bytes_in);
+                HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_INTERIOR, a, b, nx, ny, nz, r, tin, til, s),
+                       "heat_interior launch");
+                tm.done();
+            }
+            {
+                Timed tm(hc::K_HEAT_BOUNDARY, d->aux, bytes_bd);
+                HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_BOUNDARY, a, b, nx, ny, nz, r, tbd, til,
+                                                d->aux),
+                       "heat_boundary launch");
+                tm.done();
+            }
+            // join: the next step needs both halves of this one, in both streams
+            HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
+            HC_TRY(hipEventRecord(d->ev_aux, d->aux), "hipEventRecord");
+            HC_TRY(hipStreamWaitEvent(s, d->ev_aux, 0), "hipStreamWaitEvent");
+            HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
+        }
+        std::swap(a, b);
+    }
+    if (a != u)
+        HC_TRY(hipMemcpyAsync(u, a, (size_t)nx * ny * nz * sizeof(double), hipMemcpyDeviceToDevice, s),
+               "hipMemcpyAsync");
+    return HC_OK;
+}
+
+int validate_heat(const void *u, const void *un, int nx, int ny, int nz, double r, int steps,
+                  int dtype, int mode, int parts, size_t *bytes) {
+    if (!u || !un) return fail(HC_EINVAL, "u and u_new must be non-NULL");
+    if (dtype != HC_F64) return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    int rc = check_dims(nx, ny, nz, 3, 8, bytes);
+    if (rc) return rc;
+    if (!std::isfinite(r) || r < 0.0 || r > 1.0 / 6.0)
+        return fail(HC_EUNSTABLE, "r = %g is outside [0, 1/6]", r);
+    if (steps < 0) return fail(HC_EINVAL, "steps = %d < 0", steps);
+    if (mode != HC_HEAT_SPLIT && mode != HC_HEAT_FUSED && mode != HC_HEAT_PLAIN)
+        return fail(HC_EINVAL, "mode %d unknown", mode);
+    const int max_parts = std::min(32, nz - 2);
+    if (parts < 1 || parts > max_parts)
+        return fail(HC_EINVAL, "parts = %d outside [1, %d]", parts, max_parts);
+    if (parts != 1 && mode != HC_HEAT_SPLIT) return fail(HC_EINVAL, "parts > 1 needs the split mode");
+    if (mode == HC_HEAT_PLAIN && (nz - 2 > 65535 || ny - 2 > 4 * 65535))
+        return fail(HC_EINVAL, "plain mode supports at most 65537 planes");
+    if (overlaps(u, *bytes, un, *bytes)) return fail(HC_EALIAS, "u and u_new overlap");
+    return HC_OK;
+}
+
+int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int maxit, void *work,
+           hipStream_t s, int *iters_out, double *relres_out) {
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    const hc::CGWork w = hc::cg_work_carve(work, nx, ny, nz);
+    hc::CGScalars *h = d->host_sc;
+    const double n = (double)nx * ny * nz;
+
+    auto read_scalars = [&]() -> int {
+        HC_TRY(hipMemcpyAsync(h, w.sc, sizeof(hc::CGScalars), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        HC_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return HC_OK;
+    };
+    auto residual = [&](int store_r) -> int {
+        Timed tm(hc::K_CG_RESIDUAL, s, (store_r ? 24.0 : 16.0) * n);
+        HC_TRY(hc::launch_cg_residual(b, x, w, nx, ny, nz, store_r, s), "cg_residual launch");
+        tm.done();
+        return HC_OK;
+    };
+
+    HC_TRY(hc::launch_cg_init(w, tol, s), "cg_init launch");
+    if ((rc = residual(1))) return rc;
+    if ((rc = read_scalars())) return rc;
+    if (h->bnorm2 == 0.0) {
+        HC_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s), "hipMemsetAsync");
+        HC_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        *iters_out = 0;
+        *relres_out = 0.0;
+        return HC_OK;
+    }
+
+    const int kBatch = 16;
+    int cur = 0, first = 1, restarts = 0;
+    bool true_done = false;
+    for (;;) {
+        if (h->state < 0) break;
+        if (h->state == 1) {
+            if ((rc = residual(0))) return rc;
+            if ((rc = read_scalars())) return rc;
+            true_done = true;
+            if (std::sqrt(h->rtrue2) <= h->thresh || h->iter >= maxit || restarts >= 3) break;
+            // residual gap: restart from the current x
+            ++restarts;
+            true_done = false;
+            first = 1;
+            if ((rc = residual(1))) return rc;
+            if ((rc = read_scalars())) return rc;
+            continue;
+        }
+        if (h->iter >= maxit) break;
+        const int batch = std::min(kBatch, maxit - h->iter);
+        for (int q = 0; q < batch; ++q) {
+            {
+                Timed tm(hc::K_CG_DIRECTION, s, (first ? 16.0 : 24.0) * n);
+                HC_TRY(hc::launch_cg_direction(w, cur, first, nx, ny, nz, s), "cg_direction launch");
+                tm.done();
+            }
+            {
+                Timed tm(hc::K_CG_UPDATE, s, 40.0 * n);
+                HC_TRY(hc::launch_cg_update(x, w, cur, nx, ny, nz, s), "cg_update launch");
+                tm.done();
+            }
+            cur ^= 1;
+            first = 0;
+        }
+        if ((rc = read_scalars())) return rc;
+    }
+    if (!true_done) {
+        if ((rc = residual(0))) return rc;
+        if ((rc = read_scalars())) return rc;
+    }
+    *iters_out = h->iter;
+    *relres_out = std::sqrt(h->rtrue2) / std::sqrt(h->bnorm2);
+    if (h->state == -6) return fail(HC_EBREAKDOWN, "p.Ap = %g <= 0 at iteration %d", h->pap, h->iter);
+    if (h->state == -7) return fail(HC_ENONFINITE, "non-finite scalar at iteration %d", h->iter);
+    if (h->state == 1 && std::sqrt(h->rtrue2) <= h->thresh) return HC_OK;
+    return HC_ENOTCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hc_strerror(int code) {
+    switch (code) {
+        case HC_OK: return "HC_OK";
+        case HC_ENOTCONV: return "HC_ENOTCONV";
+        case HC_EINVAL: return "HC_EINVAL";
+        case HC_EUNSTABLE: return "HC_EUNSTABLE";
+        case HC_EALIAS: return "HC_EALIAS";
+        case HC_ENOMEM: return "HC_ENOMEM";
+        case HC_EHIP: return "HC_EHIP";
+        case HC_EBREAKDOWN: return "HC_EBREAKDOWN";
+        case HC_ENONFINITE: return "HC_ENONFINITE";
+        default: return "HC_UNKNOWN";
+    }
+}
+
+const char *hc_last_error_message(void) { return g_msg.c_str(); }
+
+int heat_step_ex(void *u, void *u_new, int nx, int ny, int nz, double r, int steps, int dtype,
+                 int mode, int parts, hc_stream_t stream) {
+    g_msg.clear();
+    size_t bytes = 0;
+    int rc = validate_heat(u, u_new, nx, ny, nz, r, steps, dtype, mode, parts, &bytes);
+    if (rc) return rc;
+    if (steps == 0) return HC_OK;
+    if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
+    if ((rc = check_device_buffer(u_new, bytes, "u_new"))) return rc;
+    return heat_f64(static_cast<double *>(u), static_cast<double *>(u_new), nx, ny, nz, r, steps,
+                    mode, parts, reinterpret_cast<hipStream_t>(stream));
+}
+
+int heat_step(double *u, double *u_new, int nx, int ny, int nz, double r, int steps) {
+    int rc = heat_step_ex(u, u_new, nx, ny, nz, r, steps, HC_F64, HC_HEAT_SPLIT, 1, nullptr);
+    if (rc != HC_OK || steps == 0) return rc;
+    HC_TRY(hipStreamSynchronize(nullptr), "heat_step (kernel execution)");
+    return HC_OK;
+}
+
+size_t cg_workspace_bytes(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    if ((double)nx * ny * nz * 8.0 > 9.0e15) return 0;
+    return hc::cg_work_bytes(nx, ny, nz);
+}
+
+int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol, int maxit,
+                void *work, size_t work_bytes, hc_stream_t stream, int *iters,
+                double *true_relres) {
+    g_msg.clear();
+    g_cg_iters = 0;
+    g_cg_relres = 0.0;
+    if (!b || !x) return fail(HC_EINVAL, "b and x must be non-NULL");
+    size_t bytes = 0;
+    int rc = check_dims(nx, ny, nz, 1, 8, &bytes);
+    if (rc) return rc;
+    if (!std::isfinite(tol) || tol <= 0.0) return fail(HC_EINVAL, "tol = %g must be > 0", tol);
+    if (maxit < 0) return fail(HC_EINVAL, "maxit = %d < 0", maxit);
+    if (overlaps(b, bytes, x, bytes)) return fail(HC_EALIAS, "b and x overlap");
+    const size_t need = hc::cg_work_bytes(nx, ny, nz);
+    if (hc::cg_blocks(nx, ny, nz) > 2147483647LL) return fail(HC_EINVAL, "grid too large");
+    if (work && work_bytes < need)
+        return fail(HC_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
+    if ((rc = check_device_buffer(b, bytes, "b"))) return rc;
+    if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
+    if (work) {
+        if ((rc = check_device_buffer(work, need, "work"))) return rc;
+        if (overlaps(work, need, b, bytes) || overlaps(work, need, x, bytes))
+            return fail(HC_EALIAS, "workspace overlaps b or x");
+    } else {
+        DevState *d = nullptr;
+        if ((rc = device_state(&d))) return rc;
+        std::lock_guard<std::mutex> g(g_dev_mu);
+        if (d->cg_work_size < need) {
+            if (d->cg_work) {
+                HC_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+                HC_TRY(hipFree(d->cg_work), "hipFree");
+                d->cg_work = nullptr;
+                d->cg_work_size = 0;
+            }
+            if (hipMalloc(&d->cg_work, need) != hipSuccess) {
+                (void)hipGetLastError();
+                d->cg_work = nullptr;
+                return fail(HC_ENOMEM, "CG workspace of %zu bytes", need);
+            }
+            d->cg_work_size = need;
+        }
+        work = d->cg_work;
+    }
+    int it = 0;
+    double rel = 0.0;
+    rc = cg_run(b, x, nx, ny, nz, tol, maxit, work, reinterpret_cast<hipStream_t>(stream), &it, &rel);
+    g_cg_iters = it;
+    g_cg_relres = rel;
+    if (iters) *iters = it;
+    if (true_relres) *true_relres = rel;
+    return rc;
+}
+
+int cg_solve(const double *b, double *x, int n, double tol, int maxit) {
+    return cg_solve_ex(b, x, n, n, n, tol, maxit, nullptr, 0, nullptr, nullptr, nullptr);
+}
+
+void hc_cg_last_info(int *iters, double *true_relres) {
+    if (iters) *iters = g_cg_iters;
+    if (true_relres) *true_relres = g_cg_relres;
+}
+
+int hc_lap7_apply(const double *x, double *y, int nx, int ny, int nz, hc_stream_t stream) {
+    g_msg.clear();
+    if (!x || !y) return fail(HC_EINVAL, "x and y must be non-NULL");
+    size_t bytes = 0;
+    int rc = check_dims(nx, ny, nz, 1, 8, &bytes);
+    if (rc) return rc;
+    if (overlaps(x, bytes, y, bytes)) return fail(HC_EALIAS, "x and y overlap");
+    if (hc::cg_blocks(nx, ny, nz) > 2147483647LL) return fail(HC_EINVAL, "grid too large");
+    if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
+    if ((rc = check_device_buffer(y, bytes, "y"))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Timed tm(hc::K_LAP7, s, 16.0 * nx * ny * nz);
+    HC_TRY(hc::launch_lap7_f64(x, y, nx, ny, nz, s), "lap7 launch");
+    tm.done();
+    return HC_OK;
+}
+
+int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream) {
+    g_msg.clear();
+    if (!src || !dst) return fail(HC_EINVAL, "src and dst must be non-NULL");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(HC_EINVAL, "bytes and both pointers must be multiples of 16");
+    if (overlaps(src, bytes, dst, bytes)) return fail(HC_EALIAS, "src and dst overlap");
+    if (bytes == 0) return HC_OK;
+    int rc;
+    if ((rc = check_device_buffer(src, bytes, "src"))) return rc;
+    if ((rc = check_device_buffer(dst, bytes, "dst"))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Timed tm(hc::K_COPY, s, 2.0 * (double)bytes);
+    HC_TRY(hc::launch_copy_probe(src, dst, bytes, s), "copy_probe launch");
+    tm.done();
+    return HC_OK;
+}
+
+int hc_heat_set_tiling(int by, int zdepth, int xcd, int pf) {
+    g_msg.clear();
+    const bool ok_shape = ((by == 4 || by == 8) && pf >= 1 && pf <= 3 &&
+                           (zdepth == 16 || zdepth == 32 || zdepth == 64)) ||
+                          (by == 16 && pf >= 1 && pf <= 2 && (zdepth == 16 || zdepth == 32));
+    if (!ok_shape)
+        return fail(HC_EINVAL, "tile shape (by %d, zdepth %d, pf %d) is not built", by, zdepth, pf);
+    if (xcd != 0 && xcd != 1) return fail(HC_EINVAL, "xcd must be 0 or 1");
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_tiling = {by, zdepth, xcd, pf};
+    return HC_OK;
+}
+
+void hc_heat_get_tiling(int *by, int *zdepth, int *xcd, int *pf) {
+    const hc::HeatTiling t = current_tiling();
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (xcd) *xcd = t.xcd;
+    if (pf) *pf = t.pf;
+}
+
+int hc_prof_enable(int on) {
+    g_msg.clear();
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (const Pending &p : g_pending) {
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    g_pending.clear();
+    for (int k = 0; k < hc::K_COUNT; ++k) {
+        g_prof_ms[k] = 0.0;
+        g_prof_n[k] = 0;
+        g_prof_bytes[k] = 0.0;
+    }
+    g_prof_on = (on != 0);
+    return HC_OK;
+}
+
+int hc_prof_read(int kind, double *total_ms, long long *launches, double *algo_bytes) {
+    g_msg.clear();
+    if (kind < 0 || kind >= hc::K_COUNT) return fail(HC_EINVAL, "kernel kind %d unknown", kind);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (const Pending &p : g_pending) {
+        HC_TRY(hipEventSynchronize(p.b), "hipEventSynchronize");
+        float ms = 0.f;
+        HC_TRY(hipEventElapsedTime(&ms, p.a, p.b), "hipEventElapsedTime");
+        g_prof_ms[p.kind] += ms;
+        g_prof_n[p.kind] += 1;
+        g_prof_bytes[p.kind] += p.bytes;
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    g_pending.clear();
+    if (total_ms) *total_ms = g_prof_ms[kind];
+    if (launches) *launches = g_prof_n[kind];
+    if (algo_bytes) *algo_bytes = g_prof_bytes[kind];
+    return HC_OK;
+}
+
+}  // extern "C"

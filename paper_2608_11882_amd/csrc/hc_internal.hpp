@@ -1,0 +1,109 @@
+// Internal declarations shared by the kernel translation units and the C ABI
+// layer of libheatcg.so.  Nothing here is exported.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hc {
+
+// Width of a tile along x: one wavefront of 64 lanes, one node per lane, so
+// every plane row of a tile is one 512-byte (FP64) coalesced access.
+constexpr int kTileX = 64;
+
+// Up to this many k-ranges can be swept by one launch (the slab count of
+// the Interior/Boundary split is bounded by it).
+constexpr int kMaxRanges = 64;
+
+// Work list of a z-marching launch.  Range r covers the planes
+// [kb[r], ke[r]] (inclusive), cut into z-blocks of depth[r] planes; the
+// z-blocks of range r are numbered first[r] .. first[r+1]-1.
+struct ZTable {
+    int n;
+    int kb[kMaxRanges];
+    int ke[kMaxRanges];
+    int depth[kMaxRanges];
+    int first[kMaxRanges + 1];
+};
+
+// Launch shape of the z-marching heat kernels.
+struct HeatTiling {
+    int by;       // waves (rows of 64 nodes) per block: 4, 8 or 16
+    int zdepth;   // planes per z-block of the Interior / fused kernel
+    int xcd;      // 1: map consecutive tiles to the same XCD
+    int pf;       // planes of loads kept in flight: 1 or 2
+};
+
+// Kernel kinds the launches are timed under (same values as hc_kernel_kind).
+enum KernelKind {
+    K_HEAT_INTERIOR = 0,
+    K_HEAT_BOUNDARY = 1,
+    K_HEAT_FUSED = 2,
+    K_HEAT_PLAIN = 3,
+    K_CG_DIRECTION = 4,
+    K_CG_UPDATE = 5,
+    K_CG_RESIDUAL = 6,
+    K_LAP7 = 7,
+    K_COPY = 8,
+    K_COUNT = 9
+};
+
+// ---- heat (heat_kernels.hip) ------------------------------------------------
+int ztable_blocks(const ZTable &zt);
+// Grid size of a z-marching launch over table zt (tiles of 64 x by nodes).
+long long heat_tile_blocks(int nx, int ny, int by, const ZTable &zt);
+hipError_t launch_heat_tile_f64(KernelKind kind, const double *u, double *un,
+                                int nx, int ny, int nz, double r,
+                                const ZTable &zt, const HeatTiling &t,
+                                hipStream_t s);
+hipError_t launch_heat_plain_f64(const double *u, double *un, int nx, int ny,
+                                 int nz, double r, hipStream_t s);
+hipError_t launch_copy_faces_f64(const double *u, double *un, int nx, int ny,
+                                 int nz, hipStream_t s);
+
+// ---- CG (cg_kernels.hip) ------------------------------------------------------
+// Device-resident scalars of one CG solve.  Written by the last block of
+// each reduction kernel, read by the next kernel and (64 bytes) by the host.
+struct CGScalars {
+    double rho;       // r.r of the current residual
+    double pap;       // p.Ap of the current direction
+    double alpha;
+    double beta;
+    double bnorm2;    // b.b
+    double tol;       // relative tolerance
+    double thresh;    // tol * ||b||
+    double rtrue2;    // |b - A x|^2 of the last true-residual pass
+    int iter;         // completed iterations
+    int state;        // 0 running, 1 converged, -6 breakdown, -7 non-finite
+    unsigned ticket;  // arrival counter of the reductions (0 between kernels)
+    unsigned pad;
+};
+
+struct CGWork {
+    double *r;
+    double *p[2];
+    double *partial;   // two doubles per block
+    CGScalars *sc;
+};
+
+size_t cg_work_bytes(int nx, int ny, int nz);
+// Carve a CGWork out of `base` (at least cg_work_bytes bytes).
+CGWork cg_work_carve(void *base, int nx, int ny, int nz);
+long long cg_blocks(int nx, int ny, int nz);
+hipError_t launch_cg_init(const CGWork &w, double tol, hipStream_t s);
+hipError_t launch_cg_residual(const double *b, const double *x, const CGWork &w,
+                              int nx, int ny, int nz, int store_r, hipStream_t s);
+hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int nx,
+                               int ny, int nz, hipStream_t s);
+hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx, int ny,
+                            int nz, hipStream_t s);
+hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
+                           hipStream_t s);
+
+// ---- probes (probe.hip) ---------------------------------------------------------
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes,
+                             hipStream_t s);
+
+}  // namespace hc

@@ -1,0 +1,120 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol,
+and rejects bad arguments before touching the device (so these checks need
+no GPU; the pointers below are never dereferenced)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2608_11882_amd as hc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "heatcg.h")
+
+HC_OK, HC_EINVAL, HC_EUNSTABLE, HC_EALIAS = 0, -1, -2, -3
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "sizeof")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hc.load()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("heat_step", "heat_step_ex", "cg_solve", "cg_solve_ex", "hc_lap7_apply",
+                     "hc_copy_probe", "hc_strerror", "hc_last_error_message"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), "libheatcg.so does not export " + name
+
+
+def test_status_names(lib):
+    assert hc.strerror(0) == "HC_OK"
+    assert hc.strerror(-2) == "HC_EUNSTABLE"
+    assert hc.strerror(12345) == "HC_UNKNOWN"
+
+
+FAKE_U = ctypes.c_void_p(0x10000)
+FAKE_V = ctypes.c_void_p(0x10000 + 8 * 10 ** 6)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, FAKE_V, 10, 10, 10, 0.1, 1), HC_EINVAL),          # null pointer
+    ((FAKE_U, FAKE_V, 2, 10, 10, 0.1, 1), HC_EINVAL),         # edge < 3
+    ((FAKE_U, FAKE_V, 10, 10, 10, 0.2, 1), HC_EUNSTABLE),     # r > 1/6
+    ((FAKE_U, FAKE_V, 10, 10, 10, -0.01, 1), HC_EUNSTABLE),   # r < 0
+    ((FAKE_U, FAKE_V, 10, 10, 10, float("nan"), 1), HC_EUNSTABLE),
+    ((FAKE_U, FAKE_V, 10, 10, 10, float("inf"), 1), HC_EUNSTABLE),
+    ((FAKE_U, FAKE_V, 10, 10, 10, 0.1, -1), HC_EINVAL),       # negative steps
+    ((FAKE_U, FAKE_U, 10, 10, 10, 0.1, 1), HC_EALIAS),        # same buffer
+    ((FAKE_U, ctypes.c_void_p(0x10000 + 8 * 999), 10, 10, 10, 0.1, 1), HC_EALIAS),  # overlap
+    ((FAKE_U, FAKE_V, 10, 10, 10, 0.1, 0), HC_OK),            # steps = 0: no-op
+])
+def test_heat_step_validation_happens_before_device_work(lib, args, code):
+    assert lib.heat_step(*args) == code
+    if code != HC_OK:
+        assert lib.hc_last_error_message().decode() != ""
+
+
+def test_heat_step_ex_rejects_bad_mode_dtype_and_parts(lib):
+    f = lib.heat_step_ex
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 1, 7, 0, 1, None) == HC_EINVAL      # dtype
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 1, 0, 9, 1, None) == HC_EINVAL      # mode
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 1, 0, 0, 0, None) == HC_EINVAL      # parts 0
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 1, 0, 0, 9, None) == HC_EINVAL      # > nz-2
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 1, 0, 1, 2, None) == HC_EINVAL      # parts w/o split
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 1.0 / 6.0, 0, 0, 0, 8, None) == HC_OK    # r = 1/6 allowed
+
+
+def test_cg_validation(lib):
+    b, x = FAKE_U, FAKE_V
+    assert lib.cg_solve(None, x, 8, 1e-10, 10) == HC_EINVAL
+    assert lib.cg_solve(b, x, 0, 1e-10, 10) == HC_EINVAL
+    assert lib.cg_solve(b, x, 8, 0.0, 10) == HC_EINVAL
+    assert lib.cg_solve(b, x, 8, float("nan"), 10) == HC_EINVAL
+    assert lib.cg_solve(b, x, 8, 1e-10, -1) == HC_EINVAL
+    assert lib.cg_solve(b, b, 8, 1e-10, 10) == HC_EALIAS
+    small = ctypes.c_size_t(16)
+    assert lib.cg_solve_ex(b, x, 8, 8, 8, 1e-10, 10, FAKE_U, small, None, None, None) == HC_EINVAL
+
+
+def test_workspace_size_formula(lib):
+    n = 64
+    need = lib.cg_workspace_bytes(n, n, n)
+    assert need >= 3 * 8 * n ** 3
+    assert lib.cg_workspace_bytes(0, 4, 4) == 0
+
+
+def test_copy_probe_and_lap7_validation(lib):
+    assert lib.hc_copy_probe(FAKE_U, FAKE_V, 17, None) == HC_EINVAL
+    assert lib.hc_copy_probe(FAKE_U, FAKE_U, 16, None) == HC_EALIAS
+    assert lib.hc_copy_probe(FAKE_U, FAKE_V, 0, None) == HC_OK
+    assert lib.hc_lap7_apply(FAKE_U, FAKE_U, 4, 4, 4, None) == HC_EALIAS
+    assert lib.hc_lap7_apply(FAKE_U, FAKE_V, 0, 4, 4, None) == HC_EINVAL
+
+
+def test_tiling_knob(lib):
+    assert lib.hc_heat_set_tiling(5, 32, 1, 2) == HC_EINVAL
+    assert lib.hc_heat_set_tiling(4, 48, 1, 2) == HC_EINVAL
+    assert lib.hc_heat_set_tiling(16, 64, 1, 2) == HC_EINVAL
+    assert lib.hc_heat_set_tiling(8, 16, 0, 3) == HC_OK
+    assert hc.get_tiling() == (8, 16, 0, 3)
+    assert lib.hc_heat_set_tiling(4, 32, 1, 2) == HC_OK
+
+
+def test_binding_raises_without_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        hc.heat_step(torch.zeros(4, 4, 4, dtype=torch.float64),
+                     torch.zeros(4, 4, 4, dtype=torch.float64), 0.1, 1)
