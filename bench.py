@@ -212,7 +212,7 @@ def main():
         b_host = b.cpu().numpy()
         cpu = cpu_baseline(u0_host, r, b_host, cg_iters, args.cpu_seconds)
 
-    by, zd, xcd, pf = hc.get_tiling()
+    tiling = hc.get_tiling()
     out = {
         "metric": METRIC,
         "value": round(glups, 3),
@@ -231,7 +231,7 @@ def main():
                         "+ CG 7-point Laplacian FP64 256^3 to relres 1e-10",
             "heat_grid": [n, n, n], "heat_steps": nsteps, "heat_r": r,
             "cg_grid": [m, m, m], "cg_tol": tol, "parallelism": "single-gpu",
-            "tiling": {"by": by, "zdepth": zd, "xcd": xcd, "pf": pf},
+            "tiling": tiling,
         },
         "heat": {
             "glups": round(glups, 3),

@@ -68,8 +68,9 @@ enum hc_heat_mode {
  *          return.  Its outermost layer holds the Dirichlet data and is
  *          never written (the paper uses zero data, Eq. 5).
  *  u_new   [scratch] nx*ny*nz FP64, device, must not overlap u.  On entry
- *          its outermost layer is overwritten with u's; on return it holds
- *          u^(steps-1) when steps >= 1.
+ *          its outermost layer is overwritten with u's.  On return it holds
+ *          u^(steps-1) when steps is even and >= 2, and u^steps when steps
+ *          is odd (the last sweep lands in u_new and is copied to u).
  *  nx,ny,nz  stored edge lengths including the Dirichlet layer, each >= 3;
  *          (nx-2)(ny-2)(nz-2) nodes are updated.
  *  r       finite, 0 <= r <= 1/6 (stability and the discrete maximum
@@ -163,17 +164,23 @@ int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream);
 
 /*
  * Tile shape of the z-marching heat kernels, for the whole process (the
- * knob an autotuner turns; the result does not depend on it, bit for bit).
- *  by      rows of 64 nodes per block (one wavefront each): 4, 8 or 16
- *  zdepth  planes each block walks in z: 16, 32 or 64 (64 not with by 16)
- *  xcd     1: deal consecutive tiles to the same XCD (shared L2), 0: not
- *  pf      planes of loads kept in flight ahead of the computed one: 1, 2
- *          or 3 (at most 2 with by 16)
- * Returns HC_EINVAL for other combinations.  Default: by 4, zdepth 32,
- * xcd 1, pf 2.
+ * knob an autotuner turns; results do not depend on it, bit for bit).  A
+ * block covers 64*vec*wx nodes along x by `by` rows and walks `zdepth`
+ * planes along z.
+ *  vec     nodes per lane along x: 1, or 2 (16-byte accesses; used only when
+ *          nx is even and both arrays are 16-byte aligned, else a one-node
+ *          shape of the same depth is used)
+ *  wx      wavefronts per tile row
+ *  by      rows per tile
+ *  zdepth  planes per z-block
+ *  pf      planes of loads kept in flight ahead of the computed one (1, 2)
+ *  xcd     1: deal consecutive tiles to the same XCD, 0: hardware order
+ * The shapes built are listed in heat_kernels.hip (HC_HEAT_SHAPES); others
+ * return HC_EINVAL.  Default: vec 2, wx 2, by 8, zdepth 16, pf 2, xcd 0.
  */
-int hc_heat_set_tiling(int by, int zdepth, int xcd, int pf);
-void hc_heat_get_tiling(int *by, int *zdepth, int *xcd, int *pf);
+int hc_heat_set_tiling(int vec, int wx, int by, int zdepth, int pf, int xcd);
+void hc_heat_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *pf,
+                        int *xcd);
 
 /* Name of a status code (static string). */
 const char *hc_strerror(int code);

@@ -14,7 +14,7 @@ import os
 __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "cg_solve",
            "cg_workspace_bytes", "lap7_apply", "copy_probe", "prof_enable",
            "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV", "set_tiling",
-           "get_tiling"]
+           "get_tiling", "DEFAULT_TILING"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -64,8 +64,8 @@ def load():
         "hc_last_error_message": (ctypes.c_char_p, []),
         "hc_prof_enable": (i, [i]),
         "hc_prof_read": (i, [i, dp, llp, dp]),
-        "hc_heat_set_tiling": (i, [i, i, i, i]),
-        "hc_heat_get_tiling": (None, [ip, ip, ip, ip]),
+        "hc_heat_set_tiling": (i, [i, i, i, i, i, i]),
+        "hc_heat_get_tiling": (None, [ip, ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -183,15 +183,19 @@ def copy_probe(src, dst, stream=None) -> None:
                                 nbytes, _stream_handle(src, stream)))
 
 
-def set_tiling(by: int = 4, zdepth: int = 32, xcd: int = 1, pf: int = 2) -> None:
+DEFAULT_TILING = dict(vec=2, wx=2, by=8, zdepth=16, pf=2, xcd=0)
+
+
+def set_tiling(vec: int = 2, wx: int = 2, by: int = 8, zdepth: int = 16, pf: int = 2,
+               xcd: int = 0) -> None:
     """Tile shape of the z-marching heat kernels (results do not depend on it)."""
-    _check(load().hc_heat_set_tiling(int(by), int(zdepth), int(xcd), int(pf)))
+    _check(load().hc_heat_set_tiling(int(vec), int(wx), int(by), int(zdepth), int(pf), int(xcd)))
 
 
-def get_tiling():
-    v = [ctypes.c_int(0) for _ in range(4)]
+def get_tiling() -> dict:
+    v = [ctypes.c_int(0) for _ in range(6)]
     load().hc_heat_get_tiling(*[ctypes.byref(x) for x in v])
-    return tuple(x.value for x in v)
+    return dict(zip(("vec", "wx", "by", "zdepth", "pf", "xcd"), (x.value for x in v)))
 
 
 def prof_enable(on: bool = True) -> None:

@@ -44,7 +44,9 @@ int hip_fail(hipError_t e, const char *what) {
 
 // ---- tile shape of the heat kernels (settable for tuning) -------------------
 std::mutex g_tiling_mu;
-hc::HeatTiling g_tiling = {4, 32, 1, 2};
+// default: 256 x 8 tiles (two nodes per lane, two wavefronts per row),
+// z-blocks of 16 planes, two planes of loads in flight, hardware block order
+hc::HeatTiling g_tiling = {2, 2, 8, 16, 2, 0};
 
 hc::HeatTiling current_tiling() {
     std::lock_guard<std::mutex> g(g_tiling_mu);
@@ -224,7 +226,11 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
     DevState *d = nullptr;
     int rc = device_state(&d);
     if (rc) return rc;
-    const hc::HeatTiling til = current_tiling();
+    hc::HeatTiling til = current_tiling();
+    // two nodes per lane need 16-byte aligned rows
+    if (til.vec == 2 && ((nx & 1) || (reinterpret_cast<uintptr_t>(u) & 15) ||
+                         (reinterpret_cast<uintptr_t>(un) & 15)))
+        til = {1, 1, 16, 16, 2, til.xcd};
     const double plain_bytes = 8.0 * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
 
     hc::ZTable tin = empty_table(), tbd = empty_table();
@@ -243,8 +249,8 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
     } else if (mode == HC_HEAT_FUSED) {
         push_range(tin, 1, nz - 2, til.zdepth);
     }
-    const long long nb_in = hc::heat_tile_blocks(nx, ny, til.by, tin);
-    const long long nb_bd = hc::heat_tile_blocks(nx, ny, til.by, tbd);
+    const long long nb_in = hc::heat_tile_blocks(nx, ny, til, tin);
+    const long long nb_bd = hc::heat_tile_blocks(nx, ny, til, tbd);
     if (nb_in > 2147483647LL || nb_bd > 2147483647LL)
         return fail(HC_EINVAL, "grid too large for this tile shape");
     const double bytes_in = tile_algo_bytes(tin, nx, ny, nz, 8);
@@ -539,25 +545,26 @@ int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream) 
     return HC_OK;
 }
 
-int hc_heat_set_tiling(int by, int zdepth, int xcd, int pf) {
+int hc_heat_set_tiling(int vec, int wx, int by, int zdepth, int pf, int xcd) {
     g_msg.clear();
-    const bool ok_shape = ((by == 4 || by == 8) && pf >= 1 && pf <= 3 &&
-                           (zdepth == 16 || zdepth == 32 || zdepth == 64)) ||
-                          (by == 16 && pf >= 1 && pf <= 2 && (zdepth == 16 || zdepth == 32));
-    if (!ok_shape)
-        return fail(HC_EINVAL, "tile shape (by %d, zdepth %d, pf %d) is not built", by, zdepth, pf);
+    const hc::HeatTiling t = {vec, wx, by, zdepth, pf, xcd};
+    if (!hc::heat_tiling_supported(t))
+        return fail(HC_EINVAL, "tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built",
+                    vec, wx, by, zdepth, pf);
     if (xcd != 0 && xcd != 1) return fail(HC_EINVAL, "xcd must be 0 or 1");
     std::lock_guard<std::mutex> g(g_tiling_mu);
-    g_tiling = {by, zdepth, xcd, pf};
+    g_tiling = t;
     return HC_OK;
 }
 
-void hc_heat_get_tiling(int *by, int *zdepth, int *xcd, int *pf) {
+void hc_heat_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *pf, int *xcd) {
     const hc::HeatTiling t = current_tiling();
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
     if (by) *by = t.by;
     if (zdepth) *zdepth = t.zdepth;
-    if (xcd) *xcd = t.xcd;
     if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
 }
 
 int hc_prof_enable(int on) {

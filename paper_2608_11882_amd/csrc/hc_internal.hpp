@@ -30,10 +30,12 @@ struct ZTable {
 
 // Launch shape of the z-marching heat kernels.
 struct HeatTiling {
-    int by;       // waves (rows of 64 nodes) per block: 4, 8 or 16
+    int vec;      // nodes per lane along x: 1 or 2 (2: 16-byte accesses)
+    int wx;       // wavefronts per tile row: tile width = 64 * vec * wx
+    int by;       // rows per tile
     int zdepth;   // planes per z-block of the Interior / fused kernel
-    int xcd;      // 1: map consecutive tiles to the same XCD
     int pf;       // planes of loads kept in flight: 1 or 2
+    int xcd;      // 1: map consecutive tiles to the same XCD
 };
 
 // Kernel kinds the launches are timed under (same values as hc_kernel_kind).
@@ -52,8 +54,10 @@ enum KernelKind {
 
 // ---- heat (heat_kernels.hip) ------------------------------------------------
 int ztable_blocks(const ZTable &zt);
-// Grid size of a z-marching launch over table zt (tiles of 64 x by nodes).
-long long heat_tile_blocks(int nx, int ny, int by, const ZTable &zt);
+// Grid size of a z-marching launch over table zt.
+long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt);
+int tile_width(const HeatTiling &t);
+bool heat_tiling_supported(const HeatTiling &t);
 hipError_t launch_heat_tile_f64(KernelKind kind, const double *u, double *un,
                                 int nx, int ny, int nz, double r,
                                 const ZTable &zt, const HeatTiling &t,

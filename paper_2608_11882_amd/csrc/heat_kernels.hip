@@ -28,8 +28,6 @@
 namespace hc {
 namespace {
 
-constexpr int kLd = kTileX + 2;  // LDS row stride (tile row plus ring)
-
 __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
     constexpr int kXcd = 8;
     const int xcd = bid % kXcd, slot = bid / kXcd;
@@ -39,11 +37,13 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 
 // Loads are never predicated: a node outside the array is read at a clamped
 // in-bounds address instead, and such values only ever reach lanes whose own
-// node is not updated.  Those lanes store their own (unchanged) value back
-// to a Dirichlet node of un -- the same bits the face copy put there -- so
-// the store is not predicated either.  With no branch around a memory
-// access every wave issues the same accesses each plane, and the compiler
-// waits only for the loads a plane needs.
+// nodes are not updated.  Those lanes store their own (unchanged) values
+// back to Dirichlet nodes of un -- the same bits the face copy put there --
+// so the store is not predicated either: a lane whose nodes lie in the array
+// stores to them, a lane past the last column or row stores to the Dirichlet
+// row ny-1.  With no branch around a memory access every wave issues the
+// same accesses each plane, and the compiler waits only for the loads a
+// plane needs.
 //
 // A z-block of exactly ZB planes takes the fast path: the march is fully
 // unrolled, so the register queue along z is renamed rather than copied
@@ -52,162 +52,219 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 // range is shifted back to a full ZB planes; the planes it shares with the
 // block before are computed twice and written twice with identical bits.
 // Ranges shorter than ZB (the Boundary planes) take the generic loop.
+//
+// Tile: WX wavefronts per row, each lane owning VEC consecutive nodes in x
+// (VEC = 2: one 16-byte access per lane, 1 KiB per wavefront row), BY rows.
 
+template <int VEC, int WX, int BY>
 struct TileGeom {
+    static constexpr int TX = 64 * VEC * WX;   // tile width in nodes
+    static constexpr int LD = TX + 2;          // LDS row stride
+    static constexpr int NT = 64 * WX * BY;    // threads per block
+    static constexpr int RROW = TX / VEC;      // threads per ring row
+    static_assert(NT >= 2 * RROW + 2 * BY, "one thread per ring element");
     int kb, ke;
     long long plane, own, ring;
-    bool own_st;
+    bool st[VEC];
     int own_slot, rslot;
+    bool rvec;  // ring element is a VEC-wide row piece (else one node)
+
+    __device__ __forceinline__ TileGeom(int nx, int ny, const ZTable &zt, int ntx,
+                                        int nty, int xcd, int zb_full) {
+        const int L = xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+        const int tx = L % ntx;
+        const int rest = L / ntx;
+        const int ty = rest % nty;
+        const int z = rest / nty;
+        int rg = 0;
+        while (rg + 1 < zt.n && z >= zt.first[rg + 1]) ++rg;
+        int k0 = zt.kb[rg] + (z - zt.first[rg]) * zt.depth[rg];
+        if (zt.depth[rg] == zb_full && zt.ke[rg] - zt.kb[rg] + 1 >= zb_full)
+            k0 = min(k0, zt.ke[rg] - zb_full + 1);  // full-depth last block
+        kb = k0;
+        ke = min(k0 + zt.depth[rg] - 1, zt.ke[rg]);
+
+        const int t = threadIdx.x;
+        const int lane = t & 63, w = t >> 6;
+        const int wy = w / WX, wx = w % WX;
+        const int i0 = tx * TX;
+        const int j0 = 1 + ty * BY;  // first updated row of the tile
+        const int ia = i0 + (wx * 64 + lane) * VEC;
+        const int j = j0 + wy;
+        plane = (long long)nx * ny;
+        if (ia >= nx)  // past the last column: Dirichlet row ny-1
+            own = (long long)(ny - 1) * nx + (nx - VEC);
+        else
+            own = (long long)min(j, ny - 1) * nx + ia;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) st[v] = (ia + v >= 1) && (ia + v <= nx - 2) && (j <= ny - 2);
+        own_slot = (wy + 1) * LD + (wx * 64 + lane) * VEC + 1;
+
+        // ring of the LDS tile: rows j0-1 and j0+BY (VEC nodes per thread,
+        // coalesced), then columns i0-1 and i0+TX (one node per thread)
+        rvec = false;
+        rslot = -1;
+        if (t < 2 * RROW) {
+            const int row = t / RROW, q = t % RROW;
+            const int rj = row == 0 ? j0 - 1 : min(j0 + BY, ny - 1);
+            ring = (long long)rj * nx + min(i0 + q * VEC, nx - VEC);
+            rslot = (row == 0 ? 0 : (BY + 1) * LD) + q * VEC + 1;
+            rvec = true;
+        } else if (t < 2 * RROW + 2 * BY) {
+            const int q = t - 2 * RROW;
+            const int row = q % BY, side = q / BY;
+            const int ri = side == 0 ? i0 - 1 : i0 + TX;
+            ring = (long long)min(j0 + row, ny - 1) * nx + max(0, min(ri, nx - 1));
+            rslot = (row + 1) * LD + (side == 0 ? 0 : TX + 1);
+        } else {
+            ring = own;
+        }
+    }
 };
 
-template <int BY>
-__device__ __forceinline__ TileGeom tile_geom(int nx, int ny, const ZTable &zt,
-                                              int ntx, int nty, int xcd,
-                                              int zb_full) {
-    TileGeom g;
-    const int L = xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int tx = L % ntx;
-    const int rest = L / ntx;
-    const int ty = rest % nty;
-    const int z = rest / nty;
-    int rg = 0;
-    while (rg + 1 < zt.n && z >= zt.first[rg + 1]) ++rg;
-    int kb = zt.kb[rg] + (z - zt.first[rg]) * zt.depth[rg];
-    if (zt.depth[rg] == zb_full && zt.ke[rg] - zt.kb[rg] + 1 >= zb_full)
-        kb = min(kb, zt.ke[rg] - zb_full + 1);  // full-depth last block
-    g.kb = kb;
-    g.ke = min(kb + zt.depth[rg] - 1, zt.ke[rg]);
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int i0 = tx * kTileX;
-    const int j0 = 1 + ty * BY;  // first updated row of the tile
-    const int i = i0 + lane;
-    const int j = j0 + w;
-    g.plane = (long long)nx * ny;
-    g.own = (long long)min(j, ny - 1) * nx + min(i, nx - 1);
-    g.own_st = (i >= 1) && (i <= nx - 2) && (j <= ny - 2);
-    g.own_slot = (w + 1) * kLd + lane + 1;
-
-    // ring of the LDS tile, one node per thread: rows j0-1 and j0+BY (64
-    // nodes each, coalesced), then columns i0-1 and i0+64 (BY nodes each)
-    constexpr int kRing = 2 * kTileX + 2 * BY;
-    const int e = threadIdx.x;
-    int ri, rj, rslot;
-    if (e < kTileX) {
-        ri = i0 + e; rj = j0 - 1; rslot = e + 1;
-    } else if (e < 2 * kTileX) {
-        ri = i0 + e - kTileX; rj = j0 + BY; rslot = (BY + 1) * kLd + (e - kTileX) + 1;
-    } else if (e < 2 * kTileX + BY) {
-        ri = i0 - 1; rj = j0 + (e - 2 * kTileX); rslot = (e - 2 * kTileX + 1) * kLd;
-    } else if (e < kRing) {
-        ri = i0 + kTileX; rj = j0 + (e - 2 * kTileX - BY);
-        rslot = (e - 2 * kTileX - BY + 1) * kLd + kTileX + 1;
+template <int VEC>
+__device__ __forceinline__ void load_vec(const double *__restrict__ p, double *o) {
+    if (VEC == 2) {
+        const f64x2 v = *reinterpret_cast<const f64x2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
     } else {
-        ri = i; rj = j; rslot = -1;
+        o[0] = *p;
     }
-    g.ring = (long long)min(rj, ny - 1) * nx + max(0, min(ri, nx - 1));
-    g.rslot = rslot;
-    return g;
 }
 
-// One plane: stage the column value and the ring in LDS, then update.
-template <int BY>
-__device__ __forceinline__ double plane_update(double *tile, const TileGeom &g,
-                                               double zm, double c, double zp,
-                                               double ringv, double r) {
-    (void)BY;
-    const double xm = tile[g.own_slot - 1];
-    const double xp = tile[g.own_slot + 1];
-    const double ym = tile[g.own_slot - kLd];
-    const double yp = tile[g.own_slot + kLd];
-    const double nsum = ((xm + xp) + (ym + yp)) + (zm + zp);
-    const double lap = nsum - 6.0 * c;
-    (void)ringv;
-    return g.own_st ? c + r * lap : c;
+template <int VEC>
+__device__ __forceinline__ void store_vec_nt(double *__restrict__ p, const double *v) {
+    if (VEC == 2) {
+        f64x2 x;
+        x.x = v[0];
+        x.y = v[1];
+        __builtin_nontemporal_store(x, reinterpret_cast<f64x2 *>(p));
+    } else {
+        __builtin_nontemporal_store(v[0], p);
+    }
 }
 
-template <int BY, int PF, int ZB>
+template <int VEC, int WX, int BY, int PF, int ZB>
 __device__ __forceinline__ void heat_tile_sweep(const double *__restrict__ u,
                                                 double *__restrict__ un, int nx,
                                                 int ny, double r,
                                                 const ZTable &zt, int ntx,
                                                 int nty, int xcd) {
-    static_assert(64 * BY >= 2 * kTileX + 2 * BY, "one thread per ring node");
-    static_assert(PF >= 1 && PF <= 3, "prefetch depth 1..3");
-    __shared__ double tile[(BY + 2) * kLd];
-    const TileGeom g = tile_geom<BY>(nx, ny, zt, ntx, nty, xcd, ZB);
+    using G = TileGeom<VEC, WX, BY>;
+    static_assert(PF >= 1 && PF <= 2, "prefetch depth 1 or 2");
+    __shared__ double tile[(BY + 2) * G::LD];
+    const G g(nx, ny, zt, ntx, nty, xcd, ZB);
     const long long plane = g.plane;
     const double *__restrict__ uo = u + g.own;
     const double *__restrict__ ur = u + g.ring;
     double *__restrict__ vo = un + g.own;
     const int kb = g.kb, ke = g.ke;
 
+    // ring value(s) of plane k
+    auto ld_ring = [&](long long kp, double *o) {
+        if (VEC == 2 && g.rvec) {
+            load_vec<2>(ur + kp, o);
+        } else {
+            o[0] = ur[kp];
+            o[1] = 0.0;
+        }
+    };
+    auto put = [&](const double *c, const double *gv) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) tile[g.own_slot + v] = c[v];
+        if (g.rslot >= 0) {
+            tile[g.rslot] = gv[0];
+            if (VEC == 2 && g.rvec) tile[g.rslot + 1] = gv[1];
+        }
+    };
+    auto update = [&](const double *zm, const double *c, const double *zp, double *out) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int sl = g.own_slot + v;
+            const double xm = tile[sl - 1];
+            const double xp = tile[sl + 1];
+            const double ym = tile[sl - G::LD];
+            const double yp = tile[sl + G::LD];
+            const double nsum = ((xm + xp) + (ym + yp)) + (zm[v] + zp[v]);
+            const double lap = nsum - 6.0 * c[v];
+            out[v] = g.st[v] ? c[v] + r * lap : c[v];
+        }
+    };
+
     if (ke - kb + 1 == ZB) {
-        // q[s] = column value of plane kb-1+s, ring[s] = ring of plane kb+s
-        double q[ZB + 2];
-        double ring[ZB];
+        // q[s] = column values of plane kb-1+s, gr[s] = ring of plane kb+s
+        double q[ZB + 2][VEC];
+        double gr[ZB][2];
 #pragma unroll
-        for (int s = 0; s < PF + 2; ++s) q[s] = uo[(long long)(kb - 1 + s) * plane];
+        for (int s = 0; s < PF + 2; ++s) load_vec<VEC>(uo + (long long)(kb - 1 + s) * plane, q[s]);
 #pragma unroll
-        for (int s = 0; s < PF; ++s) ring[s] = ur[(long long)(kb + s) * plane];
+        for (int s = 0; s < PF; ++s) ld_ring((long long)(kb + s) * plane, gr[s]);
 #pragma unroll
         for (int s = 0; s < ZB; ++s) {
             const long long kp = (long long)(kb + s) * plane;
             __syncthreads();  // the previous plane's LDS reads are done
-            tile[g.own_slot] = q[s + 1];
-            if (g.rslot >= 0) tile[g.rslot] = ring[s];
-            if (s + PF < ZB) ring[s + PF] = ur[kp + PF * plane];
+            put(q[s + 1], gr[s]);
+            if (s + PF < ZB) ld_ring(kp + PF * plane, gr[s + PF]);
             __syncthreads();
-            const double out = plane_update<BY>(tile, g, q[s], q[s + 1], q[s + 2], 0.0, r);
-            __builtin_nontemporal_store(out, vo + kp);
-            if (s + 2 + PF <= ZB + 1) q[s + 2 + PF] = uo[kp + (1 + PF) * plane];
+            double out[VEC];
+            update(q[s], q[s + 1], q[s + 2], out);
+            store_vec_nt<VEC>(vo + kp, out);
+            if (s + 2 + PF <= ZB + 1) load_vec<VEC>(uo + kp + (1 + PF) * plane, q[s + 2 + PF]);
         }
         return;
     }
 
     // generic depth (short ranges): one plane of loads ahead
-    double zm = uo[(long long)(kb - 1) * plane];
-    double c = uo[(long long)kb * plane];
-    double zp = uo[(long long)(kb + 1) * plane];
-    double g0 = ur[(long long)kb * plane];
+    double zm[VEC], c[VEC], zp[VEC], g0[2];
+    load_vec<VEC>(uo + (long long)(kb - 1) * plane, zm);
+    load_vec<VEC>(uo + (long long)kb * plane, c);
+    load_vec<VEC>(uo + (long long)(kb + 1) * plane, zp);
+    ld_ring((long long)kb * plane, g0);
     for (int k = kb; k <= ke; ++k) {
         const long long kp = (long long)k * plane;
-        const double zn = uo[(long long)min(k + 2, ke + 1) * plane];
-        const double gn = ur[(long long)min(k + 1, ke) * plane];
+        double zn[VEC], gn[2];
+        load_vec<VEC>(uo + (long long)min(k + 2, ke + 1) * plane, zn);
+        ld_ring((long long)min(k + 1, ke) * plane, gn);
         __syncthreads();
-        tile[g.own_slot] = c;
-        if (g.rslot >= 0) tile[g.rslot] = g0;
+        put(c, g0);
         __syncthreads();
-        const double out = plane_update<BY>(tile, g, zm, c, zp, 0.0, r);
-        __builtin_nontemporal_store(out, vo + kp);
-        zm = c;
-        c = zp;
-        zp = zn;
-        g0 = gn;
+        double out[VEC];
+        update(zm, c, zp, out);
+        store_vec_nt<VEC>(vo + kp, out);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            zm[v] = c[v];
+            c[v] = zp[v];
+            zp[v] = zn[v];
+        }
+        g0[0] = gn[0];
+        g0[1] = gn[1];
     }
 }
 
 // Three entry points with one body, so that profiles name the role.
-template <int BY, int PF, int ZB>
-__global__ __launch_bounds__(64 * BY) void heat_interior_f64(
+template <int VEC, int WX, int BY, int PF, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void heat_interior_f64(
     const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
     double r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+    heat_tile_sweep<VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
 }
 
-template <int BY, int PF, int ZB>
-__global__ __launch_bounds__(64 * BY) void heat_boundary_f64(
+template <int VEC, int WX, int BY, int PF, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void heat_boundary_f64(
     const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
     double r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+    heat_tile_sweep<VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
 }
 
-template <int BY, int PF, int ZB>
-__global__ __launch_bounds__(64 * BY) void heat_fused_f64(
+template <int VEC, int WX, int BY, int PF, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void heat_fused_f64(
     const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
     double r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+    heat_tile_sweep<VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
 }
 
 // One thread per interior node, all seven values loaded from memory: the
@@ -263,10 +320,34 @@ __global__ __launch_bounds__(256) void copy_faces_f64(
 
 int ztable_blocks(const ZTable &zt) { return zt.n > 0 ? zt.first[zt.n] : 0; }
 
-long long heat_tile_blocks(int nx, int ny, int by, const ZTable &zt) {
-    const long long ntx = (nx + kTileX - 1) / kTileX;
-    const long long nty = (ny - 2 + by - 1) / by;
+int tile_width(const HeatTiling &t) { return 64 * t.vec * t.wx; }
+
+long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt) {
+    const long long tx = tile_width(t);
+    const long long ntx = (nx + tx - 1) / tx;
+    const long long nty = (ny - 2 + t.by - 1) / t.by;
     return ntx * nty * (long long)ztable_blocks(zt);
+}
+
+// Every tile shape the library is built with.
+#define HC_HEAT_SHAPES(X)                                                        \
+    X(1, 1, 4, 1, 16) X(1, 1, 4, 2, 16) X(1, 1, 4, 2, 32)                        \
+    X(1, 1, 8, 1, 16) X(1, 1, 8, 2, 16) X(1, 1, 8, 2, 32)                        \
+    X(1, 1, 16, 1, 16) X(1, 1, 16, 2, 16) X(1, 1, 16, 2, 32)                     \
+    X(1, 2, 8, 2, 16) X(1, 4, 4, 2, 16) X(1, 4, 4, 2, 32)                        \
+    X(2, 1, 4, 2, 16) X(2, 1, 8, 1, 16) X(2, 1, 8, 2, 16) X(2, 1, 8, 2, 32)     \
+    X(2, 1, 16, 2, 16) X(2, 2, 4, 2, 16) X(2, 2, 8, 1, 16) X(2, 2, 8, 2, 16)    \
+    X(2, 2, 8, 2, 32) X(2, 4, 4, 1, 16) X(2, 4, 4, 2, 16)                       \
+    X(2, 4, 4, 2, 32)
+
+#define HC_SHAPE_KEY(V, W, B, P, Z) ((((V * 8 + W) * 32 + B) * 4 + P) * 128 + Z)
+
+bool heat_tiling_supported(const HeatTiling &t) {
+    const int key = HC_SHAPE_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
+#define HC_X(V, W, B, P, Z) if (key == HC_SHAPE_KEY(V, W, B, P, Z)) return true;
+    HC_HEAT_SHAPES(HC_X)
+#undef HC_X
+    return false;
 }
 
 hipError_t launch_heat_tile_f64(KernelKind kind, const double *u, double *un,
@@ -274,40 +355,30 @@ hipError_t launch_heat_tile_f64(KernelKind kind, const double *u, double *un,
                                 const ZTable &zt, const HeatTiling &t,
                                 hipStream_t s) {
     (void)nz;
-    const long long nb = heat_tile_blocks(nx, ny, t.by, zt);
+    const long long nb = heat_tile_blocks(nx, ny, t, zt);
     if (nb <= 0) return hipSuccess;
     if (nb > INT_MAX) return hipErrorInvalidConfiguration;
-    const int ntx = (nx + kTileX - 1) / kTileX;
+    const int txw = tile_width(t);
+    const int ntx = (nx + txw - 1) / txw;
     const int nty = (ny - 2 + t.by - 1) / t.by;
-    const dim3 grid((unsigned)nb), block(64 * t.by);
-#define HC_HEAT_LAUNCH(BYV, PFV, ZBV)                                            \
-    do {                                                                         \
+    const dim3 grid((unsigned)nb), block(64 * t.wx * t.by);
+    const int key = HC_SHAPE_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
+#define HC_X(V, W, B, P, Z)                                                      \
+    if (key == HC_SHAPE_KEY(V, W, B, P, Z)) {                                    \
         if (kind == K_HEAT_INTERIOR)                                             \
-            heat_interior_f64<BYV, PFV, ZBV><<<grid, block, 0, s>>>(             \
+            heat_interior_f64<V, W, B, P, Z><<<grid, block, 0, s>>>(             \
                 u, un, nx, ny, r, zt, ntx, nty, t.xcd);                          \
         else if (kind == K_HEAT_BOUNDARY)                                        \
-            heat_boundary_f64<BYV, PFV, ZBV><<<grid, block, 0, s>>>(             \
+            heat_boundary_f64<V, W, B, P, Z><<<grid, block, 0, s>>>(             \
                 u, un, nx, ny, r, zt, ntx, nty, t.xcd);                          \
         else                                                                     \
-            heat_fused_f64<BYV, PFV, ZBV><<<grid, block, 0, s>>>(                \
+            heat_fused_f64<V, W, B, P, Z><<<grid, block, 0, s>>>(                \
                 u, un, nx, ny, r, zt, ntx, nty, t.xcd);                          \
-    } while (0)
-#define HC_HEAT_CASE(BYV, PFV, ZBV) \
-    case (BYV * 100 + PFV * 10000 + ZBV): HC_HEAT_LAUNCH(BYV, PFV, ZBV); break
-    switch (t.pf * 10000 + t.by * 100 + t.zdepth) {
-        HC_HEAT_CASE(4, 1, 16); HC_HEAT_CASE(4, 1, 32); HC_HEAT_CASE(4, 1, 64);
-        HC_HEAT_CASE(4, 2, 16); HC_HEAT_CASE(4, 2, 32); HC_HEAT_CASE(4, 2, 64);
-        HC_HEAT_CASE(4, 3, 16); HC_HEAT_CASE(4, 3, 32); HC_HEAT_CASE(4, 3, 64);
-        HC_HEAT_CASE(8, 1, 16); HC_HEAT_CASE(8, 1, 32); HC_HEAT_CASE(8, 1, 64);
-        HC_HEAT_CASE(8, 2, 16); HC_HEAT_CASE(8, 2, 32); HC_HEAT_CASE(8, 2, 64);
-        HC_HEAT_CASE(8, 3, 16); HC_HEAT_CASE(8, 3, 32); HC_HEAT_CASE(8, 3, 64);
-        HC_HEAT_CASE(16, 1, 16); HC_HEAT_CASE(16, 1, 32);
-        HC_HEAT_CASE(16, 2, 16); HC_HEAT_CASE(16, 2, 32);
-        default: return hipErrorInvalidValue;
+        return hipGetLastError();                                                \
     }
-#undef HC_HEAT_CASE
-#undef HC_HEAT_LAUNCH
-    return hipGetLastError();
+    HC_HEAT_SHAPES(HC_X)
+#undef HC_X
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_heat_plain_f64(const double *u, double *un, int nx, int ny,

@@ -105,12 +105,14 @@ def test_copy_probe_and_lap7_validation(lib):
 
 
 def test_tiling_knob(lib):
-    assert lib.hc_heat_set_tiling(5, 32, 1, 2) == HC_EINVAL
-    assert lib.hc_heat_set_tiling(4, 48, 1, 2) == HC_EINVAL
-    assert lib.hc_heat_set_tiling(16, 64, 1, 2) == HC_EINVAL
-    assert lib.hc_heat_set_tiling(8, 16, 0, 3) == HC_OK
-    assert hc.get_tiling() == (8, 16, 0, 3)
-    assert lib.hc_heat_set_tiling(4, 32, 1, 2) == HC_OK
+    assert lib.hc_heat_set_tiling(2, 4, 2, 16, 2, 0) == HC_EINVAL   # ring needs more threads
+    assert lib.hc_heat_set_tiling(1, 1, 4, 48, 2, 0) == HC_EINVAL   # depth not built
+    assert lib.hc_heat_set_tiling(3, 1, 4, 16, 2, 0) == HC_EINVAL
+    assert lib.hc_heat_set_tiling(1, 1, 8, 16, 2, 2) == HC_EINVAL   # xcd flag
+    assert lib.hc_heat_set_tiling(1, 4, 4, 32, 2, 1) == HC_OK
+    assert hc.get_tiling() == dict(vec=1, wx=4, by=4, zdepth=32, pf=2, xcd=1)
+    hc.set_tiling()
+    assert hc.get_tiling() == hc.DEFAULT_TILING
 
 
 def test_binding_raises_without_tensors():

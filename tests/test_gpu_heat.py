@@ -78,21 +78,71 @@ def test_ragged_shapes_bitwise(gpu, dims, mode):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("by,zdepth,pf,xcd", [
-    (4, 16, 1, 1), (4, 32, 2, 1), (4, 64, 3, 1), (8, 16, 2, 0), (8, 32, 1, 1),
-    (8, 64, 2, 1), (16, 16, 1, 1), (16, 32, 2, 0), (4, 32, 3, 0)])
-def test_every_tile_shape_is_bitwise_identical(gpu, by, zdepth, pf, xcd):
-    dims = (150, 37, 75)   # 71 interior planes: ragged against every depth
-    note("heat tiling by=%d zdepth=%d pf=%d xcd=%d" % (by, zdepth, pf, xcd))
+def built_shapes():
+    """Every tile shape libheatcg.so accepts (probed through the C ABI)."""
+    import paper_2608_11882_amd as hc
+    lib = hc.load()
+    shapes = []
+    for vec in (1, 2):
+        for wx in (1, 2, 4):
+            for by in (4, 8, 16):
+                for zd in (16, 32):
+                    for pf in (1, 2):
+                        if lib.hc_heat_set_tiling(vec, wx, by, zd, pf, 0) == 0:
+                            shapes.append((vec, wx, by, zd, pf))
+    hc.set_tiling()
+    return shapes
+
+
+def test_every_tile_shape_is_bitwise_identical(gpu):
+    dims = (150, 37, 75)   # 71 interior planes: ragged against every depth and width
     u0 = inputs.uniform_field(*dims, seed=31)
     want = oracle.heat(u0, 1.0 / 6.5, 5)
+    shapes = built_shapes()
+    assert len(shapes) >= 20
     try:
-        gpu.set_tiling(by, zdepth, xcd, pf)
-        for mode in ("split", "fused"):
-            got, _ = gpu_heat(gpu, u0, 1.0 / 6.5, 5, mode=mode)
-            assert np.array_equal(got, want), mode
+        for shape in shapes:
+            for xcd in (0, 1):
+                note("heat tiling vec,wx,by,zdepth,pf=%s xcd=%d" % (shape, xcd))
+                gpu.set_tiling(*shape, xcd=xcd)
+                for mode in ("split", "fused"):
+                    got, _ = gpu_heat(gpu, u0, 1.0 / 6.5, 5, mode=mode)
+                    assert np.array_equal(got, want), (shape, xcd, mode)
     finally:
         gpu.set_tiling()
+
+
+@pytest.mark.parametrize("dims", [(131, 20, 40), (257, 9, 35), (256, 17, 36), (260, 30, 34)])
+def test_wide_lanes_on_ragged_and_odd_widths(gpu, dims):
+    """Two-node lanes: widths that end inside a tile, and odd widths (which
+    fall back to one-node lanes)."""
+    note("heat wide lanes %s" % (dims,))
+    u0 = inputs.uniform_field(*dims, seed=dims[0])
+    want = oracle.heat(u0, 0.16, 6)
+    for shape in [(2, 1, 8, 16, 2), (2, 2, 8, 16, 2), (2, 4, 4, 16, 2)]:
+        try:
+            gpu.set_tiling(*shape)
+            got, _ = gpu_heat(gpu, u0, 0.16, 6)
+        finally:
+            gpu.set_tiling()
+        assert np.array_equal(got, want), shape
+
+
+def test_misaligned_arrays_fall_back_to_one_node_lanes(gpu):
+    dims = (130, 21, 33)
+    note("heat on 8-byte aligned (not 16) views")
+    u0 = inputs.uniform_field(*dims, seed=77)
+    n = u0.size
+    big_u = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    big_v = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    u = big_u[1:].view(dims[::-1])
+    un = big_v[1:].view(dims[::-1])
+    assert u.data_ptr() % 16 == 8
+    u.copy_(torch.from_numpy(u0))
+    gpu.heat_step(u, un, 0.1, 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(u.cpu().numpy(), oracle.heat(u0, 0.1, 4))
+    assert big_u[0].item() == 0.0 and big_v[0].item() == 0.0
 
 
 @pytest.mark.parametrize("parts", [1, 2, 3, 7, 32])
@@ -105,16 +155,19 @@ def test_slab_split_bitwise(gpu, parts):
     assert np.array_equal(got, want)
 
 
-def test_nonzero_dirichlet_data_is_kept_and_scratch_holds_previous_step(gpu):
+@pytest.mark.parametrize("steps", [5, 6])
+def test_nonzero_dirichlet_data_is_kept_and_scratch_contract(gpu, steps):
+    """Dirichlet data need not be zero; u_new ends as the header states:
+    u^(steps-1) for even step counts, u^steps for odd ones."""
     dims = (40, 33, 21)
-    note("heat nonzero boundary")
+    note("heat nonzero boundary, %d steps" % steps)
     rng = np.random.default_rng(17)
     u0 = rng.uniform(-1, 1, size=dims[::-1])
-    want = oracle.heat(u0, 0.1, 5)
-    prev = oracle.heat(u0, 0.1, 4)
-    got, scratch = gpu_heat(gpu, u0, 0.1, 5)
+    want = oracle.heat(u0, 0.1, steps)
+    got, scratch = gpu_heat(gpu, u0, 0.1, steps)
     assert np.array_equal(got, want)
-    assert np.array_equal(scratch, prev)
+    expect_scratch = want if steps % 2 else oracle.heat(u0, 0.1, steps - 1)
+    assert np.array_equal(scratch, expect_scratch)
 
 
 def test_chunked_calls_compose_and_zero_steps_is_a_noop(gpu):
