@@ -174,13 +174,26 @@ int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream);
  *  by      rows per tile
  *  zdepth  planes per z-block
  *  pf      planes of loads kept in flight ahead of the computed one (1, 2)
- *  xcd     1: deal consecutive tiles to the same XCD, 0: hardware order
+ *  xcd     0..64: runs of this many y-neighbouring tiles are dealt to one
+ *          XCD (so their shared halo rows are read through one L2); 0 or 1
+ *          keeps the hardware order
  * The shapes built are listed in heat_kernels.hip (HC_HEAT_SHAPES); others
- * return HC_EINVAL.  Default: vec 2, wx 2, by 8, zdepth 16, pf 2, xcd 0.
+ * return HC_EINVAL.  Default: vec 2, wx 4, by 4, zdepth 32, pf 2, xcd 8.
  */
 int hc_heat_set_tiling(int vec, int wx, int by, int zdepth, int pf, int xcd);
 void hc_heat_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *pf,
                         int *xcd);
+
+/*
+ * Tile shape of the CG kernels (and hc_lap7_apply), for the whole process;
+ * same meaning as for the heat kernels.  The shapes built are listed in
+ * cg_kernels.hip (HC_CG_SHAPES); others return HC_EINVAL.  Results are
+ * deterministic for a given shape; the summation tree of the dot products
+ * (and so the last bits of the iterates) depends on it.  Default: vec 2,
+ * wx 2, by 8, zdepth 32, xcd 8.
+ */
+int hc_cg_set_tiling(int vec, int wx, int by, int zdepth, int xcd);
+void hc_cg_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd);
 
 /* Name of a status code (static string). */
 const char *hc_strerror(int code);
@@ -189,12 +202,14 @@ const char *hc_strerror(int code);
 const char *hc_last_error_message(void);
 
 /*
- * Kernel timing for measurement.  While enabled, every launch of the
- * library's kernels is bracketed by HIP events on the stream it runs on,
- * and the algorithmic bytes it must move are added up per kernel kind.
- * hc_prof_enable(1) clears the counters; hc_prof_read waits for the
- * recorded launches and returns the total duration (ms), the launch count
- * and the algorithmic bytes of one kernel kind.
+ * Kernel timing for measurement.  hc_prof_enable(every) with every >= 1
+ * clears the counters and from then on brackets every `every`-th launch of
+ * each kernel kind with HIP events on the stream it runs on (the events cost
+ * a few microseconds of GPU time each, so sampling keeps the measured run
+ * close to an unmeasured one), adding up the algorithmic bytes each timed
+ * launch must move; every = 0 stops timing.  hc_prof_read waits for the
+ * recorded launches and returns, for one kernel kind, the total duration
+ * (ms), the number of timed launches and their algorithmic bytes.
  */
 enum hc_kernel_kind {
     HC_K_HEAT_INTERIOR = 0,
@@ -208,7 +223,7 @@ enum hc_kernel_kind {
     HC_K_COPY = 8,
     HC_K_COUNT = 9
 };
-int hc_prof_enable(int on);
+int hc_prof_enable(int every);
 int hc_prof_read(int kind, double *total_ms, long long *launches,
                  double *algo_bytes);
 

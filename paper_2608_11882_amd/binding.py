@@ -14,7 +14,8 @@ import os
 __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "cg_solve",
            "cg_workspace_bytes", "lap7_apply", "copy_probe", "prof_enable",
            "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV", "set_tiling",
-           "get_tiling", "DEFAULT_TILING"]
+           "get_tiling", "DEFAULT_TILING", "set_cg_tiling", "get_cg_tiling",
+           "DEFAULT_CG_TILING"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -66,6 +67,8 @@ def load():
         "hc_prof_read": (i, [i, dp, llp, dp]),
         "hc_heat_set_tiling": (i, [i, i, i, i, i, i]),
         "hc_heat_get_tiling": (None, [ip, ip, ip, ip, ip, ip]),
+        "hc_cg_set_tiling": (i, [i, i, i, i, i]),
+        "hc_cg_get_tiling": (None, [ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -183,11 +186,11 @@ def copy_probe(src, dst, stream=None) -> None:
                                 nbytes, _stream_handle(src, stream)))
 
 
-DEFAULT_TILING = dict(vec=2, wx=2, by=8, zdepth=16, pf=2, xcd=0)
+DEFAULT_TILING = dict(vec=2, wx=4, by=4, zdepth=32, pf=2, xcd=8)
 
 
-def set_tiling(vec: int = 2, wx: int = 2, by: int = 8, zdepth: int = 16, pf: int = 2,
-               xcd: int = 0) -> None:
+def set_tiling(vec: int = 2, wx: int = 4, by: int = 4, zdepth: int = 32, pf: int = 2,
+               xcd: int = 8) -> None:
     """Tile shape of the z-marching heat kernels (results do not depend on it)."""
     _check(load().hc_heat_set_tiling(int(vec), int(wx), int(by), int(zdepth), int(pf), int(xcd)))
 
@@ -198,8 +201,23 @@ def get_tiling() -> dict:
     return dict(zip(("vec", "wx", "by", "zdepth", "pf", "xcd"), (x.value for x in v)))
 
 
-def prof_enable(on: bool = True) -> None:
-    _check(load().hc_prof_enable(1 if on else 0))
+DEFAULT_CG_TILING = dict(vec=2, wx=2, by=8, zdepth=32, xcd=8)
+
+
+def set_cg_tiling(vec: int = 2, wx: int = 2, by: int = 8, zdepth: int = 32, xcd: int = 8) -> None:
+    """Tile shape of the CG kernels and of lap7_apply."""
+    _check(load().hc_cg_set_tiling(int(vec), int(wx), int(by), int(zdepth), int(xcd)))
+
+
+def get_cg_tiling() -> dict:
+    v = [ctypes.c_int(0) for _ in range(5)]
+    load().hc_cg_get_tiling(*[ctypes.byref(x) for x in v])
+    return dict(zip(("vec", "wx", "by", "zdepth", "xcd"), (x.value for x in v)))
+
+
+def prof_enable(on: bool = True, every: int = 1) -> None:
+    """Time every `every`-th launch of each kernel kind (off: on=False)."""
+    _check(load().hc_prof_enable(int(every) if on else 0))
 
 
 def prof_read(kind: str):

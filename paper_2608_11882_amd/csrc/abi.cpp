@@ -44,13 +44,30 @@ int hip_fail(hipError_t e, const char *what) {
 
 // ---- tile shape of the heat kernels (settable for tuning) -------------------
 std::mutex g_tiling_mu;
-// default: 256 x 8 tiles (two nodes per lane, two wavefronts per row),
-// z-blocks of 16 planes, two planes of loads in flight, hardware block order
-hc::HeatTiling g_tiling = {2, 2, 8, 16, 2, 0};
+// default: 512 x 4 tiles (two nodes per lane, four wavefronts per row),
+// z-blocks of 32 planes, two planes of loads in flight, runs of 8
+// y-neighbouring tiles per XCD (the fastest shape measured at 512^3)
+hc::HeatTiling g_tiling = {2, 4, 4, 32, 2, 8};
 
 hc::HeatTiling current_tiling() {
     std::lock_guard<std::mutex> g(g_tiling_mu);
     return g_tiling;
+}
+
+hc::CGTiling g_cg_tiling = {2, 2, 8, 32, 8};
+
+// The CG tile shape for these arrays: two-node lanes need an even x-edge and
+// 16-byte aligned vectors, else the one-node shape of the same tile height.
+hc::CGTiling cg_tiling_for(int nx, const void *a, const void *b, const void *c) {
+    hc::CGTiling t;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        t = g_cg_tiling;
+    }
+    const uintptr_t mis = (reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+                           reinterpret_cast<uintptr_t>(c)) & 15;
+    if (t.vec == 2 && ((nx & 1) || mis)) t = {1, 1, 4, 16, t.xcd};
+    return t;
 }
 
 // ---- per-device state -------------------------------------------------------
@@ -61,6 +78,7 @@ struct DevState {
     void *cg_work = nullptr;
     size_t cg_work_size = 0;
     hc::CGScalars *host_sc = nullptr;  // pinned
+    double *sink = nullptr;  // store target of lanes outside a CG box
 };
 
 constexpr int kMaxDev = 64;
@@ -80,6 +98,9 @@ int device_state(DevState **out) {
         void *h = nullptr;
         HC_TRY(hipHostMalloc(&h, sizeof(hc::CGScalars), hipHostMallocDefault), "hipHostMalloc");
         d.host_sc = static_cast<hc::CGScalars *>(h);
+        void *sk = nullptr;
+        HC_TRY(hipMalloc(&sk, hc::kSinkDoubles * sizeof(double)), "hipMalloc (sink)");
+        d.sink = static_cast<double *>(sk);
         d.ready = true;
     }
     *out = &d;
@@ -94,6 +115,8 @@ struct Pending {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+int g_prof_every = 1;                 // time every n-th launch of a kind
+long long g_prof_seen[hc::K_COUNT];   // launches of each kind since enable
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 double g_prof_ms[hc::K_COUNT];
@@ -117,6 +140,7 @@ class Timed {
     Timed(KernelKind kind, hipStream_t s, double bytes) : kind_(kind), s_(s), bytes_(bytes) {
         std::lock_guard<std::mutex> g(g_prof_mu);
         if (!g_prof_on) return;
+        if (g_prof_seen[kind]++ % g_prof_every != 0) return;
         a_ = pool_event();
         b_ = pool_event();
         if (a_ && b_ && hipEventRecord(a_, s_) == hipSuccess) on_ = true;
@@ -230,7 +254,7 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
     // two nodes per lane need 16-byte aligned rows
     if (til.vec == 2 && ((nx & 1) || (reinterpret_cast<uintptr_t>(u) & 15) ||
                          (reinterpret_cast<uintptr_t>(un) & 15)))
-        til = {1, 1, 16, 16, 2, til.xcd};
+        til = {1, 4, 4, 16, 2, til.xcd};
     const double plain_bytes = 8.0 * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
 
     hc::ZTable tin = empty_table(), tbd = empty_table();
@@ -274,17 +298,19 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
                    "heat_fused launch");
             tm.done();
         } else {
-            if (tin.n > 0) {
-                Timed tm(hc::K_HEAT_INTERIOR, s, bytes_in);
-                HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_INTERIOR, a, b, nx, ny, nz, r, tin, til, s),
-                       "heat_interior launch");
-                tm.done();
-            }
+            // the short Boundary kernel goes first, so it is long done when
+            // the next step's Interior kernel waits for it
             {
                 Timed tm(hc::K_HEAT_BOUNDARY, d->aux, bytes_bd);
                 HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_BOUNDARY, a, b, nx, ny, nz, r, tbd, til,
                                                 d->aux),
                        "heat_boundary launch");
+                tm.done();
+            }
+            if (tin.n > 0) {
+                Timed tm(hc::K_HEAT_INTERIOR, s, bytes_in);
+                HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_INTERIOR, a, b, nx, ny, nz, r, tin, til, s),
+                       "heat_interior launch");
                 tm.done();
             }
             // join: the next step needs both halves of this one, in both streams
@@ -328,6 +354,7 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
     int rc = device_state(&d);
     if (rc) return rc;
     const hc::CGWork w = hc::cg_work_carve(work, nx, ny, nz);
+    const hc::CGTiling til = cg_tiling_for(nx, b, x, w.r);
     hc::CGScalars *h = d->host_sc;
     const double n = (double)nx * ny * nz;
 
@@ -338,11 +365,21 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
     };
     auto residual = [&](int store_r) -> int {
         Timed tm(hc::K_CG_RESIDUAL, s, (store_r ? 24.0 : 16.0) * n);
-        HC_TRY(hc::launch_cg_residual(b, x, w, nx, ny, nz, store_r, s), "cg_residual launch");
+        HC_TRY(hc::launch_cg_residual(b, x, w, nx, ny, nz, store_r, til, d->sink, s),
+               "cg_residual launch");
         tm.done();
         return HC_OK;
     };
 
+    // the zero planes around r, p0 and p1
+    {
+        const size_t plane_bytes = (size_t)nx * ny * sizeof(double);
+        double *vecs[3] = {w.r, w.p[0], w.p[1]};
+        for (double *v : vecs) {
+            HC_TRY(hipMemsetAsync(v - (size_t)nx * ny, 0, plane_bytes, s), "hipMemsetAsync");
+            HC_TRY(hipMemsetAsync(v + (size_t)nz * nx * ny, 0, plane_bytes, s), "hipMemsetAsync");
+        }
+    }
     HC_TRY(hc::launch_cg_init(w, tol, s), "cg_init launch");
     if ((rc = residual(1))) return rc;
     if ((rc = read_scalars())) return rc;
@@ -377,12 +414,14 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         for (int q = 0; q < batch; ++q) {
             {
                 Timed tm(hc::K_CG_DIRECTION, s, (first ? 16.0 : 24.0) * n);
-                HC_TRY(hc::launch_cg_direction(w, cur, first, nx, ny, nz, s), "cg_direction launch");
+                HC_TRY(hc::launch_cg_direction(w, cur, first, nx, ny, nz, til, d->sink, s),
+                       "cg_direction launch");
                 tm.done();
             }
             {
                 Timed tm(hc::K_CG_UPDATE, s, 40.0 * n);
-                HC_TRY(hc::launch_cg_update(x, w, cur, nx, ny, nz, s), "cg_update launch");
+                HC_TRY(hc::launch_cg_update(x, w, cur, nx, ny, nz, til, d->sink, s),
+                       "cg_update launch");
                 tm.done();
             }
             cur ^= 1;
@@ -463,7 +502,8 @@ int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol, 
     if (maxit < 0) return fail(HC_EINVAL, "maxit = %d < 0", maxit);
     if (overlaps(b, bytes, x, bytes)) return fail(HC_EALIAS, "b and x overlap");
     const size_t need = hc::cg_work_bytes(nx, ny, nz);
-    if (hc::cg_blocks(nx, ny, nz) > 2147483647LL) return fail(HC_EINVAL, "grid too large");
+    if (hc::cg_blocks(nx, ny, nz, {1, 1, 4, 8, 0}) > 2147483647LL)
+        return fail(HC_EINVAL, "grid too large");
     if (work && work_bytes < need)
         return fail(HC_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
     if ((rc = check_device_buffer(b, bytes, "b"))) return rc;
@@ -518,12 +558,16 @@ int hc_lap7_apply(const double *x, double *y, int nx, int ny, int nz, hc_stream_
     int rc = check_dims(nx, ny, nz, 1, 8, &bytes);
     if (rc) return rc;
     if (overlaps(x, bytes, y, bytes)) return fail(HC_EALIAS, "x and y overlap");
-    if (hc::cg_blocks(nx, ny, nz) > 2147483647LL) return fail(HC_EINVAL, "grid too large");
+    if (hc::cg_blocks(nx, ny, nz, {1, 1, 4, 8, 0}) > 2147483647LL)
+        return fail(HC_EINVAL, "grid too large");
     if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
     if ((rc = check_device_buffer(y, bytes, "y"))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DevState *d = nullptr;
+    if ((rc = device_state(&d))) return rc;
+    const hc::CGTiling til = cg_tiling_for(nx, x, y, x);
     Timed tm(hc::K_LAP7, s, 16.0 * nx * ny * nz);
-    HC_TRY(hc::launch_lap7_f64(x, y, nx, ny, nz, s), "lap7 launch");
+    HC_TRY(hc::launch_lap7_f64(x, y, nx, ny, nz, til, d->sink, s), "lap7 launch");
     tm.done();
     return HC_OK;
 }
@@ -551,7 +595,7 @@ int hc_heat_set_tiling(int vec, int wx, int by, int zdepth, int pf, int xcd) {
     if (!hc::heat_tiling_supported(t))
         return fail(HC_EINVAL, "tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built",
                     vec, wx, by, zdepth, pf);
-    if (xcd != 0 && xcd != 1) return fail(HC_EINVAL, "xcd must be 0 or 1");
+    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
     std::lock_guard<std::mutex> g(g_tiling_mu);
     g_tiling = t;
     return HC_OK;
@@ -567,8 +611,34 @@ void hc_heat_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *pf, int *x
     if (xcd) *xcd = t.xcd;
 }
 
-int hc_prof_enable(int on) {
+int hc_cg_set_tiling(int vec, int wx, int by, int zdepth, int xcd) {
     g_msg.clear();
+    const hc::CGTiling t = {vec, wx, by, zdepth, xcd};
+    if (!hc::cg_tiling_supported(t))
+        return fail(HC_EINVAL, "CG tile shape (vec %d, wx %d, by %d, zdepth %d) is not built", vec,
+                    wx, by, zdepth);
+    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_cg_tiling = t;
+    return HC_OK;
+}
+
+void hc_cg_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd) {
+    hc::CGTiling t;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        t = g_cg_tiling;
+    }
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (xcd) *xcd = t.xcd;
+}
+
+int hc_prof_enable(int every) {
+    g_msg.clear();
+    if (every < 0) return fail(HC_EINVAL, "every = %d < 0", every);
     std::lock_guard<std::mutex> g(g_prof_mu);
     for (const Pending &p : g_pending) {
         g_event_pool.push_back(p.a);
@@ -579,8 +649,10 @@ int hc_prof_enable(int on) {
         g_prof_ms[k] = 0.0;
         g_prof_n[k] = 0;
         g_prof_bytes[k] = 0.0;
+        g_prof_seen[k] = 0;
     }
-    g_prof_on = (on != 0);
+    g_prof_on = (every != 0);
+    g_prof_every = every > 0 ? every : 1;
     return HC_OK;
 }
 

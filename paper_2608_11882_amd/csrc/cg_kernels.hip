@@ -16,8 +16,13 @@
 // from r and p (the same expression, so the same bits as the value stored
 // there), and the update kernel recomputes A p' from p'.  Each iteration
 // therefore moves 64 bytes per unknown (r, p read + p' written; x, r, p'
-// read + x, r written), against 80 with a stored q.  The z-march is the one
-// of the heat kernels: 64 x BY tiles, registers along z, LDS ring in x/y.
+// read + x, r written), against 80 with a stored q.
+//
+// The z-march is the heat kernels' one: tiles of 64*VEC*WX (x) by BY (y)
+// nodes walk z-blocks of ZB planes with the column in registers and the
+// plane in LDS with a one-node ring; loads are issued at clamped in-box
+// addresses with out-of-box values replaced by the zero Dirichlet data, and
+// full-depth z-blocks are unrolled so that loads stay in flight.
 //
 // Reductions are deterministic: every block reduces its own partial in a
 // fixed tree; the last block to arrive (arrival ticket) adds the partials
@@ -27,163 +32,275 @@
 #include "hc_internal.hpp"
 
 #include <climits>
+#include <type_traits>
 
 namespace hc {
 namespace {
 
-constexpr int kBY = 4;                 // waves per block
-constexpr int kThreads = 64 * kBY;
-constexpr int kZDepth = 32;            // planes per z-block
-constexpr int kLd = kTileX + 2;
+constexpr int kPF = 2;  // planes of field loads in flight
 
-__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
-    constexpr int kXcd = 8;
-    const int xcd = bid % kXcd, slot = bid / kXcd;
-    const int per = nblk / kXcd, rem = nblk % kXcd;
-    return xcd * per + min(xcd, rem) + slot;
+// Block order: the hardware deals workgroups to the 8 XCDs round-robin; with
+// g > 1, runs of g consecutive tiles (y-neighbours) are dealt to one XCD
+// inside windows of 8g blocks (same scheme as the heat kernels).
+__device__ __forceinline__ int block_order(int b, int nb, int g) {
+    if (g <= 1) return b;
+    const int win = 8 * g;
+    const int w = b / win;
+    if ((w + 1) * win > nb) return b;
+    const int o = b - w * win;
+    return w * win + (o & 7) * g + (o >> 3);
 }
 
-struct Tile {
-    int tx, ty, kb, ke;
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <int VEC>
+__device__ __forceinline__ void load_vec(const double *__restrict__ p, double *o) {
+    if (VEC == 2) {
+        const f64x2 v = *reinterpret_cast<const f64x2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    } else {
+        o[0] = *p;
+    }
+}
+
+// Store VEC values.  With two-node lanes the x-edge is even, so a lane is
+// either inside the box or wholly outside it; a lane outside stores into
+// its own slot of a sink buffer instead, so no store sits under a branch.
+template <int VEC>
+__device__ __forceinline__ void store_vec(double *__restrict__ p, const double *v, bool nt) {
+    if (VEC == 2) {
+        f64x2 x;
+        x.x = v[0];
+        x.y = v[VEC - 1];
+        if (nt)
+            __builtin_nontemporal_store(x, reinterpret_cast<f64x2 *>(p));
+        else
+            *reinterpret_cast<f64x2 *>(p) = x;
+    } else {
+        if (nt)
+            __builtin_nontemporal_store(v[0], p);
+        else
+            p[0] = v[0];
+    }
+}
+
+// Address of a node: a uniform base (array + plane k, in scalar registers)
+// plus the lane's 32-bit byte offset within the plane, the form the
+// SGPR-base addressing of global loads and stores takes.  A plane is far
+// below 4 GiB, so the offset fits.
+template <class T>
+__device__ __forceinline__ T *node(T *base, long long plane, int k, unsigned off) {
+    return reinterpret_cast<T *>(
+        reinterpret_cast<typename std::conditional<std::is_const<T>::value, const char, char>::type *>(
+            base + (long long)k * plane) + off);
+}
+
+template <int VEC, int WX, int BY>
+struct BoxGeom {
+    static constexpr int TX = 64 * VEC * WX;
+    static constexpr int LD = TX + 2;
+    static constexpr int NT = 64 * WX * BY;
+    static constexpr int RROW = TX / VEC;
+    static_assert(NT >= 2 * RROW + 2 * BY, "one thread per ring element");
+    int kb, ke;
+    long long plane, own, ring;  // ring: VEC-aligned offset of the ring load
+    unsigned own_b, ring_b;      // the same in bytes within the plane
+    bool in[VEC];     // own nodes inside the box
+    bool lane_in;     // all own nodes inside the box
+    bool rin[VEC];    // ring nodes inside the box
+    int own_slot, rslot;
+    bool rvec;
+    int rsel;         // a column node's index within its aligned ring load
+
+    __device__ __forceinline__ BoxGeom(int nx, int ny, int nz, int zdepth, int xcd) {
+        const int ntx = (nx + TX - 1) / TX;
+        const int nty = (ny + BY - 1) / BY;
+        const int L = block_order(blockIdx.x, gridDim.x, xcd);
+        const int ty = L % nty;
+        const int rest = L / nty;
+        const int tx = rest % ntx;
+        kb = (rest / ntx) * zdepth;
+        ke = min(kb + zdepth - 1, nz - 1);
+
+        const int t = threadIdx.x;
+        const int lane = t & 63, w = t >> 6;
+        const int wy = w / WX, wx = w % WX;
+        const int i0 = tx * TX, j0 = ty * BY;
+        const int ia = i0 + (wx * 64 + lane) * VEC;
+        const int j = j0 + wy;
+        plane = (long long)nx * ny;
+        own = (long long)min(j, ny - 1) * nx + min(ia, nx - VEC);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) in[v] = (ia + v < nx) && (j < ny);
+        lane_in = in[VEC - 1];
+        own_slot = (wy + 1) * LD + (wx * 64 + lane) * VEC + 1;
+
+        rvec = false;
+        rslot = -1;
+        rsel = 0;
+        int ri = 0, rj = 0;
+        if (t < 2 * RROW) {
+            const int row = t / RROW, q = t % RROW;
+            rj = row == 0 ? j0 - 1 : j0 + BY;
+            ri = i0 + q * VEC;
+            rslot = (row == 0 ? 0 : (BY + 1) * LD) + q * VEC + 1;
+            rvec = true;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) rin[v] = (rj >= 0) && (rj < ny) && (ri + v < nx);
+            ri = min(ri, nx - VEC);
+        } else if (t < 2 * RROW + 2 * BY) {
+            const int q = t - 2 * RROW;
+            const int row = q % BY, side = q / BY;
+            ri = side == 0 ? i0 - 1 : i0 + TX;
+            rj = j0 + row;
+            rslot = (row + 1) * LD + (side == 0 ? 0 : TX + 1);
+            rin[0] = (ri >= 0) && (ri < nx) && (rj < ny);
+#pragma unroll
+            for (int v = 1; v < VEC; ++v) rin[v] = false;
+            ri = max(0, min(ri, nx - 1));
+            rsel = ri % VEC;
+            ri -= rsel;
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) rin[v] = false;
+            ri = min(ia, nx - VEC);
+            rj = j;
+        }
+        ring = (long long)max(0, min(rj, ny - 1)) * nx + ri;
+        own_b = (unsigned)(own * (long long)sizeof(double));
+        ring_b = (unsigned)(ring * (long long)sizeof(double));
+    }
 };
 
-__device__ __forceinline__ Tile decode_tile(int nx, int ny, int nz) {
-    const int ntx = (nx + kTileX - 1) / kTileX;
-    const int nty = (ny + kBY - 1) / kBY;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    Tile t;
-    t.tx = L % ntx;
-    const int rest = L / ntx;
-    t.ty = rest % nty;
-    t.kb = (rest / nty) * kZDepth;
-    t.ke = min(t.kb + kZDepth - 1, nz - 1);
-    return t;
-}
-
-// Walk a 64 x kBY tile of the box through planes [kb, ke].
+// Walk the block's tile through its z-block.
 //
-//  field.at(off)        value of the marched field at the in-box node `off`
-//                       (every load is issued unconditionally at a clamped
-//                       in-box address; nodes outside the box are then
-//                       replaced by 0, the zero Dirichlet data)
-//  epi.prefetch(off)    issue the loads the epilogue needs at the own node
-//                       `off` of a plane (clamped offset), returned as Pre
-//  epi.finish(ok, off, c, nsum, pre)  own node: field value c, the ordered
-//                       sum of its six neighbours and the prefetched values;
-//                       ok is false off the box
+//  field.template load<V>(off, out)   V field values from the in-box node
+//                        `off` on (clamped offsets; loads unconditional)
+//  epi.prefetch(off)     the epilogue's own loads for a plane, as Epi::Pre
+//  epi.finish(ok, off, c, nsum, pre)  own nodes: field values, ordered
+//                        neighbour sums, prefetched values; ok[v] false off
+//                        the box
 //
-// As in the heat kernels no load sits under a branch, and a z-block of
-// exactly kZDepth planes is fully unrolled so that the register queue along
-// z is renamed rather than copied; kPF planes of field loads and one plane
-// of epilogue loads stay in flight.  Shorter z-blocks take a plain loop.
-constexpr int kPF = 2;
-
-template <class Field, class Epi>
-__device__ __forceinline__ void box_zmarch(int nx, int ny, int nz,
-                                           const Tile &t, Field &field,
-                                           Epi &epi) {
-    constexpr int kRing = 2 * kTileX + 2 * kBY;
-    static_assert(kThreads >= kRing, "one thread per ring node");
+// ZPAD: the field's arrays carry one zero plane below plane 0 and one above
+// plane nz-1, so planes -1 and nz are read from memory and no plane index
+// is ever tested (a uniform test would let the compiler branch around the
+// load, and a load under a branch makes it wait for every load in flight).
+// UNROLL: take the unrolled path for full-depth z-blocks (false keeps the
+// plain loop, for kernels that run once or twice per solve).
+template <int VEC, int WX, int BY, int ZB, bool ZPAD, bool UNROLL = true, class Field,
+          class Epi>
+__device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
+                                           double *sink, Field &field, Epi &epi) {
+    using G = BoxGeom<VEC, WX, BY>;
     using Pre = typename Epi::Pre;
-    __shared__ double tile[(kBY + 2) * kLd];
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int i0 = t.tx * kTileX, j0 = t.ty * kBY;
-    const int i = i0 + lane, j = j0 + w;
-    const long long plane = (long long)nx * ny;
+    static_assert(G::NT * VEC <= kSinkDoubles, "sink holds one slot per lane");
+    __shared__ double tile[(BY + 2) * G::LD];
+    const G g(nx, ny, nz, ZB, xcd);
+    // a lane outside the box writes its own sink slot
+    double *const lane_sink = sink + (long long)threadIdx.x * VEC;
 
-    const bool own_in = (i < nx) && (j < ny);
-    const long long own = (long long)min(j, ny - 1) * nx + min(i, nx - 1);
-    const int own_slot = (w + 1) * kLd + lane + 1;
-
-    const int e = threadIdx.x;
-    int ri, rj, rslot;
-    if (e < kTileX) {
-        ri = i0 + e; rj = j0 - 1; rslot = e + 1;
-    } else if (e < 2 * kTileX) {
-        ri = i0 + e - kTileX; rj = j0 + kBY; rslot = (kBY + 1) * kLd + (e - kTileX) + 1;
-    } else if (e < 2 * kTileX + kBY) {
-        ri = i0 - 1; rj = j0 + (e - 2 * kTileX); rslot = (e - 2 * kTileX + 1) * kLd;
-    } else if (e < kRing) {
-        ri = i0 + kTileX; rj = j0 + (e - 2 * kTileX - kBY);
-        rslot = (e - 2 * kTileX - kBY + 1) * kLd + kTileX + 1;
-    } else {
-        ri = i; rj = j; rslot = -1;
-    }
-    const bool ring_in = (ri >= 0) && (ri < nx) && (rj >= 0) && (rj < ny);
-    const long long ring =
-        (long long)max(0, min(rj, ny - 1)) * nx + max(0, min(ri, nx - 1));
-
-    // value at plane k (clamped into the box, 0 outside)
-    auto val = [&](int k, long long off, bool in) -> double {
-        const int kc = max(0, min(k, nz - 1));
-        const double v = field.at((long long)kc * plane + off);
-        return (in && k >= 0 && k < nz) ? v : 0.0;
+    // column values of plane k (0 outside the box)
+    auto col = [&](int k, double *o) {
+        const int kc = ZPAD ? k : max(0, min(k, nz - 1));
+        const bool kin = ZPAD || ((k >= 0) && (k < nz));
+        double v[VEC];
+        field.template load<VEC>(kc, g.own_b, v);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = (kin && g.in[e]) ? v[e] : 0.0;
     };
-    auto neighbours = [&](double zm, double zp) -> double {
-        const double xm = tile[own_slot - 1];
-        const double xp = tile[own_slot + 1];
-        const double ym = tile[own_slot - kLd];
-        const double yp = tile[own_slot + kLd];
-        return ((xm + xp) + (ym + yp)) + (zm + zp);
+    // one aligned VEC-wide load in every lane; a column node is picked out
+    auto ringv = [&](int k, double *o) {
+        const int kc = ZPAD ? k : max(0, min(k, nz - 1));
+        const bool kin = ZPAD || ((k >= 0) && (k < nz));
+        double v[VEC];
+        field.template load<VEC>(kc, g.ring_b, v);
+        if (VEC == 2 && g.rsel) v[0] = v[VEC - 1];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = (kin && g.rin[e]) ? v[e] : 0.0;
     };
-    const int kb = t.kb;
+    auto put = [&](const double *c, const double *rv) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) tile[g.own_slot + e] = c[e];
+        if (g.rslot >= 0) {
+            tile[g.rslot] = rv[0];
+            if (VEC == 2 && g.rvec) tile[g.rslot + VEC - 1] = rv[VEC - 1];
+        }
+    };
+    auto nsums = [&](const double *zm, const double *zp, double *ns) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int sl = g.own_slot + e;
+            const double xm = tile[sl - 1];
+            const double xp = tile[sl + 1];
+            const double ym = tile[sl - G::LD];
+            const double yp = tile[sl + G::LD];
+            ns[e] = ((xm + xp) + (ym + yp)) + (zm[e] + zp[e]);
+        }
+    };
+    const int kb = g.kb, ke = g.ke;
 
-    if (t.ke - kb + 1 == kZDepth) {
-        double q[kZDepth + 2];  // q[s]: field at plane kb-1+s of the column
-        double rgv[kZDepth];    // ring values of plane kb+s
-        Pre pre[kZDepth];
+    if (UNROLL && ke - kb + 1 == ZB) {
+        double q[ZB + 2][VEC];  // q[s]: column at plane kb-1+s
+        double rg[ZB][VEC];     // ring values of plane kb+s
+        Pre pre[ZB];
 #pragma unroll
-        for (int s = 0; s < kPF + 2; ++s) q[s] = val(kb - 1 + s, own, own_in);
+        for (int s = 0; s < kPF + 2; ++s) col(kb - 1 + s, q[s]);
 #pragma unroll
-        for (int s = 0; s < kPF; ++s) rgv[s] = val(kb + s, ring, ring_in);
-        pre[0] = epi.prefetch((long long)kb * plane + own);
+        for (int s = 0; s < kPF; ++s) ringv(kb + s, rg[s]);
+        pre[0] = epi.prefetch(kb, g.own_b);
 #pragma unroll
-        for (int s = 0; s < kZDepth; ++s) {
-            const long long kp = (long long)(kb + s) * plane;
+        for (int s = 0; s < ZB; ++s) {
             __syncthreads();
-            tile[own_slot] = q[s + 1];
-            if (rslot >= 0) tile[rslot] = rgv[s];
-            if (s + kPF < kZDepth) rgv[s + kPF] = val(kb + s + kPF, ring, ring_in);
-            if (s + 1 < kZDepth) pre[s + 1] = epi.prefetch(kp + plane + own);
+            put(q[s + 1], rg[s]);
+            if (s + kPF < ZB) ringv(kb + s + kPF, rg[s + kPF]);
+            if (s + 1 < ZB) pre[s + 1] = epi.prefetch(kb + s + 1, g.own_b);
             __syncthreads();
-            epi.finish(own_in, kp + own, q[s + 1], neighbours(q[s], q[s + 2]), pre[s]);
-            if (s + 2 + kPF <= kZDepth + 1) q[s + 2 + kPF] = val(kb + s + 1 + kPF, own, own_in);
+            double ns[VEC];
+            nsums(q[s], q[s + 2], ns);
+            epi.finish(g.in, g.lane_in, kb + s, g.own_b, lane_sink, q[s + 1], ns, pre[s]);
+            if (s + 2 + kPF <= ZB + 1) col(kb + s + 1 + kPF, q[s + 2 + kPF]);
         }
         return;
     }
 
-    double zm = val(kb - 1, own, own_in);
-    double c = val(kb, own, own_in);
-    double zp = val(kb + 1, own, own_in);
-    double rc = val(kb, ring, ring_in);
-    for (int k = kb; k <= t.ke; ++k) {
-        const long long kp = (long long)k * plane;
-        const double nn = val(k + 2, own, own_in);
-        const double rn = val(min(k + 1, t.ke), ring, ring_in);
-        const Pre pr = epi.prefetch(kp + own);
+    double zm[VEC], c[VEC], zp[VEC], rc[VEC];
+    col(kb - 1, zm);
+    col(kb, c);
+    col(kb + 1, zp);
+    ringv(kb, rc);
+    for (int k = kb; k <= ke; ++k) {
+        double nn[VEC], rn[VEC];
+        col(k + 2, nn);
+        ringv(min(k + 1, ke), rn);
+        const Pre pr = epi.prefetch(k, g.own_b);
         __syncthreads();
-        tile[own_slot] = c;
-        if (rslot >= 0) tile[rslot] = rc;
+        put(c, rc);
         __syncthreads();
-        epi.finish(own_in, kp + own, c, neighbours(zm, zp), pr);
-        zm = c;
-        c = zp;
-        zp = nn;
-        rc = rn;
+        double ns[VEC];
+        nsums(zm, zp, ns);
+        epi.finish(g.in, g.lane_in, k, g.own_b, lane_sink, c, ns, pr);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            zm[e] = c[e];
+            c[e] = zp[e];
+            zp[e] = nn[e];
+            rc[e] = rn[e];
+        }
     }
 }
 
 // Fixed-order block sum; the result is valid in thread 0.
+template <int NT>
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double red[kThreads / 64];
+    __shared__ double red[NT / 64];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) red[w] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int q = 0; q < kThreads / 64; ++q) s += red[q];
+        for (int q = 0; q < NT / 64; ++q) s += red[q];
     __syncthreads();
     return s;
 }
@@ -217,12 +334,12 @@ __device__ __forceinline__ bool arrive(CGScalars *sc, double *partial,
 }
 
 // In the last block: fixed-order sum of partial[b*nsum + q] over blocks b.
-__device__ __forceinline__ double gather(const double *partial, int nsum,
-                                         int q) {
+template <int NT>
+__device__ __forceinline__ double gather(const double *partial, int nsum, int q) {
     double t = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kThreads)
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT)
         t += load_agent(&partial[(long long)b * nsum + q]);
-    return block_sum(t);
+    return block_sum<NT>(t);
 }
 
 __global__ __launch_bounds__(64) void cg_init(CGScalars *sc, double tol) {
@@ -241,63 +358,150 @@ __global__ __launch_bounds__(64) void cg_init(CGScalars *sc, double tol) {
     }
 }
 
-struct NoPre {};
-
 struct PlainField {
     const double *__restrict__ x;
-    __device__ double at(long long o) const { return x[o]; }
+    long long plane;
+    template <int V>
+    __device__ void load(int k, unsigned off, double *out) const {
+        load_vec<V>(node(x, plane, k, off), out);
+    }
 };
 
 // p' = r + beta p (p' = r on the first iteration)
 struct DirectionField {
     const double *__restrict__ r;
     const double *__restrict__ p;
+    long long plane;
     double beta;
     int first;
-    __device__ double at(long long o) const {
-        const double ro = r[o];
-        const double po = p[o];
-        return first ? ro : ro + beta * po;
+    template <int V>
+    __device__ void load(int k, unsigned off, double *out) const {
+        double rv[V], pv[V];
+        load_vec<V>(node(r, plane, k, off), rv);
+        load_vec<V>(node(p, plane, k, off), pv);
+#pragma unroll
+        for (int e = 0; e < V; ++e) out[e] = first ? rv[e] : rv[e] + beta * pv[e];
     }
 };
 
-// mode 0: r = b - A x (stored), rho = r.r, b.b, threshold and state.
-// mode 1: true residual only: rtrue2 = |b - A x|^2 (nothing stored).
+struct NoPre {
+    int unused;
+};
+
+// out = b - A x, with r.r and b.b
+// (b is loaded where it is used: this kernel runs once or twice per solve
+// and is not worth the registers of a prefetch)
+template <int VEC>
 struct ResidualEpi {
-    struct Pre {
-        double b;
-    };
+    using Pre = NoPre;
     const double *__restrict__ b;
     double *__restrict__ r;
-    int store;
+    long long plane;
     double rr = 0.0, bb = 0.0;
-    __device__ Pre prefetch(long long o) const { return Pre{b[o]}; }
-    __device__ void finish(bool ok, long long o, double c, double nsum, Pre p) {
-        const double bo = p.b;
-        const double q = 6.0 * c - nsum;
-        const double ro = bo - q;
-        if (ok) {
-            if (store) r[o] = ro;
-            rr += ro * ro;
-            bb += bo * bo;
+    __device__ Pre prefetch(int, unsigned) const { return Pre{0}; }
+    __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
+                           const double *c, const double *ns, const Pre &) {
+        double bo[VEC], ro[VEC];
+        load_vec<VEC>(node(b, plane, k, off), bo);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const double q = 6.0 * c[e] - ns[e];
+            ro[e] = bo[e] - q;
+            if (ok[e]) {
+                rr += ro[e] * ro[e];
+                bb += bo[e] * bo[e];
+            }
         }
+        store_vec<VEC>(lane_in ? node(r, plane, k, off) : sink, ro, false);
     }
 };
 
-__global__ __launch_bounds__(kThreads) void cg_residual_f64(
+template <int VEC>
+struct DirectionEpi {
+    using Pre = NoPre;
+    double *__restrict__ pnew;
+    long long plane;
+    double acc = 0.0;
+    __device__ Pre prefetch(int, unsigned) const { return Pre{0}; }
+    __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
+                           const double *c, const double *ns, const Pre &) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const double q = 6.0 * c[e] - ns[e];
+            if (ok[e]) acc += c[e] * q;
+        }
+        store_vec<VEC>(lane_in ? node(pnew, plane, k, off) : sink, c, true);
+    }
+};
+
+// x += alpha p', r -= alpha A p', and r.r of the new residual
+template <int VEC>
+struct UpdateEpi {
+    struct Pre {
+        double x[VEC], r[VEC];
+    };
+    double *__restrict__ x;
+    double *__restrict__ r;
+    long long plane;
+    double alpha;
+    double acc = 0.0;
+    __device__ Pre prefetch(int k, unsigned off) const {
+        Pre p;
+        load_vec<VEC>(node(x, plane, k, off), p.x);
+        load_vec<VEC>(node(r, plane, k, off), p.r);
+        return p;
+    }
+    __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
+                           const double *c, const double *ns, const Pre &p) {
+        double xn[VEC], rn[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const double q = 6.0 * c[e] - ns[e];
+            xn[e] = p.x[e] + alpha * c[e];
+            rn[e] = p.r[e] - alpha * q;
+            if (ok[e]) acc += rn[e] * rn[e];
+        }
+        store_vec<VEC>(lane_in ? node(x, plane, k, off) : sink, xn, false);
+        store_vec<VEC>(lane_in ? node(r, plane, k, off) : sink, rn, false);
+    }
+};
+
+template <int VEC>
+struct Lap7Epi {
+    using Pre = NoPre;
+    double *__restrict__ y;
+    long long plane;
+    __device__ Pre prefetch(int, unsigned) const { return Pre{0}; }
+    __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
+                           const double *c, const double *ns, const Pre &) {
+        (void)ok;
+        double out[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) out[e] = 6.0 * c[e] - ns[e];
+        store_vec<VEC>(lane_in ? node(y, plane, k, off) : sink, out, false);
+    }
+};
+
+// mode 0: r = b - A x, rho = r.r, b.b, threshold and state.
+// mode 1: the true residual |b - A x|^2 of the current x; the vector b - A x
+//         goes to `r`, which the driver then points at a dead direction
+//         buffer (a restart rebuilds both r and p).
+template <int VEC, int WX, int BY, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void cg_residual_f64(
     const double *__restrict__ b, const double *__restrict__ x,
     double *__restrict__ r, double *partial, CGScalars *sc, int nx, int ny,
-    int nz, int mode) {
-    const Tile t = decode_tile(nx, ny, nz);
-    PlainField f{x};
-    ResidualEpi epi{b, r, mode == 0 ? 1 : 0};
-    box_zmarch(nx, ny, nz, t, f, epi);
+    int nz, int xcd, double *sink, int mode) {
+    constexpr int NT = 64 * WX * BY;
+    const long long plane = (long long)nx * ny;
+    PlainField f{x, plane};
+    ResidualEpi<VEC> epi{b, r, plane};
+    box_zmarch<VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi);
     double v[2];
-    v[0] = block_sum(epi.rr);
-    v[1] = block_sum(epi.bb);
+    v[0] = block_sum<NT>(epi.rr);
+    v[1] = block_sum<NT>(epi.bb);
     if (arrive(sc, partial, 2, v)) {
-        const double srr = gather(partial, 2, 0);
-        const double sbb = gather(partial, 2, 1);
+        const double srr = gather<NT>(partial, 2, 0);
+        const double sbb = gather<NT>(partial, 2, 1);
         if (threadIdx.x == 0) {
             if (mode == 0) {
                 sc->rho = srr;
@@ -315,33 +519,21 @@ __global__ __launch_bounds__(kThreads) void cg_residual_f64(
     }
 }
 
-struct DirectionEpi {
-    using Pre = NoPre;
-    double *__restrict__ pnew;
-    double acc = 0.0;
-    __device__ Pre prefetch(long long) const { return Pre{}; }
-    __device__ void finish(bool ok, long long o, double c, double nsum, Pre) {
-        const double q = 6.0 * c - nsum;
-        if (ok) {
-            __builtin_nontemporal_store(c, pnew + o);
-            acc += c * q;
-        }
-    }
-};
-
-__global__ __launch_bounds__(kThreads) void cg_direction_f64(
+template <int VEC, int WX, int BY, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void cg_direction_f64(
     const double *__restrict__ r, const double *__restrict__ pold,
     double *__restrict__ pnew, double *partial, CGScalars *sc, int nx, int ny,
-    int nz, int first) {
+    int nz, int xcd, double *sink, int first) {
+    constexpr int NT = 64 * WX * BY;
     if (load_state(sc) != 0) return;  // converged or failed: nothing to do
-    const Tile t = decode_tile(nx, ny, nz);
-    DirectionField f{r, first ? r : pold, first ? 0.0 : sc->beta, first};
-    DirectionEpi epi{pnew};
-    box_zmarch(nx, ny, nz, t, f, epi);
+    const long long plane = (long long)nx * ny;
+    DirectionField f{r, first ? r : pold, plane, first ? 0.0 : sc->beta, first};
+    DirectionEpi<VEC> epi{pnew, plane};
+    box_zmarch<VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
     double v[1];
-    v[0] = block_sum(epi.acc);
+    v[0] = block_sum<NT>(epi.acc);
     if (arrive(sc, partial, 1, v)) {
-        const double pap = gather(partial, 1, 0);
+        const double pap = gather<NT>(partial, 1, 0);
         if (threadIdx.x == 0) {
             sc->pap = pap;
             if (!isfinite(pap))
@@ -355,41 +547,21 @@ __global__ __launch_bounds__(kThreads) void cg_direction_f64(
     }
 }
 
-// x += alpha p', r -= alpha A p', and r.r of the new residual
-struct UpdateEpi {
-    struct Pre {
-        double x, r;
-    };
-    double *__restrict__ x;
-    double *__restrict__ r;
-    double alpha;
-    double acc = 0.0;
-    __device__ Pre prefetch(long long o) const { return Pre{x[o], r[o]}; }
-    __device__ void finish(bool ok, long long o, double c, double nsum, Pre p) {
-        const double q = 6.0 * c - nsum;
-        const double xn = p.x + alpha * c;
-        const double rn = p.r - alpha * q;
-        if (ok) {
-            x[o] = xn;
-            r[o] = rn;
-            acc += rn * rn;
-        }
-    }
-};
-
-__global__ __launch_bounds__(kThreads) void cg_update_f64(
+template <int VEC, int WX, int BY, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void cg_update_f64(
     double *__restrict__ x, double *__restrict__ r,
     const double *__restrict__ p, double *partial, CGScalars *sc, int nx,
-    int ny, int nz) {
+    int ny, int nz, int xcd, double *sink) {
+    constexpr int NT = 64 * WX * BY;
     if (load_state(sc) != 0) return;
-    const Tile t = decode_tile(nx, ny, nz);
-    PlainField f{p};
-    UpdateEpi epi{x, r, sc->alpha};
-    box_zmarch(nx, ny, nz, t, f, epi);
+    const long long plane = (long long)nx * ny;
+    PlainField f{p, plane};
+    UpdateEpi<VEC> epi{x, r, plane, sc->alpha};
+    box_zmarch<VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
     double v[1];
-    v[0] = block_sum(epi.acc);
+    v[0] = block_sum<NT>(epi.acc);
     if (arrive(sc, partial, 1, v)) {
-        const double rho_new = gather(partial, 1, 0);
+        const double rho_new = gather<NT>(partial, 1, 0);
         if (threadIdx.x == 0) {
             sc->iter += 1;
             if (!isfinite(rho_new)) {
@@ -404,106 +576,135 @@ __global__ __launch_bounds__(kThreads) void cg_update_f64(
     }
 }
 
-struct Lap7Epi {
-    using Pre = NoPre;
-    double *__restrict__ y;
-    __device__ Pre prefetch(long long) const { return Pre{}; }
-    __device__ void finish(bool ok, long long o, double c, double nsum, Pre) {
-        if (ok) y[o] = 6.0 * c - nsum;
-    }
-};
-
-__global__ __launch_bounds__(kThreads) void lap7_f64(
+template <int VEC, int WX, int BY, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void lap7_f64(
     const double *__restrict__ x, double *__restrict__ y, int nx, int ny,
-    int nz) {
-    const Tile t = decode_tile(nx, ny, nz);
-    PlainField f{x};
-    Lap7Epi epi{y};
-    box_zmarch(nx, ny, nz, t, f, epi);
+    int nz, int xcd, double *sink) {
+    const long long plane = (long long)nx * ny;
+    PlainField f{x, plane};
+    Lap7Epi<VEC> epi{y, plane};
+    box_zmarch<VEC, WX, BY, ZB, false>(nx, ny, nz, xcd, sink, f, epi);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
-long long cg_blocks(int nx, int ny, int nz) {
-    const long long ntx = (nx + kTileX - 1) / kTileX;
-    const long long nty = (ny + kBY - 1) / kBY;
-    const long long nzb = (nz + kZDepth - 1) / kZDepth;
-    return ntx * nty * nzb;
+// Every CG tile shape the library is built with (vec, wx, by, zdepth).
+#define HC_CG_SHAPES(X)                                                          \
+    X(1, 1, 4, 16) X(1, 1, 4, 32) X(1, 4, 4, 16) X(2, 1, 4, 16) X(2, 1, 8, 16)   \
+    X(2, 2, 4, 8) X(2, 2, 4, 16) X(2, 2, 4, 32) X(2, 2, 8, 8) X(2, 2, 8, 16)     \
+    X(2, 2, 8, 32) X(2, 4, 4, 8) X(2, 4, 4, 16) X(2, 1, 16, 16)
+
+#define HC_CG_KEY(V, W, B, Z) (((V * 8 + W) * 32 + B) * 128 + Z)
+
+bool cg_tiling_supported(const CGTiling &t) {
+    const int key = HC_CG_KEY(t.vec, t.wx, t.by, t.zdepth);
+#define HC_X(V, W, B, Z) if (key == HC_CG_KEY(V, W, B, Z)) return true;
+    HC_CG_SHAPES(HC_X)
+#undef HC_X
+    return false;
 }
 
+long long cg_blocks(int nx, int ny, int nz, const CGTiling &t) {
+    const long long tx = 64LL * t.vec * t.wx;
+    return ((nx + tx - 1) / tx) * ((ny + t.by - 1) / t.by) *
+           ((nz + t.zdepth - 1) / t.zdepth);
+}
+
+// Partial sums are sized for the smallest tile built (64 x 4 x 8), so one
+// workspace serves every shape.
+static long long max_blocks(int nx, int ny, int nz) {
+    return ((nx + 63) / 64LL) * ((ny + 3) / 4LL) * ((nz + 7) / 8LL);
+}
+
+// r, p0 and p1 each carry a zero plane below and above the box (see ZPAD).
 size_t cg_work_bytes(int nx, int ny, int nz) {
-    const size_t n = (size_t)nx * ny * nz;
-    const size_t vec = align256(n * sizeof(double));
-    const size_t part = align256((size_t)cg_blocks(nx, ny, nz) * 2 * sizeof(double));
+    const size_t plane = (size_t)nx * ny;
+    const size_t vec = align256((size_t)(nz + 2) * plane * sizeof(double));
+    const size_t part = align256((size_t)max_blocks(nx, ny, nz) * 2 * sizeof(double));
     return 3 * vec + part + align256(sizeof(CGScalars));
 }
 
 CGWork cg_work_carve(void *base, int nx, int ny, int nz) {
-    const size_t n = (size_t)nx * ny * nz;
-    const size_t vec = align256(n * sizeof(double));
-    const size_t part = align256((size_t)cg_blocks(nx, ny, nz) * 2 * sizeof(double));
+    const size_t plane = (size_t)nx * ny;
+    const size_t vec = align256((size_t)(nz + 2) * plane * sizeof(double));
+    const size_t part = align256((size_t)max_blocks(nx, ny, nz) * 2 * sizeof(double));
     char *c = static_cast<char *>(base);
     CGWork w;
-    w.r = reinterpret_cast<double *>(c);
-    w.p[0] = reinterpret_cast<double *>(c + vec);
-    w.p[1] = reinterpret_cast<double *>(c + 2 * vec);
+    w.r = reinterpret_cast<double *>(c) + plane;
+    w.p[0] = reinterpret_cast<double *>(c + vec) + plane;
+    w.p[1] = reinterpret_cast<double *>(c + 2 * vec) + plane;
     w.partial = reinterpret_cast<double *>(c + 3 * vec);
     w.sc = reinterpret_cast<CGScalars *>(c + 3 * vec + part);
     return w;
 }
 
-static hipError_t grid_of(int nx, int ny, int nz, dim3 *g) {
-    const long long nb = cg_blocks(nx, ny, nz);
-    if (nb <= 0 || nb > INT_MAX) return hipErrorInvalidConfiguration;
-    *g = dim3((unsigned)nb);
-    return hipSuccess;
-}
+// Launch kernel template KER<V, W, B, Z> for the tile shape t.
+#define HC_CG_DISPATCH(KER)                                                       \
+    do {                                                                          \
+        const long long nb = cg_blocks(nx, ny, nz, t);                            \
+        if (nb <= 0 || nb > INT_MAX) return hipErrorInvalidConfiguration;         \
+        const dim3 grid((unsigned)nb), block(64 * t.wx * t.by);                   \
+        const int key = HC_CG_KEY(t.vec, t.wx, t.by, t.zdepth);                   \
+        bool done = false;                                                        \
+        HC_CG_SHAPES(HC_CG_ONE_##KER)                                             \
+        if (!done) return hipErrorInvalidValue;                                   \
+        return hipGetLastError();                                                 \
+    } while (0)
+
+#define HC_CG_ONE_RES(V, W, B, Z)                                                 \
+    if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
+        cg_residual_f64<V, W, B, Z><<<grid, block, 0, s>>>(                       \
+            b, x, store_r ? w.r : w.p[0], w.partial, w.sc, nx, ny, nz, t.xcd,     \
+            sink, store_r ? 0 : 1);                                               \
+        done = true;                                                              \
+    }
+#define HC_CG_ONE_DIR(V, W, B, Z)                                                 \
+    if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
+        cg_direction_f64<V, W, B, Z><<<grid, block, 0, s>>>(                      \
+            w.r, w.p[cur], w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd,      \
+            sink, first);                                                         \
+        done = true;                                                              \
+    }
+#define HC_CG_ONE_UPD(V, W, B, Z)                                                 \
+    if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
+        cg_update_f64<V, W, B, Z><<<grid, block, 0, s>>>(                         \
+            x, w.r, w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd, sink);      \
+        done = true;                                                              \
+    }
+#define HC_CG_ONE_LAP(V, W, B, Z)                                                 \
+    if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
+        lap7_f64<V, W, B, Z><<<grid, block, 0, s>>>(x, y, nx, ny, nz, t.xcd,      \
+                                                    sink);                        \
+        done = true;                                                              \
+    }
 
 hipError_t launch_cg_init(const CGWork &w, double tol, hipStream_t s) {
     cg_init<<<1, 64, 0, s>>>(w.sc, tol);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_residual(const double *b, const double *x,
-                              const CGWork &w, int nx, int ny, int nz,
-                              int store_r, hipStream_t s) {
-    dim3 g;
-    hipError_t e = grid_of(nx, ny, nz, &g);
-    if (e != hipSuccess) return e;
-    cg_residual_f64<<<g, kThreads, 0, s>>>(b, x, w.r, w.partial, w.sc, nx, ny,
-                                           nz, store_r ? 0 : 1);
-    return hipGetLastError();
+hipError_t launch_cg_residual(const double *b, const double *x, const CGWork &w,
+                              int nx, int ny, int nz, int store_r,
+                              const CGTiling &t, double *sink, hipStream_t s) {
+    HC_CG_DISPATCH(RES);
 }
 
 hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int nx,
-                               int ny, int nz, hipStream_t s) {
-    dim3 g;
-    hipError_t e = grid_of(nx, ny, nz, &g);
-    if (e != hipSuccess) return e;
-    cg_direction_f64<<<g, kThreads, 0, s>>>(w.r, w.p[cur], w.p[cur ^ 1],
-                                            w.partial, w.sc, nx, ny, nz, first);
-    return hipGetLastError();
+                               int ny, int nz, const CGTiling &t, double *sink,
+                               hipStream_t s) {
+    HC_CG_DISPATCH(DIR);
 }
 
-hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx,
-                            int ny, int nz, hipStream_t s) {
-    dim3 g;
-    hipError_t e = grid_of(nx, ny, nz, &g);
-    if (e != hipSuccess) return e;
-    cg_update_f64<<<g, kThreads, 0, s>>>(x, w.r, w.p[cur ^ 1], w.partial, w.sc,
-                                         nx, ny, nz);
-    return hipGetLastError();
+hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx, int ny,
+                            int nz, const CGTiling &t, double *sink, hipStream_t s) {
+    HC_CG_DISPATCH(UPD);
 }
 
 hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
-                           hipStream_t s) {
-    dim3 g;
-    hipError_t e = grid_of(nx, ny, nz, &g);
-    if (e != hipSuccess) return e;
-    lap7_f64<<<g, kThreads, 0, s>>>(x, y, nx, ny, nz);
-    return hipGetLastError();
+                           const CGTiling &t, double *sink, hipStream_t s) {
+    HC_CG_DISPATCH(LAP);
 }
 
 }  // namespace hc

@@ -35,7 +35,8 @@ struct HeatTiling {
     int by;       // rows per tile
     int zdepth;   // planes per z-block of the Interior / fused kernel
     int pf;       // planes of loads kept in flight: 1 or 2
-    int xcd;      // 1: map consecutive tiles to the same XCD
+    int xcd;      // run length of y-neighbouring tiles dealt to one XCD
+                  // (0 or 1: hardware order)
 };
 
 // Kernel kinds the launches are timed under (same values as hc_kernel_kind).
@@ -85,6 +86,8 @@ struct CGScalars {
     unsigned pad;
 };
 
+// r, p[0], p[1] point at plane 0 of vectors that carry one zero plane
+// below plane 0 and one above plane nz-1 (cleared by the driver).
 struct CGWork {
     double *r;
     double *p[2];
@@ -92,19 +95,35 @@ struct CGWork {
     CGScalars *sc;
 };
 
+// Tile shape of the CG kernels (same meaning as HeatTiling, one plane of
+// epilogue loads and two of field loads in flight).
+struct CGTiling {
+    int vec;
+    int wx;
+    int by;
+    int zdepth;
+    int xcd;
+};
+
+bool cg_tiling_supported(const CGTiling &t);
 size_t cg_work_bytes(int nx, int ny, int nz);
 // Carve a CGWork out of `base` (at least cg_work_bytes bytes).
 CGWork cg_work_carve(void *base, int nx, int ny, int nz);
-long long cg_blocks(int nx, int ny, int nz);
+long long cg_blocks(int nx, int ny, int nz, const CGTiling &t);
 hipError_t launch_cg_init(const CGWork &w, double tol, hipStream_t s);
+// `sink`: a device buffer of at least kSinkDoubles doubles that lanes outside
+// the box store into (never read).
+constexpr int kSinkDoubles = 2048;
 hipError_t launch_cg_residual(const double *b, const double *x, const CGWork &w,
-                              int nx, int ny, int nz, int store_r, hipStream_t s);
+                              int nx, int ny, int nz, int store_r,
+                              const CGTiling &t, double *sink, hipStream_t s);
 hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int nx,
-                               int ny, int nz, hipStream_t s);
+                               int ny, int nz, const CGTiling &t, double *sink,
+                               hipStream_t s);
 hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx, int ny,
-                            int nz, hipStream_t s);
+                            int nz, const CGTiling &t, double *sink, hipStream_t s);
 hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
-                           hipStream_t s);
+                           const CGTiling &t, double *sink, hipStream_t s);
 
 // ---- probes (probe.hip) ---------------------------------------------------------
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes,

@@ -6,20 +6,18 @@
 // without floating-point contraction, so every node is bit-identical to a
 // plain serial evaluation of the same expression.
 //
-// Kernel design (2.5-D z-march).  A block owns a tile of 64 (x) by BY (y)
-// nodes and walks it through a run of planes [kb, ke].  Each thread keeps
-// its column's values at k-1, k, k+1 in registers, so every stored node is
+// Kernel design (2.5-D z-march).  A block owns a tile of 64*VEC*WX (x) by
+// BY (y) nodes -- WX wavefronts per row, VEC consecutive nodes per lane --
+// and walks it through a run of planes [kb, ke].  Each thread keeps its
+// column's values at k-1, k, k+1 in registers, so every stored node is
 // loaded once per z-block; the x/y neighbours come from the current plane
-// staged in LDS with a one-node ring.  The ring's two rows are coalesced
-// 64-wide loads, its two columns are one node per row.  The next plane is
-// loaded before the current one is computed, so one plane of loads is
-// always in flight per wave.  Results are stored non-temporally: u_new is
-// not read again in this step, so it should not evict u from L2.
+// staged in LDS with a one-node ring (two coalesced rows, two columns).
+// PF planes of loads are in flight while a plane is computed.  Results are
+// stored non-temporally: u_new is not read again in this step.
 //
-// Block order is XCD-aware: the hardware deals consecutive workgroups to
-// the 8 XCDs round-robin, so the block id is remapped to make each XCD walk
-// a contiguous run of tiles (neighbouring tiles, whose halos overlap, then
-// share one L2).  Tiles are numbered x fastest, then y, then z-block.
+// Tiles are numbered y fastest, then x, then z-block, and the block ids can
+// be regrouped so that runs of y-neighbouring tiles share an XCD's L2 (see
+// block_order).
 
 #include "hc_internal.hpp"
 
@@ -28,11 +26,21 @@
 namespace hc {
 namespace {
 
-__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
-    constexpr int kXcd = 8;
-    const int xcd = bid % kXcd, slot = bid / kXcd;
-    const int per = nblk / kXcd, rem = nblk % kXcd;
-    return xcd * per + min(xcd, rem) + slot;
+// Block order.  The hardware deals workgroups to the 8 XCDs round-robin
+// (block b runs on XCD b % 8), so consecutive block ids never share an L2.
+// With xcd = G > 1 the ids are remapped in windows of 8G blocks: inside a
+// window XCD x takes the G consecutive tiles x*G .. x*G+G-1, so runs of G
+// neighbouring tiles -- whose halo rows overlap -- are read through one L2,
+// while all XCDs still work inside the same window of the array (which keeps
+// the DRAM accesses of the whole chip close together).  A last, partial
+// window keeps the hardware order.  xcd = 0 or 1: hardware order.
+__device__ __forceinline__ int block_order(int b, int nb, int g) {
+    if (g <= 1) return b;
+    const int win = 8 * g;
+    const int w = b / win;
+    if ((w + 1) * win > nb) return b;
+    const int o = b - w * win;
+    return w * win + (o & 7) * g + (o >> 3);
 }
 
 // Loads are never predicated: a node outside the array is read at a clamped
@@ -64,18 +72,21 @@ struct TileGeom {
     static constexpr int RROW = TX / VEC;      // threads per ring row
     static_assert(NT >= 2 * RROW + 2 * BY, "one thread per ring element");
     int kb, ke;
-    long long plane, own, ring;
+    long long plane, own, ring;  // ring: VEC-aligned offset of the ring load
     bool st[VEC];
     int own_slot, rslot;
     bool rvec;  // ring element is a VEC-wide row piece (else one node)
+    int rsel;   // the node's index within the aligned VEC-wide ring load
 
     __device__ __forceinline__ TileGeom(int nx, int ny, const ZTable &zt, int ntx,
                                         int nty, int xcd, int zb_full) {
-        const int L = xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-        const int tx = L % ntx;
-        const int rest = L / ntx;
-        const int ty = rest % nty;
-        const int z = rest / nty;
+        // tiles are numbered y fastest (runs of tiles share halo rows), then
+        // x, then z-block
+        const int L = block_order(blockIdx.x, gridDim.x, xcd);
+        const int ty = L % nty;
+        const int rest = L / nty;
+        const int tx = rest % ntx;
+        const int z = rest / ntx;
         int rg = 0;
         while (rg + 1 < zt.n && z >= zt.first[rg + 1]) ++rg;
         int k0 = zt.kb[rg] + (z - zt.first[rg]) * zt.depth[rg];
@@ -102,8 +113,12 @@ struct TileGeom {
 
         // ring of the LDS tile: rows j0-1 and j0+BY (VEC nodes per thread,
         // coalesced), then columns i0-1 and i0+TX (one node per thread)
+        // Every thread issues one VEC-wide aligned ring load (a column node
+        // is taken out of the aligned VEC nodes that hold it), so the load
+        // is the same instruction in every lane.
         rvec = false;
         rslot = -1;
+        rsel = 0;
         if (t < 2 * RROW) {
             const int row = t / RROW, q = t % RROW;
             const int rj = row == 0 ? j0 - 1 : min(j0 + BY, ny - 1);
@@ -113,8 +128,9 @@ struct TileGeom {
         } else if (t < 2 * RROW + 2 * BY) {
             const int q = t - 2 * RROW;
             const int row = q % BY, side = q / BY;
-            const int ri = side == 0 ? i0 - 1 : i0 + TX;
-            ring = (long long)min(j0 + row, ny - 1) * nx + max(0, min(ri, nx - 1));
+            const int ri = max(0, min(side == 0 ? i0 - 1 : i0 + TX, nx - 1));
+            rsel = ri % VEC;
+            ring = (long long)min(j0 + row, ny - 1) * nx + (ri - rsel);
             rslot = (row + 1) * LD + (side == 0 ? 0 : TX + 1);
         } else {
             ring = own;
@@ -163,14 +179,12 @@ __device__ __forceinline__ void heat_tile_sweep(const double *__restrict__ u,
     double *__restrict__ vo = un + g.own;
     const int kb = g.kb, ke = g.ke;
 
-    // ring value(s) of plane k
+    // ring value(s) of plane k: one aligned VEC-wide load in every lane
     auto ld_ring = [&](long long kp, double *o) {
-        if (VEC == 2 && g.rvec) {
-            load_vec<2>(ur + kp, o);
-        } else {
-            o[0] = ur[kp];
-            o[1] = 0.0;
-        }
+        double v[VEC];
+        load_vec<VEC>(ur + kp, v);
+        o[0] = (VEC == 2 && g.rsel) ? v[VEC - 1] : v[0];
+        o[1] = v[VEC - 1];
     };
     auto put = [&](const double *c, const double *gv) {
 #pragma unroll
@@ -338,7 +352,7 @@ long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt
     X(2, 1, 4, 2, 16) X(2, 1, 8, 1, 16) X(2, 1, 8, 2, 16) X(2, 1, 8, 2, 32)     \
     X(2, 1, 16, 2, 16) X(2, 2, 4, 2, 16) X(2, 2, 8, 1, 16) X(2, 2, 8, 2, 16)    \
     X(2, 2, 8, 2, 32) X(2, 4, 4, 1, 16) X(2, 4, 4, 2, 16)                       \
-    X(2, 4, 4, 2, 32)
+    X(2, 4, 4, 2, 32) X(2, 2, 8, 2, 64) X(2, 4, 4, 2, 64) X(2, 1, 16, 2, 32)
 
 #define HC_SHAPE_KEY(V, W, B, P, Z) ((((V * 8 + W) * 32 + B) * 4 + P) * 128 + Z)
 

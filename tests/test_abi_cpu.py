@@ -108,11 +108,21 @@ def test_tiling_knob(lib):
     assert lib.hc_heat_set_tiling(2, 4, 2, 16, 2, 0) == HC_EINVAL   # ring needs more threads
     assert lib.hc_heat_set_tiling(1, 1, 4, 48, 2, 0) == HC_EINVAL   # depth not built
     assert lib.hc_heat_set_tiling(3, 1, 4, 16, 2, 0) == HC_EINVAL
-    assert lib.hc_heat_set_tiling(1, 1, 8, 16, 2, 2) == HC_EINVAL   # xcd flag
+    assert lib.hc_heat_set_tiling(1, 1, 8, 16, 2, 65) == HC_EINVAL  # xcd run length
     assert lib.hc_heat_set_tiling(1, 4, 4, 32, 2, 1) == HC_OK
     assert hc.get_tiling() == dict(vec=1, wx=4, by=4, zdepth=32, pf=2, xcd=1)
     hc.set_tiling()
     assert hc.get_tiling() == hc.DEFAULT_TILING
+
+
+def test_cg_tiling_knob(lib):
+    assert lib.hc_cg_set_tiling(2, 4, 2, 16, 0) == HC_EINVAL
+    assert lib.hc_cg_set_tiling(2, 2, 8, 12, 0) == HC_EINVAL
+    assert lib.hc_cg_set_tiling(2, 2, 8, 16, 65) == HC_EINVAL
+    assert lib.hc_cg_set_tiling(1, 1, 4, 32, 3) == HC_OK
+    assert hc.get_cg_tiling() == dict(vec=1, wx=1, by=4, zdepth=32, xcd=3)
+    hc.set_cg_tiling()
+    assert hc.get_cg_tiling() == hc.DEFAULT_CG_TILING
 
 
 def test_binding_raises_without_tensors():

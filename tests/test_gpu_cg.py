@@ -167,3 +167,39 @@ def test_large_config_converges_to_manufactured_solution(gpu):
     b_cpu = bt.cpu().numpy()
     sub = oracle.lap7_apply(xs[:40])  # planes 0..38 only see planes 0..39
     assert np.array_equal(b_cpu[:39], sub[:39])
+
+
+def built_cg_shapes():
+    """Every CG tile shape libheatcg.so accepts (probed through the C ABI)."""
+    import paper_2608_11882_amd as hc
+    lib = hc.load()
+    shapes = []
+    for vec in (1, 2):
+        for wx in (1, 2, 4):
+            for by in (4, 8, 16):
+                for zd in (8, 16, 32):
+                    if lib.hc_cg_set_tiling(vec, wx, by, zd, 0) == 0:
+                        shapes.append((vec, wx, by, zd))
+    hc.set_cg_tiling()
+    return shapes
+
+
+def test_every_cg_shape_spmv_bitwise_and_converges(gpu):
+    shapes = built_cg_shapes()
+    assert len(shapes) >= 10
+    x1 = inputs.manufactured_solution(130, 66, 40, seed=5)
+    x2 = inputs.manufactured_solution(71, 9, 35, seed=6)   # odd width: one-node lanes
+    want1, want2 = oracle.lap7_apply(x1), oracle.lap7_apply(x2)
+    b = oracle.lap7_apply(inputs.manufactured_solution(40, 38, 36, seed=7))
+    ref = oracle.cg(b, 1e-10, 3000)
+    try:
+        for shape in shapes:
+            for xcd in (0, 3, 8):
+                note("cg shape vec,wx,by,zdepth=%s xcd=%d" % (shape, xcd))
+                gpu.set_cg_tiling(*shape, xcd=xcd)
+                assert np.array_equal(gpu_lap7(gpu, x1), want1), (shape, xcd)
+                assert np.array_equal(gpu_lap7(gpu, x2), want2), (shape, xcd)
+                st, it, rel, _ = gpu_cg(gpu, b, 1e-10, 3000)
+                assert st == 0 and rel <= 1e-10 and abs(it - ref.iters) <= 3, (shape, xcd, it)
+    finally:
+        gpu.set_cg_tiling()

@@ -102,7 +102,7 @@ def test_every_tile_shape_is_bitwise_identical(gpu):
     assert len(shapes) >= 20
     try:
         for shape in shapes:
-            for xcd in (0, 1):
+            for xcd in (0, 3, 8):
                 note("heat tiling vec,wx,by,zdepth,pf=%s xcd=%d" % (shape, xcd))
                 gpu.set_tiling(*shape, xcd=xcd)
                 for mode in ("split", "fused"):
