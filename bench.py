@@ -62,10 +62,15 @@ def cpu_baseline(u0_host, r, b_host, gpu_cg_iters, budget_s):
     import oracle
     n = u0_host.shape[0]
     lups_per_step = (n - 2) ** 3
+    # marginal cost of a step (a call also copies and allocates arrays)
     t = time.perf_counter()
     oracle.heat(u0_host, r, 1)
     one = time.perf_counter() - t
-    steps = max(1, int(0.6 * budget_s / max(one, 1e-3)))
+    t = time.perf_counter()
+    oracle.heat(u0_host, r, 4)
+    four = time.perf_counter() - t
+    per_step = max((four - one) / 3.0, 1e-3)
+    steps = max(1, int(0.6 * budget_s / per_step))
     log("cpu baseline: heat %d steps on %d^3" % (steps, n))
     t = time.perf_counter()
     oracle.heat(u0_host, r, steps)
@@ -74,7 +79,10 @@ def cpu_baseline(u0_host, r, b_host, gpu_cg_iters, budget_s):
     t = time.perf_counter()
     oracle.cg(b_host, 1e-30, 2)
     two = time.perf_counter() - t
-    iters = max(2, int(0.4 * budget_s / max(two / 2, 1e-3)))
+    t = time.perf_counter()
+    oracle.cg(b_host, 1e-30, 6)
+    six = time.perf_counter() - t
+    iters = max(2, int(0.4 * budget_s / max((six - two) / 4.0, 1e-3)))
     log("cpu baseline: cg %d iterations on %d^3" % (iters, b_host.shape[0]))
     t = time.perf_counter()
     oracle.cg(b_host, 1e-30, iters)
