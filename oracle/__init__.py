@@ -52,6 +52,14 @@ def _configure(lib):
     lib.oracle_cg.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    hp = ctypes.POINTER(ctypes.c_uint16)
+    lib.oracle_heat_f32.argtypes = [fp, L, L, L, ctypes.c_float, L]
+    lib.oracle_heat_f32.restype = ctypes.c_int
+    lib.oracle_heat_bf16.argtypes = [hp, L, L, L, ctypes.c_float, L]
+    lib.oracle_heat_bf16.restype = ctypes.c_int
+    lib.oracle_bf16_round_array.argtypes = [fp, hp, L]
+    lib.oracle_bf16_round_array.restype = None
     return lib
 
 
@@ -122,6 +130,46 @@ def heat(u0: np.ndarray, r: float, steps: int) -> np.ndarray:
     if rc != 0:
         raise MemoryError("oracle_heat_f64 returned %d" % rc)
     return u
+
+
+def heat_f32(u0: np.ndarray, r: float, steps: int) -> np.ndarray:
+    """The explicit step in binary32 throughout (r rounded to binary32)."""
+    u = np.ascontiguousarray(u0, dtype=np.float32).copy()
+    if u.ndim != 3:
+        raise ValueError("expected a 3-D (nz, ny, nx) array")
+    nz, ny, nx = u.shape
+    rc = _load().oracle_heat_f32(u.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                 nx, ny, nz, float(np.float32(r)), int(steps))
+    if rc != 0:
+        raise MemoryError("oracle_heat_f32 returned %d" % rc)
+    return u
+
+
+def heat_bf16(u0_bits: np.ndarray, r: float, steps: int) -> np.ndarray:
+    """bfloat16 storage (uint16 bit patterns), binary32 arithmetic."""
+    u = np.ascontiguousarray(u0_bits, dtype=np.uint16).copy()
+    if u.ndim != 3:
+        raise ValueError("expected a 3-D (nz, ny, nx) array")
+    nz, ny, nx = u.shape
+    rc = _load().oracle_heat_bf16(u.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                  nx, ny, nz, float(np.float32(r)), int(steps))
+    if rc != 0:
+        raise MemoryError("oracle_heat_bf16 returned %d" % rc)
+    return u
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """binary32 -> bfloat16 bit patterns, round to nearest, ties to even."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty(x.shape, dtype=np.uint16)
+    _load().oracle_bf16_round_array(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)), x.size)
+    return out
+
+
+def bf16_widen(bits: np.ndarray) -> np.ndarray:
+    """bfloat16 bit patterns -> binary32 (exact)."""
+    return (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
 
 
 def lap7_apply(x: np.ndarray) -> np.ndarray:

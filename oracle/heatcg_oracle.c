@@ -18,6 +18,7 @@
  */
 #include <math.h>
 #include <omp.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -85,6 +86,134 @@ int oracle_heat_f64(double *u, long nx, long ny, long nz, double r, long steps)
     }
     if (a != u)
         memcpy(u, a, (size_t)n * sizeof(double));
+    free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Heat equation in lower precision (not in the paper, which works in FP64)  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The same step in single precision: every value and every operation is
+ * binary32 (x86-64 SSE arithmetic, no excess precision, no contraction), in
+ * the order of the FP64 step, with r rounded to binary32 once.
+ */
+void oracle_heat_sweep_f32(const float *u, float *un, long nx, long ny,
+                           long nz, float r)
+{
+    const long sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 1; k < nz - 1; ++k)
+        for (long j = 1; j < ny - 1; ++j)
+            for (long i = 1; i < nx - 1; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const float c = u[p];
+                const float nsum = ((u[p - sx] + u[p + sx]) +
+                                    (u[p - sy] + u[p + sy])) +
+                                   (u[p - sz] + u[p + sz]);
+                const float lap = nsum - 6.0f * c;
+                un[p] = c + r * lap;
+            }
+}
+
+int oracle_heat_f32(float *u, long nx, long ny, long nz, float r, long steps)
+{
+    const long n = nx * ny * nz;
+    if (steps <= 0)
+        return 0;
+    float *w = (float *)malloc((size_t)n * sizeof(float));
+    if (!w)
+        return -4;
+    memcpy(w, u, (size_t)n * sizeof(float));
+    float *a = u, *b = w;
+    for (long s = 0; s < steps; ++s) {
+        oracle_heat_sweep_f32(a, b, nx, ny, nz, r);
+        float *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != u)
+        memcpy(u, a, (size_t)n * sizeof(float));
+    free(w);
+    return 0;
+}
+
+/*
+ * bfloat16: the upper 16 bits of a binary32 (sign, 8-bit exponent, 7
+ * stored significand bits).  Widening is exact.  Narrowing rounds to the
+ * nearest bfloat16, ties to the even significand; NaN stays a quiet NaN.
+ */
+float oracle_f32_from_bf16(uint16_t h)
+{
+    const uint32_t bits = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &bits, sizeof f);
+    return f;
+}
+
+uint16_t oracle_bf16_from_f32(float f)
+{
+    uint32_t bits;
+    memcpy(&bits, &f, sizeof bits);
+    if ((bits & 0x7fffffffu) > 0x7f800000u)      /* NaN */
+        return (uint16_t)((bits >> 16) | 0x0040u);
+    const uint32_t upper = bits >> 16;
+    const uint32_t lower = bits & 0xffffu;
+    uint32_t out = upper;
+    if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u)))
+        out = upper + 1u;                        /* carries into the exponent */
+    return (uint16_t)out;
+}
+
+void oracle_bf16_round_array(const float *in, uint16_t *out, long n)
+{
+    for (long q = 0; q < n; ++q)
+        out[q] = oracle_bf16_from_f32(in[q]);
+}
+
+/*
+ * One step with bfloat16 storage and binary32 arithmetic: the stored values
+ * are widened, the binary32 step above is applied, and the new value is
+ * rounded to bfloat16 (round to nearest, ties to even).
+ */
+void oracle_heat_sweep_bf16(const uint16_t *u, uint16_t *un, long nx, long ny,
+                            long nz, float r)
+{
+    const long sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 1; k < nz - 1; ++k)
+        for (long j = 1; j < ny - 1; ++j)
+            for (long i = 1; i < nx - 1; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const float c = oracle_f32_from_bf16(u[p]);
+                const float nsum =
+                    ((oracle_f32_from_bf16(u[p - sx]) + oracle_f32_from_bf16(u[p + sx])) +
+                     (oracle_f32_from_bf16(u[p - sy]) + oracle_f32_from_bf16(u[p + sy]))) +
+                    (oracle_f32_from_bf16(u[p - sz]) + oracle_f32_from_bf16(u[p + sz]));
+                const float lap = nsum - 6.0f * c;
+                un[p] = oracle_bf16_from_f32(c + r * lap);
+            }
+}
+
+int oracle_heat_bf16(uint16_t *u, long nx, long ny, long nz, float r, long steps)
+{
+    const long n = nx * ny * nz;
+    if (steps <= 0)
+        return 0;
+    uint16_t *w = (uint16_t *)malloc((size_t)n * sizeof(uint16_t));
+    if (!w)
+        return -4;
+    memcpy(w, u, (size_t)n * sizeof(uint16_t));
+    uint16_t *a = u, *b = w;
+    for (long s = 0; s < steps; ++s) {
+        oracle_heat_sweep_bf16(a, b, nx, ny, nz, r);
+        uint16_t *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != u)
+        memcpy(u, a, (size_t)n * sizeof(uint16_t));
     free(w);
     return 0;
 }

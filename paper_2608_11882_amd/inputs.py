@@ -113,6 +113,51 @@ def batched_fields(dims, rng, dtype=np.float32):
     return out
 
 
+def to_bf16_bits(x) -> np.ndarray:
+    """bfloat16 bit patterns (uint16) of float64 values, rounded once to the
+    nearest bfloat16 with ties to even (no double rounding through binary32).
+    Values must be finite and inside the bfloat16 normal range, or zero."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    b = x.view(np.uint64)
+    sign = (b >> np.uint64(63)).astype(np.uint32)
+    exp = ((b >> np.uint64(52)) & np.uint64(0x7FF)).astype(np.int64)
+    man = b & np.uint64((1 << 52) - 1)
+    keep = (man >> np.uint64(45)).astype(np.int64)          # 7 stored bits
+    rest = man & np.uint64((1 << 45) - 1)
+    half = np.uint64(1 << 44)
+    up = (rest > half) | ((rest == half) & ((keep & 1) == 1))
+    keep = keep + up.astype(np.int64)
+    exp = exp + (keep >> 7)
+    keep = keep & 0x7F
+    zero = (x == 0.0)
+    e8 = exp - 1023 + 127
+    if np.any(~zero & ((e8 < 1) | (e8 > 254))):
+        raise ValueError("value outside the bfloat16 normal range")
+    bits = (sign << 15) | (np.where(zero, 0, e8).astype(np.uint32) << 7) | \
+        np.where(zero, 0, keep).astype(np.uint32)
+    return bits.astype(np.uint16)
+
+
+def sine_field_lowp(nx: int, ny: int, nz: int, noise: float, seed: int, dtype: str):
+    """sine_field(..., noise, seed) rounded once from float64 to "f32" or
+    "bf16" (bfloat16 returned as uint16 bit patterns), plane by plane."""
+    if dtype not in ("f32", "bf16"):
+        raise ValueError(dtype)
+    _check_dims(nx, ny, nz)
+    sx = np.sin(np.pi * node_coords(nx))
+    sy = np.sin(np.pi * node_coords(ny))
+    sz = np.sin(np.pi * node_coords(nz))
+    rng = np.random.default_rng(seed)
+    out = np.zeros((nz, ny, nx), dtype=np.float32 if dtype == "f32" else np.uint16)
+    syx = sy[1:-1, None] * sx[None, 1:-1]
+    for k in range(1, nz - 1):
+        plane = sz[k] * syx
+        if noise:
+            plane = plane + rng.uniform(-noise, noise, size=(ny - 2, nx - 2))
+        out[k, 1:-1, 1:-1] = plane.astype(np.float32) if dtype == "f32" else to_bf16_bits(plane)
+    return out
+
+
 # --- the configurations the library is measured and tested on -------------
 
 def heat_small_f64(seed: int = 1, n: int = 66) -> np.ndarray:

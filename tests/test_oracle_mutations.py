@@ -11,6 +11,7 @@ import pytest
 import oracle
 import test_oracle_cg as cg_pins
 import test_oracle_heat as heat_pins
+import test_oracle_precision as prec_pins
 
 HEAT_PINS = [
     lambda: heat_pins.test_single_sine_mode_decays_by_exact_factor((13, 9, 7), (2, 3, 1), 0.16, 15),
@@ -25,10 +26,25 @@ CG_PINS = [
     cg_pins.test_errors_decrease_monotonically_in_a_norm_and_2_norm,
 ]
 
+PREC_PINS = [
+    prec_pins.test_bf16_rounding_matches_exact_ties_to_even,
+    prec_pins.test_bf16_step_is_exact_when_the_result_is_representable,
+    lambda: prec_pins.test_f32_step_error_against_f64_oracle_within_bound(7),
+    prec_pins.test_f32_sine_mode_decays_within_single_precision,
+    prec_pins.test_bf16_error_against_f64_within_bound_and_stagnation,
+]
+
 MUTATIONS = {
+    "bf16_ties_away": ("if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u)))", "if (lower >= 0x8000u)", PREC_PINS),
+    "bf16_truncates": ("out = upper + 1u;", "out = upper;", PREC_PINS),
+    "f32_dropped_weight": ("const float lap = nsum - 6.0f * c;\n                un[p] = c + r * lap;",
+                           "const float lap = nsum - 5.0f * c;\n                un[p] = c + r * lap;", PREC_PINS),
+    "bf16_step_sign": ("un[p] = oracle_bf16_from_f32(c + r * lap);", "un[p] = oracle_bf16_from_f32(c - r * lap);", PREC_PINS),
     "dropped_neighbour_weight": ("const double lap = nsum - 6.0 * c;", "const double lap = nsum - 4.0 * c;", HEAT_PINS),
-    "sign_of_update": ("un[p] = c + r * lap;", "un[p] = c - r * lap;", HEAT_PINS),
-    "x_stride_for_y": ("((u[p - sx] + u[p + sx]) +", "((u[p - sy] + u[p + sx]) +", HEAT_PINS),
+    "sign_of_update": ("const double lap = nsum - 6.0 * c;\n                un[p] = c + r * lap;",
+                       "const double lap = nsum - 6.0 * c;\n                un[p] = c - r * lap;", HEAT_PINS),
+    "x_stride_for_y": ("const double nsum = ((u[p - sx] + u[p + sx]) +",
+                       "const double nsum = ((u[p - sy] + u[p + sx]) +", HEAT_PINS),
     "skipped_last_row": ("for (long j = 1; j < ny - 1; ++j)\n            for (long i = 1; i < nx - 1; ++i) {\n                const long p = IDX(i, j, k, nx, ny);\n                const double c = u[p];",
                          "for (long j = 1; j < ny - 2; ++j)\n            for (long i = 1; i < nx - 1; ++i) {\n                const long p = IDX(i, j, k, nx, ny);\n                const double c = u[p];", HEAT_PINS),
     "operator_sign": ("y[p] = 6.0 * x[p] - nsum;", "y[p] = 6.0 * x[p] + nsum;", CG_PINS),

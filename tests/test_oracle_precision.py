@@ -1,0 +1,129 @@
+"""Pins for the oracle's binary32 and bfloat16 heat steps and for the
+bfloat16 rounding used on both input preparation and storage.
+
+References: exact rational arithmetic (fractions) for the rounding rules and
+for a step whose result is exactly representable; the FP64 oracle (itself
+pinned to closed forms) with the rounding-error bound of a contractive
+scheme; the exact decay of a sine mode.
+"""
+import fractions
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_11882_amd import inputs
+
+U32 = 2.0 ** -24   # binary32 unit roundoff
+UBF = 2.0 ** -8    # bfloat16 unit roundoff
+
+
+def exact_bf16(q):
+    """Nearest bfloat16 to the rational q (ties to even), as a Fraction."""
+    if q == 0:
+        return fractions.Fraction(0)
+    sign = -1 if q < 0 else 1
+    a = abs(q)
+    e = math.floor(math.log2(a))
+    if fractions.Fraction(2) ** e > a:
+        e -= 1
+    if fractions.Fraction(2) ** (e + 1) <= a:
+        e += 1
+    ulp = fractions.Fraction(2) ** (e - 7)
+    m = a / ulp
+    lo = math.floor(m)
+    rem = m - lo
+    if rem > fractions.Fraction(1, 2) or (rem == fractions.Fraction(1, 2) and lo % 2 == 1):
+        lo += 1
+    return sign * lo * ulp
+
+
+def test_bf16_rounding_matches_exact_ties_to_even():
+    rng = np.random.default_rng(1)
+    vals = list(rng.uniform(-4, 4, size=3000).astype(np.float32))
+    # ties between neighbouring bfloat16 values, both parities, and extremes
+    for m in range(128, 256):
+        for e in (-20, -1, 0, 5, 100):
+            vals.append(np.float32((m + 0.5) * 2.0 ** (e - 7)))
+            vals.append(np.float32(-(m + 0.5) * 2.0 ** (e - 7)))
+    vals += [np.float32(1e-30), np.float32(3.0e38), np.float32(1.0), np.float32(0.0)]
+    x = np.array(vals, dtype=np.float32)
+    got = oracle.bf16_widen(oracle.bf16_round(x))
+    for xi, gi in zip(x, got):
+        assert fractions.Fraction(float(gi)) == exact_bf16(fractions.Fraction(float(xi))), xi
+
+
+def test_input_rounding_from_f64_is_single_rounding():
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-3, 3, size=2000)
+    # values just off a bfloat16 tie: rounding through binary32 first would err
+    ties = np.array([1.0 + 2.0 ** -8 + 2.0 ** -30, 1.0 + 2.0 ** -8 - 2.0 ** -30,
+                     1.0 + 3 * 2.0 ** -8 + 2.0 ** -40, 0.0])
+    x = np.concatenate([x, ties])
+    got = oracle.bf16_widen(inputs.to_bf16_bits(x))
+    for xi, gi in zip(x, got):
+        assert fractions.Fraction(float(gi)) == exact_bf16(fractions.Fraction(float(xi)))
+
+
+def test_bf16_step_is_exact_when_the_result_is_representable():
+    """Values k/8 in [-2, 2] with r = 1/8: one step lands on multiples of
+    1/64 of magnitude below 4, all exact in bfloat16 and binary32."""
+    rng = np.random.default_rng(3)
+    nx, ny, nz = 9, 8, 7
+    k = rng.integers(-16, 17, size=(nz, ny, nx))
+    u0 = k / 8.0
+    got = oracle.bf16_widen(oracle.heat_bf16(inputs.to_bf16_bits(u0), 0.125, 1)).astype(np.float64)
+    want = u0.copy()
+    F = fractions.Fraction
+    for kk in range(1, nz - 1):
+        for j in range(1, ny - 1):
+            for i in range(1, nx - 1):
+                c = F(int(k[kk, j, i]), 8)
+                s = sum(F(int(k[kk + dz, j + dy, i + dx]), 8)
+                        for dz, dy, dx in ((0, 0, -1), (0, 0, 1), (0, -1, 0), (0, 1, 0), (-1, 0, 0), (1, 0, 0)))
+                want[kk, j, i] = float(exact_bf16(c + F(1, 8) * (s - 6 * c)))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("steps", [1, 7, 40])
+def test_f32_step_error_against_f64_oracle_within_bound(steps):
+    nx, ny, nz = 23, 17, 19
+    u0 = inputs.uniform_field(nx, ny, nz, seed=steps, lo=-1.0, hi=1.0)
+    r = 0.15
+    ref = oracle.heat(u0.astype(np.float32).astype(np.float64), float(np.float32(r)), steps)
+    got = oracle.heat_f32(u0.astype(np.float32), r, steps).astype(np.float64)
+    err = np.max(np.abs(got - ref))
+    assert 0.0 < err <= steps * 8 * U32 * np.max(np.abs(u0))
+
+
+def test_f32_sine_mode_decays_within_single_precision():
+    n, r, steps = 34, 0.1, 60
+    u0 = inputs.sine_field(n, n, n)
+    g = 1.0 - 12.0 * float(np.float32(r)) * np.sin(np.pi / (2.0 * (n - 1))) ** 2
+    got = oracle.heat_f32(u0.astype(np.float32), r, steps).astype(np.float64)
+    assert np.max(np.abs(got - g ** steps * u0)) <= steps * 8 * U32
+
+
+def test_f32_oracle_really_rounds_to_single_precision():
+    u0 = inputs.uniform_field(12, 11, 10, seed=4, lo=0.1, hi=1.0)
+    f32 = oracle.heat_f32(u0.astype(np.float32), 0.13, 5)
+    f64 = oracle.heat(u0.astype(np.float32).astype(np.float64), float(np.float32(0.13)), 5)
+    assert not np.array_equal(f32.astype(np.float64), f64)
+    assert np.array_equal(f32.astype(np.float64), f32.astype(np.float64).astype(np.float32))
+
+
+def test_bf16_error_against_f64_within_bound_and_stagnation():
+    nx, ny, nz = 20, 18, 16
+    u0 = inputs.uniform_field(nx, ny, nz, seed=9)
+    bits = inputs.to_bf16_bits(u0)
+    start = oracle.bf16_widen(bits).astype(np.float64)
+    steps, r = 20, 0.14
+    got = oracle.bf16_widen(oracle.heat_bf16(bits, r, steps)).astype(np.float64)
+    ref = oracle.heat(start, float(np.float32(r)), steps)
+    assert np.max(np.abs(got - ref)) <= steps * UBF * np.max(np.abs(u0))
+    # round to nearest: a change below half a bfloat16 ulp per step is lost,
+    # so a slowly decaying smooth field does not move at all
+    n = 34
+    smooth = inputs.to_bf16_bits(inputs.sine_field(n, n, n) * 0.9)
+    assert np.array_equal(oracle.heat_bf16(smooth, 0.001, 50), smooth)
