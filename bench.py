@@ -62,44 +62,171 @@ def cpu_baseline(u0_host, r, b_host, gpu_cg_iters, budget_s):
     import oracle
     n = u0_host.shape[0]
     lups_per_step = (n - 2) ** 3
-    # marginal cost of a step (a call also copies and allocates arrays)
-    t = time.perf_counter()
+    # a call also copies and allocates its arrays, so rates are marginal:
+    # the time of an s-step call minus that of a 2-step call, over s - 2
+    def timed(fn, *a):
+        t = time.perf_counter()
+        fn(*a)
+        return time.perf_counter() - t
+
     oracle.heat(u0_host, r, 1)
-    one = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.heat(u0_host, r, 4)
-    four = time.perf_counter() - t
-    per_step = max((four - one) / 3.0, 1e-3)
-    steps = max(1, int(0.6 * budget_s / per_step))
+    t2 = timed(oracle.heat, u0_host, r, 2)
+    t6 = timed(oracle.heat, u0_host, r, 6)
+    per_step = max((t6 - t2) / 4.0, t2 / 50.0)
+    steps = max(6, int(0.6 * budget_s / per_step))
     log("cpu baseline: heat %d steps on %d^3" % (steps, n))
-    t = time.perf_counter()
-    oracle.heat(u0_host, r, steps)
-    heat_s = time.perf_counter() - t
-    glups = steps * lups_per_step / heat_s / 1e9
-    t = time.perf_counter()
-    oracle.cg(b_host, 1e-30, 2)
-    two = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.cg(b_host, 1e-30, 6)
-    six = time.perf_counter() - t
-    iters = max(2, int(0.4 * budget_s / max((six - two) / 4.0, 1e-3)))
+    heat_s = timed(oracle.heat, u0_host, r, steps)
+    glups = (steps - 2) * lups_per_step / max(heat_s - t2, 1e-9) / 1e9
+    oracle.cg(b_host, 1e-30, 1)
+    c1 = timed(oracle.cg, b_host, 1e-30, 1)
+    c3 = timed(oracle.cg, b_host, 1e-30, 3)
+    per_it = max((c3 - c1) / 2.0, c1 / 20.0)
+    iters = max(3, int(0.4 * budget_s / per_it))
     log("cpu baseline: cg %d iterations on %d^3" % (iters, b_host.shape[0]))
-    t = time.perf_counter()
-    oracle.cg(b_host, 1e-30, iters)
-    cg_s = time.perf_counter() - t
-    per_it = cg_s / iters
+    cg_s = timed(oracle.cg, b_host, 1e-30, iters)
+    per_it = max(cg_s - c1, 1e-9) / (iters - 1)
     return {
         "value": glups,
         "unit": "GLUP/s",
         "cores": oracle.threads(),
         "kind": "oracle",
-        "sample": ("heat: %d of the 1000 steps on the same 512^3 FP64 field (%.3g LUP, %.1f s); "
-                   "cg: %d iterations on the same 256^3 system (%.1f s, %.3f s/iteration, "
-                   "so about %.0f s for the GPU's %d iterations to 1e-10)"
+        "sample": ("heat: %d steps (the workload runs 1000) on the same 512^3 FP64 field "
+                   "(%.3g LUP, %.1f s; rate net of the call's fixed cost, taken as the time "
+                   "of a 2-step call); cg: %d iterations on the same 256^3 system (%.1f s, "
+                   "%.3f s/iteration net of a 1-iteration call, so about %.0f s for the "
+                   "GPU's %d iterations to 1e-10)"
                    % (steps, steps * lups_per_step, heat_s, iters, cg_s, per_it,
                       per_it * gpu_cg_iters, gpu_cg_iters)),
         "cg_s_per_iteration": per_it,
     }
+
+
+def to_bf16_device(u64_host, dev):
+    """bfloat16 copy (torch.bfloat16, same bits) of a float64 host field,
+    rounded once per node, converted in chunks of planes."""
+    import numpy as np
+    import torch
+    from paper_2608_11882_amd import inputs
+    out = torch.empty(u64_host.shape, dtype=torch.bfloat16, device=dev)
+    for k0 in range(0, u64_host.shape[0], 64):
+        bits = inputs.to_bf16_bits(u64_host[k0:k0 + 64]).view(np.int16)
+        out[k0:k0 + 64].view(torch.int16).copy_(torch.from_numpy(bits))
+    return out
+
+
+def field_errors(got, ref):
+    """max |got - ref| and ||got - ref||_2 / ||ref||_2, in float64, by chunks
+    of planes (both on the device)."""
+    emax, e2, r2 = 0.0, 0.0, 0.0
+    for k0 in range(0, got.shape[0], 64):
+        g = got[k0:k0 + 64].double()
+        rf = ref[k0:k0 + 64].double()
+        d = g - rf
+        emax = max(emax, d.abs().max().item())
+        e2 += (d * d).sum().item()
+        r2 += (rf * rf).sum().item()
+    return emax, (e2 / r2) ** 0.5 if r2 > 0 else 0.0
+
+
+def timed_sweep(hc, u, un, u0, r, steps):
+    """Milliseconds of heat_step(u, un, r, steps) started from u0."""
+    import torch
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hc.heat_step(u, un, r, steps, mode="split")
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
+    """Reduced-precision sweeps, outside the timed region:
+    * 512^3: the same field and steps as the headline in binary32 (and
+      bfloat16 storage), GLUP/s and algorithmic GB/s beside FP64's;
+    * 1024^3, r = 0.15, 500 steps, sine mode + U[-1e-3, 1e-3] (seed 3):
+      binary32 and bfloat16-storage rates, and their max and relative-L2
+      errors against the FP64 path on the full grid (the FP64 kernels are
+      bit-identical to the oracle wherever the tests compare them) and
+      against the FP64 oracle itself on a 256^3 instance of the same recipe."""
+    import numpy as np
+    import torch
+    from paper_2608_11882_amd import inputs
+    out = {}
+    n = u_init64.shape[0]
+    lups = nsteps_large * (n - 2) ** 3
+    rate = {}
+    for name, u0 in (("f64", u_init64), ("f32", u_init64.float()),
+                     ("bf16", u_init64.to(torch.float32).to(torch.bfloat16))):
+        # (the bfloat16 rate does not depend on how the field was rounded)
+        u, un = torch.empty_like(u0), torch.empty_like(u0)
+        timed_sweep(hc, u, un, u0, r_large, 10)
+        ms = timed_sweep(hc, u, un, u0, r_large, nsteps_large)
+        eb = u0.element_size()
+        rate[name] = {"tiling": hc.tiling_for(u, un),
+                      "glups": round(lups / (ms / 1e3) / 1e9, 2),
+                      "algo_hbm_gbs": round(nsteps_large * eb * (n ** 3 + (n - 2) ** 3)
+                                            / (ms / 1e3) / 1e9, 1)}
+        del u, un, u0
+    out["heat_512_rates"] = rate
+    log("precision: 512^3 rates %s" % rate)
+
+    cfg = inputs.HEAT_PRECISION
+    N, r, steps, seed = cfg["n"], cfg["r"], cfg["steps"], cfg["seed"]
+    log("precision: %d^3 inputs" % N)
+    u64h = inputs.sine_field(N, N, N, noise=1e-3, seed=seed)
+    lups = steps * (N - 2) ** 3
+    res = {}
+    ref = None
+    for name in ("f64", "f32", "bf16"):
+        if name == "f64":
+            u0 = torch.from_numpy(u64h).to(dev)
+        elif name == "f32":
+            u0 = torch.from_numpy(u64h).to(dev).float()   # one rounding, to nearest even
+        else:
+            u0 = to_bf16_device(u64h, dev)
+        u, un = torch.empty_like(u0), torch.empty_like(u0)
+        timed_sweep(hc, u, un, u0, r, 5)
+        ms = timed_sweep(hc, u, un, u0, r, steps)
+        eb = u0.element_size()
+        rec = {"tiling": hc.tiling_for(u, un),
+               "glups": round(lups / (ms / 1e3) / 1e9, 2),
+               "algo_hbm_gbs": round(steps * eb * (N ** 3 + (N - 2) ** 3) / (ms / 1e3) / 1e9, 1),
+               "ms": round(ms, 2)}
+        del un, u0
+        if name == "f64":
+            ref = u
+        else:
+            emax, el2 = field_errors(u, ref)
+            rec["max_err_vs_f64_full_grid"] = emax
+            rec["rel_l2_err_vs_f64_full_grid"] = el2
+            del u
+        res[name] = rec
+        torch.cuda.empty_cache()
+    del ref
+    torch.cuda.empty_cache()
+    res["grid"] = [N, N, N]
+    res["r"] = r
+    res["steps"] = steps
+    if with_oracle:
+        import oracle
+        m = 256
+        log("precision: FP64 oracle on %d^3, %d steps" % (m, steps))
+        s64 = inputs.sine_field(m, m, m, noise=1e-3, seed=seed)
+        want = torch.from_numpy(oracle.heat(s64, r, steps)).to(dev)
+        sub = {}
+        for name in ("f32", "bf16"):
+            u0 = (torch.from_numpy(s64).to(dev).float() if name == "f32"
+                  else to_bf16_device(s64, dev))
+            u, un = torch.empty_like(u0), torch.empty_like(u0)
+            timed_sweep(hc, u, un, u0, r, steps)
+            emax, el2 = field_errors(u, want)
+            sub[name] = {"max_err": emax, "rel_l2_err": el2}
+        sub["max_abs_u"] = float(want.abs().max().item())
+        res["vs_oracle_256"] = sub
+    out["heat_1024_precision"] = res
+    return out
 
 
 def main():
@@ -110,6 +237,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline (0 skips it)")
     ap.add_argument("--heat-steps", type=int, default=1000, help=argparse.SUPPRESS)
+    ap.add_argument("--precision", type=int, default=1, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
@@ -217,12 +345,16 @@ def main():
         torch.cuda.synchronize()
         variants[mode] = round(100 * (n - 2) ** 3 / (e0.elapsed_time(e1) / 1e3) / 1e9, 2)
 
+    prec = None
+    if args.precision:
+        prec = precision_section(hc, dev, u_init, r, nsteps, args.cpu_seconds > 0)
+
     cpu = None
     if args.cpu_seconds > 0:
         b_host = b.cpu().numpy()
         cpu = cpu_baseline(u0_host, r, b_host, cg_iters, args.cpu_seconds)
 
-    tiling = hc.get_tiling()
+    tiling = hc.tiling_for(u, un)
     out = {
         "metric": METRIC,
         "value": round(glups, 3),
@@ -266,6 +398,7 @@ def main():
             "direction_kernel_avg_us": round(1e3 * cga_ms / max(cga_n, 1), 2),
             "update_kernel_avg_us": round(1e3 * cgb_ms / max(cgb_n, 1), 2),
         },
+        "precision": prec,
         "copy_probe_gbs": round(copy_gbs, 1),
         "roofline": {
             "kernel": "heat_interior_f64",

@@ -88,8 +88,16 @@ int heat_step(double *u, double *u_new, int nx, int ny, int nz, double r,
  * and stream chosen by the caller.  Enqueues the work on `stream` and
  * returns without waiting (stream order is the only ordering).
  *
- *  dtype  HC_F64 (the paper's precision).  Other values are reserved and
- *         return HC_EINVAL.
+ *  dtype  element type of u and u_new:
+ *           HC_F64  binary64 storage and arithmetic (the paper's precision);
+ *           HC_F32  binary32 storage and arithmetic;
+ *           HC_BF16 bfloat16 storage (uint16 bit patterns, the upper half
+ *                   of a binary32) with binary32 arithmetic: each node is
+ *                   widened exactly, updated in binary32 in the order above,
+ *                   and rounded to the nearest bfloat16, ties to even (NaN
+ *                   stays NaN).  r is rounded to binary32 for both reduced
+ *                   precisions.
+ *         Sizes and alignment rules are in elements of that type.
  *  mode   an hc_heat_mode.
  *  parts  number of equal k-slabs the split form treats as separate
  *         subdomains (the paper's decomposition along k, Methodology): the
@@ -163,13 +171,14 @@ int hc_lap7_apply(const double *x, double *y, int nx, int ny, int nz,
 int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream);
 
 /*
- * Tile shape of the z-marching heat kernels, for the whole process (the
- * knob an autotuner turns; results do not depend on it, bit for bit).  A
- * block covers 64*vec*wx nodes along x by `by` rows and walks `zdepth`
- * planes along z.
- *  vec     nodes per lane along x: 1, or 2 (16-byte accesses; used only when
- *          nx is even and both arrays are 16-byte aligned, else a one-node
- *          shape of the same depth is used)
+ * Tile shape of the z-marching heat kernels for element type `dtype` (an
+ * hc_dtype), for the whole process (the knob an autotuner turns; results
+ * do not depend on it, bit for bit).  A block covers 64*vec*wx nodes along
+ * x by `by` rows and walks `zdepth` planes along z.
+ *  vec     nodes per lane along x: 1, 2 (FP64), 4 (FP32) or 8 (bfloat16);
+ *          a lane of vec > 1 nodes is one access of vec elements, used only
+ *          when nx is a multiple of vec and both arrays are aligned to
+ *          vec elements, else the shape (1, 4, 4, 16, 2) is used
  *  wx      wavefronts per tile row
  *  by      rows per tile
  *  zdepth  planes per z-block
@@ -177,12 +186,29 @@ int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream);
  *  xcd     0..64: runs of this many y-neighbouring tiles are dealt to one
  *          XCD (so their shared halo rows are read through one L2); 0 or 1
  *          keeps the hardware order
- * The shapes built are listed in heat_kernels.hip (HC_HEAT_SHAPES); others
- * return HC_EINVAL.  Default: vec 2, wx 4, by 4, zdepth 32, pf 2, xcd 8.
+ * The shapes built per element type are listed in heat_kernels.hip
+ * (HC_HEAT_SHAPES_F64/_F32/_BF16); others, and an unknown dtype, return
+ * HC_EINVAL.  All six values zero select the automatic choice (the
+ * default): per call, the widest of a short list of measured shapes whose
+ * row of tiles is at most 1/8 wider than nx needs.  hc_heat_get_tiling
+ * writes the setting (zeros for automatic) through the non-NULL pointers.
  */
-int hc_heat_set_tiling(int vec, int wx, int by, int zdepth, int pf, int xcd);
-void hc_heat_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *pf,
-                        int *xcd);
+int hc_heat_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int pf,
+                       int xcd);
+int hc_heat_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth,
+                       int *pf, int *xcd);
+
+/*
+ * The tile shape heat_step_ex would run an array of x-edge nx and element
+ * type dtype with, for the arrays u and u_new (only their addresses are
+ * used, for the lane alignment; NULL counts as aligned): the setting above
+ * or the automatic choice, then the one-node shape (1, 4, 4, 16, 2) where
+ * vec nodes per lane do not fit.  Written through the non-NULL pointers.
+ * HC_EINVAL for an unknown dtype or nx < 3.
+ */
+int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new,
+                       int *vec, int *wx, int *by, int *zdepth, int *pf,
+                       int *xcd);
 
 /*
  * Tile shape of the CG kernels (and hc_lap7_apply), for the whole process;

@@ -15,7 +15,8 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "cg_solve"
            "cg_workspace_bytes", "lap7_apply", "copy_probe", "prof_enable",
            "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV", "set_tiling",
            "get_tiling", "DEFAULT_TILING", "set_cg_tiling", "get_cg_tiling",
-           "DEFAULT_CG_TILING"]
+           "DEFAULT_CG_TILING", "DTYPES", "HC_F64", "HC_F32", "HC_BF16",
+           "AUTO_TILING", "tiling_for"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -65,8 +66,9 @@ def load():
         "hc_last_error_message": (ctypes.c_char_p, []),
         "hc_prof_enable": (i, [i]),
         "hc_prof_read": (i, [i, dp, llp, dp]),
-        "hc_heat_set_tiling": (i, [i, i, i, i, i, i]),
-        "hc_heat_get_tiling": (None, [ip, ip, ip, ip, ip, ip]),
+        "hc_heat_set_tiling": (i, [i, i, i, i, i, i, i]),
+        "hc_heat_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
+        "hc_heat_tiling_for": (i, [i, i, vp, vp, ip, ip, ip, ip, ip, ip]),
         "hc_cg_set_tiling": (i, [i, i, i, i, i]),
         "hc_cg_get_tiling": (None, [ip, ip, ip, ip, ip]),
     }
@@ -186,19 +188,44 @@ def copy_probe(src, dst, stream=None) -> None:
                                 nbytes, _stream_handle(src, stream)))
 
 
-DEFAULT_TILING = dict(vec=2, wx=4, by=4, zdepth=32, pf=2, xcd=8)
+DTYPES = {"f64": HC_F64, "f32": HC_F32, "bf16": HC_BF16}
+_TILE_KEYS = ("vec", "wx", "by", "zdepth", "pf", "xcd")
+# the default of every element type: the library's automatic choice per call
+AUTO_TILING = dict.fromkeys(_TILE_KEYS, 0)
+DEFAULT_TILING = {dt: dict(AUTO_TILING) for dt in DTYPES}
 
 
-def set_tiling(vec: int = 2, wx: int = 4, by: int = 4, zdepth: int = 32, pf: int = 2,
-               xcd: int = 8) -> None:
-    """Tile shape of the z-marching heat kernels (results do not depend on it)."""
-    _check(load().hc_heat_set_tiling(int(vec), int(wx), int(by), int(zdepth), int(pf), int(xcd)))
+def set_tiling(vec: int | None = None, wx: int | None = None, by: int | None = None,
+               zdepth: int | None = None, pf: int = 2, xcd: int = 8,
+               dtype: str = "f64") -> None:
+    """Tile shape of the z-marching heat kernels for one element type
+    ("f64", "f32", "bf16"); with no shape given, the automatic choice.
+    Results do not depend on the shape."""
+    if vec is None and wx is None and by is None and zdepth is None:
+        t = AUTO_TILING
+    else:
+        if None in (vec, wx, by, zdepth):
+            raise ValueError("give vec, wx, by and zdepth, or none of them")
+        t = dict(vec=vec, wx=wx, by=by, zdepth=zdepth, pf=pf, xcd=xcd)
+    _check(load().hc_heat_set_tiling(DTYPES[dtype], *(int(t[k]) for k in _TILE_KEYS)))
 
 
-def get_tiling() -> dict:
+def get_tiling(dtype: str = "f64") -> dict:
+    """The setting for one element type (all zeros: automatic)."""
     v = [ctypes.c_int(0) for _ in range(6)]
-    load().hc_heat_get_tiling(*[ctypes.byref(x) for x in v])
-    return dict(zip(("vec", "wx", "by", "zdepth", "pf", "xcd"), (x.value for x in v)))
+    _check(load().hc_heat_get_tiling(DTYPES[dtype], *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def tiling_for(u, u_new=None) -> dict:
+    """The tile shape heat_step would sweep these tensors with."""
+    v = [ctypes.c_int(0) for _ in range(6)]
+    un = u if u_new is None else u_new
+    _check(load().hc_heat_tiling_for(_dtype_code(u), int(u.shape[-1]),
+                                     ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(un.data_ptr()),
+                                     *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
 
 
 DEFAULT_CG_TILING = dict(vec=2, wx=2, by=8, zdepth=32, xcd=8)

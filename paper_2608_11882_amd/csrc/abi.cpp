@@ -44,14 +44,56 @@ int hip_fail(hipError_t e, const char *what) {
 
 // ---- tile shape of the heat kernels (settable for tuning) -------------------
 std::mutex g_tiling_mu;
-// default: 512 x 4 tiles (two nodes per lane, four wavefronts per row),
-// z-blocks of 32 planes, two planes of loads in flight, runs of 8
-// y-neighbouring tiles per XCD (the fastest shape measured at 512^3)
-hc::HeatTiling g_tiling = {2, 4, 4, 32, 2, 8};
+// Per storage precision: a shape set by the caller, or all zeros for the
+// automatic choice (the default).
+hc::HeatTiling g_tiling[3] = {};
 
-hc::HeatTiling current_tiling() {
+hc::HeatTiling current_tiling(int dtype) {
     std::lock_guard<std::mutex> g(g_tiling_mu);
-    return g_tiling;
+    return g_tiling[dtype];
+}
+
+// Automatic choice: candidates per precision, widest tile first, all with
+// 16-byte lanes where the width allows, z-blocks of 16-32 planes, two planes
+// of loads in flight and runs of 8 y-neighbouring tiles per XCD (the fastest
+// shapes of a sweep over the built ones at 512^3 and 1024^3 on MI355X).
+// The first candidate whose row of tiles is at most 1/8 wider than the
+// narrowest candidate's wins: wide tiles amortise the ring and the block
+// set-up, but lanes past the last column do no work.
+const hc::HeatTiling kAuto[3][5] = {
+    {{2, 4, 4, 32, 2, 8}, {2, 2, 8, 16, 2, 8}, {2, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}, {}},
+    {{4, 4, 4, 16, 2, 8}, {2, 4, 4, 32, 2, 8}, {4, 1, 8, 32, 2, 8}, {2, 1, 8, 32, 2, 8},
+     {1, 1, 8, 16, 2, 8}},
+    {{8, 1, 8, 16, 2, 8}, {4, 1, 8, 16, 2, 8}, {2, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}, {}},
+};
+
+hc::HeatTiling auto_tiling(int dtype, int nx) {
+    long long best = -1;
+    for (const hc::HeatTiling &c : kAuto[dtype]) {
+        if (c.vec == 0) break;
+        const long long w = hc::tile_width(c);
+        const long long padded = (nx + w - 1) / w * w;
+        if (best < 0 || padded < best) best = padded;
+    }
+    for (const hc::HeatTiling &c : kAuto[dtype]) {
+        if (c.vec == 0) break;
+        const long long w = hc::tile_width(c);
+        if ((nx + w - 1) / w * w * 8 <= best * 9) return c;
+    }
+    return kAuto[dtype][0];
+}
+
+// The shape a sweep of these arrays runs with: the caller's or the automatic
+// one, then the one-node shape when vec nodes per lane do not fit (rows that
+// are not whole lanes, or arrays not aligned to a lane).
+hc::HeatTiling heat_tiling_for(int dtype, int nx, const void *u, const void *un) {
+    hc::HeatTiling til = current_tiling(dtype);
+    if (til.vec == 0) til = auto_tiling(dtype, nx);
+    const uintptr_t lane_bytes = (uintptr_t)til.vec * (uintptr_t)hc::dtype_bytes(dtype);
+    if (til.vec > 1 && ((nx % til.vec) || (reinterpret_cast<uintptr_t>(u) % lane_bytes) ||
+                        (reinterpret_cast<uintptr_t>(un) % lane_bytes)))
+        til = {1, 4, 4, 16, 2, til.xcd};
+    return til;
 }
 
 hc::CGTiling g_cg_tiling = {2, 2, 8, 32, 8};
@@ -245,17 +287,15 @@ double tile_algo_bytes(const hc::ZTable &t, int nx, int ny, int nz, size_t elem)
     return (double)elem * ((double)planes * nx * ny + (double)written * (nx - 2) * (ny - 2));
 }
 
-int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps, int mode,
+int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int steps, int mode,
              int parts, hipStream_t s) {
     DevState *d = nullptr;
     int rc = device_state(&d);
     if (rc) return rc;
-    hc::HeatTiling til = current_tiling();
-    // two nodes per lane need 16-byte aligned rows
-    if (til.vec == 2 && ((nx & 1) || (reinterpret_cast<uintptr_t>(u) & 15) ||
-                         (reinterpret_cast<uintptr_t>(un) & 15)))
-        til = {1, 4, 4, 16, 2, til.xcd};
-    const double plain_bytes = 8.0 * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
+    const size_t eb = (size_t)hc::dtype_bytes(dtype);
+    const hc::HeatTiling til = heat_tiling_for(dtype, nx, u, un);
+    const double plain_bytes =
+        (double)eb * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
 
     hc::ZTable tin = empty_table(), tbd = empty_table();
     if (mode == HC_HEAT_SPLIT) {
@@ -277,24 +317,24 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
     const long long nb_bd = hc::heat_tile_blocks(nx, ny, til, tbd);
     if (nb_in > 2147483647LL || nb_bd > 2147483647LL)
         return fail(HC_EINVAL, "grid too large for this tile shape");
-    const double bytes_in = tile_algo_bytes(tin, nx, ny, nz, 8);
-    const double bytes_bd = tile_algo_bytes(tbd, nx, ny, nz, 8);
+    const double bytes_in = tile_algo_bytes(tin, nx, ny, nz, eb);
+    const double bytes_bd = tile_algo_bytes(tbd, nx, ny, nz, eb);
 
-    HC_TRY(hc::launch_copy_faces_f64(u, un, nx, ny, nz, s), "copy_faces launch");
+    HC_TRY(hc::launch_copy_faces((int)eb, u, un, nx, ny, nz, s), "copy_faces launch");
     const bool split = (mode == HC_HEAT_SPLIT) && tbd.n > 0;
     if (split) {
         HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
         HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
     }
-    double *a = u, *b = un;
+    void *a = u, *b = un;
     for (int st = 0; st < steps; ++st) {
         if (mode == HC_HEAT_PLAIN) {
             Timed tm(hc::K_HEAT_PLAIN, s, plain_bytes);
-            HC_TRY(hc::launch_heat_plain_f64(a, b, nx, ny, nz, r, s), "heat_plain launch");
+            HC_TRY(hc::launch_heat_plain(dtype, a, b, nx, ny, nz, r, s), "heat_plain launch");
             tm.done();
         } else if (mode == HC_HEAT_FUSED) {
             Timed tm(hc::K_HEAT_FUSED, s, bytes_in);
-            HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_FUSED, a, b, nx, ny, nz, r, tin, til, s),
+            HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_FUSED, a, b, nx, ny, r, tin, til, s),
                    "heat_fused launch");
             tm.done();
         } else {
@@ -302,14 +342,14 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
             // the next step's Interior kernel waits for it
             {
                 Timed tm(hc::K_HEAT_BOUNDARY, d->aux, bytes_bd);
-                HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_BOUNDARY, a, b, nx, ny, nz, r, tbd, til,
-                                                d->aux),
+                HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_BOUNDARY, a, b, nx, ny, r, tbd, til,
+                                            d->aux),
                        "heat_boundary launch");
                 tm.done();
             }
             if (tin.n > 0) {
                 Timed tm(hc::K_HEAT_INTERIOR, s, bytes_in);
-                HC_TRY(hc::launch_heat_tile_f64(hc::K_HEAT_INTERIOR, a, b, nx, ny, nz, r, tin, til, s),
+                HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_INTERIOR, a, b, nx, ny, r, tin, til, s),
                        "heat_interior launch");
                 tm.done();
             }
@@ -322,7 +362,7 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
         std::swap(a, b);
     }
     if (a != u)
-        HC_TRY(hipMemcpyAsync(u, a, (size_t)nx * ny * nz * sizeof(double), hipMemcpyDeviceToDevice, s),
+        HC_TRY(hipMemcpyAsync(u, a, (size_t)nx * ny * nz * eb, hipMemcpyDeviceToDevice, s),
                "hipMemcpyAsync");
     return HC_OK;
 }
@@ -330,8 +370,9 @@ int heat_f64(double *u, double *un, int nx, int ny, int nz, double r, int steps,
 int validate_heat(const void *u, const void *un, int nx, int ny, int nz, double r, int steps,
                   int dtype, int mode, int parts, size_t *bytes) {
     if (!u || !un) return fail(HC_EINVAL, "u and u_new must be non-NULL");
-    if (dtype != HC_F64) return fail(HC_EINVAL, "dtype %d is not supported", dtype);
-    int rc = check_dims(nx, ny, nz, 3, 8, bytes);
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    int rc = check_dims(nx, ny, nz, 3, (size_t)hc::dtype_bytes(dtype), bytes);
     if (rc) return rc;
     if (!std::isfinite(r) || r < 0.0 || r > 1.0 / 6.0)
         return fail(HC_EUNSTABLE, "r = %g is outside [0, 1/6]", r);
@@ -471,8 +512,8 @@ int heat_step_ex(void *u, void *u_new, int nx, int ny, int nz, double r, int ste
     if (steps == 0) return HC_OK;
     if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
     if ((rc = check_device_buffer(u_new, bytes, "u_new"))) return rc;
-    return heat_f64(static_cast<double *>(u), static_cast<double *>(u_new), nx, ny, nz, r, steps,
-                    mode, parts, reinterpret_cast<hipStream_t>(stream));
+    return heat_run(dtype, u, u_new, nx, ny, nz, r, steps, mode, parts,
+                    reinterpret_cast<hipStream_t>(stream));
 }
 
 int heat_step(double *u, double *u_new, int nx, int ny, int nz, double r, int steps) {
@@ -589,26 +630,54 @@ int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream) 
     return HC_OK;
 }
 
-int hc_heat_set_tiling(int vec, int wx, int by, int zdepth, int pf, int xcd) {
+int hc_heat_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int pf, int xcd) {
     g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
     const hc::HeatTiling t = {vec, wx, by, zdepth, pf, xcd};
-    if (!hc::heat_tiling_supported(t))
-        return fail(HC_EINVAL, "tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built",
-                    vec, wx, by, zdepth, pf);
+    if (vec == 0 && wx == 0 && by == 0 && zdepth == 0 && pf == 0 && xcd == 0) {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        g_tiling[dtype] = t;  // automatic choice
+        return HC_OK;
+    }
+    if (!hc::heat_tiling_supported(dtype, t))
+        return fail(HC_EINVAL,
+                    "tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built for dtype %d",
+                    vec, wx, by, zdepth, pf, dtype);
     if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
     std::lock_guard<std::mutex> g(g_tiling_mu);
-    g_tiling = t;
+    g_tiling[dtype] = t;
     return HC_OK;
 }
 
-void hc_heat_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *pf, int *xcd) {
-    const hc::HeatTiling t = current_tiling();
+int hc_heat_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth, int *pf, int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    const hc::HeatTiling t = current_tiling(dtype);
     if (vec) *vec = t.vec;
     if (wx) *wx = t.wx;
     if (by) *by = t.by;
     if (zdepth) *zdepth = t.zdepth;
     if (pf) *pf = t.pf;
     if (xcd) *xcd = t.xcd;
+    return HC_OK;
+}
+
+int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new, int *vec, int *wx,
+                       int *by, int *zdepth, int *pf, int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
+    const hc::HeatTiling t = heat_tiling_for(dtype, nx, u, u_new);
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
+    return HC_OK;
 }
 
 int hc_cg_set_tiling(int vec, int wx, int by, int zdepth, int xcd) {

@@ -9,10 +9,6 @@
 
 namespace hc {
 
-// Width of a tile along x: one wavefront of 64 lanes, one node per lane, so
-// every plane row of a tile is one 512-byte (FP64) coalesced access.
-constexpr int kTileX = 64;
-
 // Up to this many k-ranges can be swept by one launch (the slab count of
 // the Interior/Boundary split is bounded by it).
 constexpr int kMaxRanges = 64;
@@ -30,7 +26,8 @@ struct ZTable {
 
 // Launch shape of the z-marching heat kernels.
 struct HeatTiling {
-    int vec;      // nodes per lane along x: 1 or 2 (2: 16-byte accesses)
+    int vec;      // nodes per lane along x: 1, 2, 4 or 8 (16-byte accesses
+                  // at 2 FP64, 4 FP32 or 8 bfloat16 nodes)
     int wx;       // wavefronts per tile row: tile width = 64 * vec * wx
     int by;       // rows per tile
     int zdepth;   // planes per z-block of the Interior / fused kernel
@@ -58,15 +55,19 @@ int ztable_blocks(const ZTable &zt);
 // Grid size of a z-marching launch over table zt.
 long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt);
 int tile_width(const HeatTiling &t);
-bool heat_tiling_supported(const HeatTiling &t);
-hipError_t launch_heat_tile_f64(KernelKind kind, const double *u, double *un,
-                                int nx, int ny, int nz, double r,
-                                const ZTable &zt, const HeatTiling &t,
-                                hipStream_t s);
-hipError_t launch_heat_plain_f64(const double *u, double *un, int nx, int ny,
-                                 int nz, double r, hipStream_t s);
-hipError_t launch_copy_faces_f64(const double *u, double *un, int nx, int ny,
-                                 int nz, hipStream_t s);
+// Storage precision codes (same values as hc_dtype): 0 FP64, 1 FP32,
+// 2 bfloat16 storage with FP32 arithmetic.
+constexpr int kDtypeF64 = 0, kDtypeF32 = 1, kDtypeBF16 = 2;
+inline int dtype_bytes(int dtype) { return dtype == 0 ? 8 : dtype == 1 ? 4 : 2; }
+bool heat_tiling_supported(int dtype, const HeatTiling &t);
+// u and un hold nodes of the storage type of `dtype`.
+hipError_t launch_heat_tile(int dtype, KernelKind kind, const void *u, void *un, int nx,
+                            int ny, double r, const ZTable &zt, const HeatTiling &t,
+                            hipStream_t s);
+hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny, int nz,
+                             double r, hipStream_t s);
+hipError_t launch_copy_faces(int elem_bytes, const void *u, void *un, int nx, int ny, int nz,
+                             hipStream_t s);
 
 // ---- CG (cg_kernels.hip) ------------------------------------------------------
 // Device-resident scalars of one CG solve.  Written by the last block of

@@ -1,19 +1,29 @@
-// heat_kernels.hip -- 7-point explicit heat update for gfx950 (FP64).
+// heat_kernels.hip -- 7-point explicit heat update for gfx950.
 //
 // The update is Eq. (4) of the paper with a constant coefficient and no
 // source: u_new = u + r * (((x- + x+) + (y- + y+)) + (z- + z+) - 6 u).
 // The sum is evaluated in exactly that order and the library is compiled
 // without floating-point contraction, so every node is bit-identical to a
-// plain serial evaluation of the same expression.
+// plain serial evaluation of the same expression in the same precision.
+//
+// Three storage precisions share one kernel body (the Prec traits below):
+// FP64 (the paper's precision), FP32, and bfloat16 storage with FP32
+// arithmetic (each new value rounded to the nearest bfloat16, ties to even).
 //
 // Kernel design (2.5-D z-march).  A block owns a tile of 64*VEC*WX (x) by
-// BY (y) nodes -- WX wavefronts per row, VEC consecutive nodes per lane --
-// and walks it through a run of planes [kb, ke].  Each thread keeps its
-// column's values at k-1, k, k+1 in registers, so every stored node is
-// loaded once per z-block; the x/y neighbours come from the current plane
-// staged in LDS with a one-node ring (two coalesced rows, two columns).
-// PF planes of loads are in flight while a plane is computed.  Results are
-// stored non-temporally: u_new is not read again in this step.
+// BY (y) nodes -- WX wavefronts per row, VEC consecutive nodes per lane, 16
+// bytes per lane for the wide shapes -- and walks it through a run of planes
+// [kb, ke].  Each thread keeps its column's values at k-1, k, k+1 in
+// registers, so every stored node is loaded once per z-block.  The current
+// plane is staged in LDS (in the arithmetic precision) with a one-node ring
+// (two coalesced rows, two columns) for the y neighbours and for the x
+// neighbours across lanes; x neighbours inside a lane's VEC nodes come from
+// its registers.  An LDS row holds node v of every lane of the row as one
+// contiguous run of 64*WX values (v = 0..VEC-1), so every LDS access of a
+// wavefront touches consecutive words (no bank conflicts) and each node
+// costs about two LDS reads.  PF planes of loads are in flight while a plane
+// is computed.  Results are stored non-temporally: u_new is not read again
+// in this step.
 //
 // Tiles are numbered y fastest, then x, then z-block, and the block ids can
 // be regrouped so that runs of y-neighbouring tiles share an XCD's L2 (see
@@ -22,8 +32,38 @@
 #include "hc_internal.hpp"
 
 #include <climits>
+#include <type_traits>
 
 namespace hc {
+
+// ---- storage precisions -------------------------------------------------------
+struct PrecF64 {
+    using S = double;  // stored
+    using C = double;  // arithmetic
+    __device__ static C widen(S v) { return v; }
+    __device__ static S narrow(C v) { return v; }
+};
+struct PrecF32 {
+    using S = float;
+    using C = float;
+    __device__ static C widen(S v) { return v; }
+    __device__ static S narrow(C v) { return v; }
+};
+// bfloat16 as its bit pattern: the upper half of a binary32.  Widening is
+// exact; narrowing rounds to nearest, ties to even (adding 0x7fff plus the
+// kept lowest bit carries exactly when the dropped half is above one half,
+// or equal to it with an odd kept part); NaN stays a quiet NaN.
+struct PrecBF16 {
+    using S = unsigned short;
+    using C = float;
+    __device__ static C widen(S v) { return __uint_as_float((unsigned)v << 16); }
+    __device__ static S narrow(C v) {
+        const unsigned u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (S)((u >> 16) | 0x40u);
+        return (S)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    }
+};
+
 namespace {
 
 // Block order.  The hardware deals workgroups to the 8 XCDs round-robin
@@ -43,6 +83,39 @@ __device__ __forceinline__ int block_order(int b, int nb, int g) {
     return w * win + (o & 7) * g + (o >> 3);
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// One access of N bytes (2, 4, 8 or 16) as a single load or store.
+template <int N> struct Raw;
+template <> struct Raw<2> { using T = unsigned short; };
+template <> struct Raw<4> { using T = unsigned int; };
+template <> struct Raw<8> { using T = u32x2; };
+template <> struct Raw<16> { using T = u32x4; };
+
+template <class P, int VEC>
+__device__ __forceinline__ void load_vec(const typename P::S *__restrict__ p,
+                                         typename P::C *o) {
+    using R = typename Raw<VEC * sizeof(typename P::S)>::T;
+    const R raw = *reinterpret_cast<const R *>(p);
+    typename P::S s[VEC];
+    __builtin_memcpy(s, &raw, sizeof raw);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) o[v] = P::widen(s[v]);
+}
+
+template <class P, int VEC>
+__device__ __forceinline__ void store_vec_nt(typename P::S *__restrict__ p,
+                                             const typename P::C *v) {
+    using R = typename Raw<VEC * sizeof(typename P::S)>::T;
+    typename P::S s[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) s[e] = P::narrow(v[e]);
+    R raw;
+    __builtin_memcpy(&raw, s, sizeof raw);
+    __builtin_nontemporal_store(raw, reinterpret_cast<R *>(p));
+}
+
 // Loads are never predicated: a node outside the array is read at a clamped
 // in-bounds address instead, and such values only ever reach lanes whose own
 // nodes are not updated.  Those lanes store their own (unchanged) values
@@ -60,21 +133,25 @@ __device__ __forceinline__ int block_order(int b, int nb, int g) {
 // range is shifted back to a full ZB planes; the planes it shares with the
 // block before are computed twice and written twice with identical bits.
 // Ranges shorter than ZB (the Boundary planes) take the generic loop.
-//
-// Tile: WX wavefronts per row, each lane owning VEC consecutive nodes in x
-// (VEC = 2: one 16-byte access per lane, 1 KiB per wavefront row), BY rows.
 
+// LDS row layout (LD values): [left ring column] [node 0 of lanes
+// 0..64*WX-1] [node 1 of every lane] ... [node VEC-1 of every lane] [right
+// ring column]; rows 0 and BY+1 are the ring rows.
 template <int VEC, int WX, int BY>
 struct TileGeom {
     static constexpr int TX = 64 * VEC * WX;   // tile width in nodes
+    static constexpr int TXL = 64 * WX;        // lanes per tile row
     static constexpr int LD = TX + 2;          // LDS row stride
     static constexpr int NT = 64 * WX * BY;    // threads per block
-    static constexpr int RROW = TX / VEC;      // threads per ring row
+    static constexpr int RROW = TXL;           // threads per ring row
     static_assert(NT >= 2 * RROW + 2 * BY, "one thread per ring element");
     int kb, ke;
     long long plane, own, ring;  // ring: VEC-aligned offset of the ring load
     bool st[VEC];
-    int own_slot, rslot;
+    int own_slot;          // LDS slot of the lane's node 0 (node v: + v*TXL)
+    int xm_slot, xp_slot;  // LDS slots of the left neighbour of node 0 and
+                           // the right neighbour of node VEC-1
+    int rslot;             // LDS slot of the ring element (node v: + v*TXL)
     bool rvec;  // ring element is a VEC-wide row piece (else one node)
     int rsel;   // the node's index within the aligned VEC-wide ring load
 
@@ -109,10 +186,14 @@ struct TileGeom {
             own = (long long)min(j, ny - 1) * nx + ia;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) st[v] = (ia + v >= 1) && (ia + v <= nx - 2) && (j <= ny - 2);
-        own_slot = (wy + 1) * LD + (wx * 64 + lane) * VEC + 1;
+        const int gl = wx * 64 + lane;  // lane index within the tile row
+        const int rowb = (wy + 1) * LD;
+        own_slot = rowb + 1 + gl;
+        xm_slot = gl == 0 ? rowb : own_slot - 1 + (VEC - 1) * TXL;
+        xp_slot = gl == TXL - 1 ? rowb + TX + 1 : own_slot + 1;
 
         // ring of the LDS tile: rows j0-1 and j0+BY (VEC nodes per thread,
-        // coalesced), then columns i0-1 and i0+TX (one node per thread)
+        // coalesced), then columns i0-1 and i0+TX (one node per thread).
         // Every thread issues one VEC-wide aligned ring load (a column node
         // is taken out of the aligned VEC nodes that hold it), so the load
         // is the same instruction in every lane.
@@ -123,7 +204,7 @@ struct TileGeom {
             const int row = t / RROW, q = t % RROW;
             const int rj = row == 0 ? j0 - 1 : min(j0 + BY, ny - 1);
             ring = (long long)rj * nx + min(i0 + q * VEC, nx - VEC);
-            rslot = (row == 0 ? 0 : (BY + 1) * LD) + q * VEC + 1;
+            rslot = (row == 0 ? 0 : (BY + 1) * LD) + 1 + q;
             rvec = true;
         } else if (t < 2 * RROW + 2 * BY) {
             const int q = t - 2 * RROW;
@@ -138,82 +219,68 @@ struct TileGeom {
     }
 };
 
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-template <int VEC>
-__device__ __forceinline__ void load_vec(const double *__restrict__ p, double *o) {
-    if (VEC == 2) {
-        const f64x2 v = *reinterpret_cast<const f64x2 *>(p);
-        o[0] = v.x;
-        o[1] = v.y;
-    } else {
-        o[0] = *p;
-    }
-}
-
-template <int VEC>
-__device__ __forceinline__ void store_vec_nt(double *__restrict__ p, const double *v) {
-    if (VEC == 2) {
-        f64x2 x;
-        x.x = v[0];
-        x.y = v[1];
-        __builtin_nontemporal_store(x, reinterpret_cast<f64x2 *>(p));
-    } else {
-        __builtin_nontemporal_store(v[0], p);
-    }
-}
-
-template <int VEC, int WX, int BY, int PF, int ZB>
-__device__ __forceinline__ void heat_tile_sweep(const double *__restrict__ u,
-                                                double *__restrict__ un, int nx,
-                                                int ny, double r,
+template <class P, int VEC, int WX, int BY, int PF, int ZB>
+__device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict__ u,
+                                                typename P::S *__restrict__ un, int nx,
+                                                int ny, typename P::C r,
                                                 const ZTable &zt, int ntx,
                                                 int nty, int xcd) {
+    using C = typename P::C;
+    using S = typename P::S;
     using G = TileGeom<VEC, WX, BY>;
     static_assert(PF >= 1 && PF <= 2, "prefetch depth 1 or 2");
-    __shared__ double tile[(BY + 2) * G::LD];
+    __shared__ C tile[(BY + 2) * G::LD];
     const G g(nx, ny, zt, ntx, nty, xcd, ZB);
     const long long plane = g.plane;
-    const double *__restrict__ uo = u + g.own;
-    const double *__restrict__ ur = u + g.ring;
-    double *__restrict__ vo = un + g.own;
+    const S *__restrict__ uo = u + g.own;
+    const S *__restrict__ ur = u + g.ring;
+    S *__restrict__ vo = un + g.own;
     const int kb = g.kb, ke = g.ke;
 
-    // ring value(s) of plane k: one aligned VEC-wide load in every lane
-    auto ld_ring = [&](long long kp, double *o) {
-        double v[VEC];
-        load_vec<VEC>(ur + kp, v);
-        o[0] = (VEC == 2 && g.rsel) ? v[VEC - 1] : v[0];
-        o[1] = v[VEC - 1];
-    };
-    auto put = [&](const double *c, const double *gv) {
+    // ring values of plane k: one aligned VEC-wide load in every lane; a
+    // column thread keeps the node it needs in o[0]
+    auto ld_ring = [&](long long kp, C *o) {
+        load_vec<P, VEC>(ur + kp, o);
+        if (!g.rvec) {
+            C sel = o[0];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) tile[g.own_slot + v] = c[v];
-        if (g.rslot >= 0) {
-            tile[g.rslot] = gv[0];
-            if (VEC == 2 && g.rvec) tile[g.rslot + 1] = gv[1];
+            for (int e = 1; e < VEC; ++e) sel = (g.rsel == e) ? o[e] : sel;
+            o[0] = sel;
         }
     };
-    auto update = [&](const double *zm, const double *c, const double *zp, double *out) {
+    auto put = [&](const C *c, const C *gv) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) tile[g.own_slot + v * G::TXL] = c[v];
+        if (g.rslot >= 0) {
+            tile[g.rslot] = gv[0];
+            if (g.rvec) {
+#pragma unroll
+                for (int v = 1; v < VEC; ++v) tile[g.rslot + v * G::TXL] = gv[v];
+            }
+        }
+    };
+    auto update = [&](const C *zm, const C *c, const C *zp, C *out) {
+        const C xm0 = tile[g.xm_slot];
+        const C xpl = tile[g.xp_slot];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-            const int sl = g.own_slot + v;
-            const double xm = tile[sl - 1];
-            const double xp = tile[sl + 1];
-            const double ym = tile[sl - G::LD];
-            const double yp = tile[sl + G::LD];
-            const double nsum = ((xm + xp) + (ym + yp)) + (zm[v] + zp[v]);
-            const double lap = nsum - 6.0 * c[v];
+            const int sl = g.own_slot + v * G::TXL;
+            const C xm = v == 0 ? xm0 : c[v - 1];
+            const C xp = v == VEC - 1 ? xpl : c[v + 1];
+            const C ym = tile[sl - G::LD];
+            const C yp = tile[sl + G::LD];
+            const C nsum = ((xm + xp) + (ym + yp)) + (zm[v] + zp[v]);
+            const C lap = nsum - C(6) * c[v];
             out[v] = g.st[v] ? c[v] + r * lap : c[v];
         }
     };
 
     if (ke - kb + 1 == ZB) {
         // q[s] = column values of plane kb-1+s, gr[s] = ring of plane kb+s
-        double q[ZB + 2][VEC];
-        double gr[ZB][2];
+        C q[ZB + 2][VEC];
+        C gr[ZB][VEC];
 #pragma unroll
-        for (int s = 0; s < PF + 2; ++s) load_vec<VEC>(uo + (long long)(kb - 1 + s) * plane, q[s]);
+        for (int s = 0; s < PF + 2; ++s) load_vec<P, VEC>(uo + (long long)(kb - 1 + s) * plane, q[s]);
 #pragma unroll
         for (int s = 0; s < PF; ++s) ld_ring((long long)(kb + s) * plane, gr[s]);
 #pragma unroll
@@ -223,86 +290,89 @@ __device__ __forceinline__ void heat_tile_sweep(const double *__restrict__ u,
             put(q[s + 1], gr[s]);
             if (s + PF < ZB) ld_ring(kp + PF * plane, gr[s + PF]);
             __syncthreads();
-            double out[VEC];
+            C out[VEC];
             update(q[s], q[s + 1], q[s + 2], out);
-            store_vec_nt<VEC>(vo + kp, out);
-            if (s + 2 + PF <= ZB + 1) load_vec<VEC>(uo + kp + (1 + PF) * plane, q[s + 2 + PF]);
+            store_vec_nt<P, VEC>(vo + kp, out);
+            if (s + 2 + PF <= ZB + 1) load_vec<P, VEC>(uo + kp + (1 + PF) * plane, q[s + 2 + PF]);
         }
         return;
     }
 
     // generic depth (short ranges): one plane of loads ahead
-    double zm[VEC], c[VEC], zp[VEC], g0[2];
-    load_vec<VEC>(uo + (long long)(kb - 1) * plane, zm);
-    load_vec<VEC>(uo + (long long)kb * plane, c);
-    load_vec<VEC>(uo + (long long)(kb + 1) * plane, zp);
+    C zm[VEC], c[VEC], zp[VEC], g0[VEC];
+    load_vec<P, VEC>(uo + (long long)(kb - 1) * plane, zm);
+    load_vec<P, VEC>(uo + (long long)kb * plane, c);
+    load_vec<P, VEC>(uo + (long long)(kb + 1) * plane, zp);
     ld_ring((long long)kb * plane, g0);
     for (int k = kb; k <= ke; ++k) {
         const long long kp = (long long)k * plane;
-        double zn[VEC], gn[2];
-        load_vec<VEC>(uo + (long long)min(k + 2, ke + 1) * plane, zn);
+        C zn[VEC], gn[VEC];
+        load_vec<P, VEC>(uo + (long long)min(k + 2, ke + 1) * plane, zn);
         ld_ring((long long)min(k + 1, ke) * plane, gn);
         __syncthreads();
         put(c, g0);
         __syncthreads();
-        double out[VEC];
+        C out[VEC];
         update(zm, c, zp, out);
-        store_vec_nt<VEC>(vo + kp, out);
+        store_vec_nt<P, VEC>(vo + kp, out);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             zm[v] = c[v];
             c[v] = zp[v];
             zp[v] = zn[v];
+            g0[v] = gn[v];
         }
-        g0[0] = gn[0];
-        g0[1] = gn[1];
     }
 }
 
 // Three entry points with one body, so that profiles name the role.
-template <int VEC, int WX, int BY, int PF, int ZB>
-__global__ __launch_bounds__(64 * WX * BY) void heat_interior_f64(
-    const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
-    double r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+template <class P, int VEC, int WX, int BY, int PF, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void heat_interior(
+    const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
+    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {
+    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
 }
 
-template <int VEC, int WX, int BY, int PF, int ZB>
-__global__ __launch_bounds__(64 * WX * BY) void heat_boundary_f64(
-    const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
-    double r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+template <class P, int VEC, int WX, int BY, int PF, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void heat_boundary(
+    const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
+    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {
+    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
 }
 
-template <int VEC, int WX, int BY, int PF, int ZB>
-__global__ __launch_bounds__(64 * WX * BY) void heat_fused_f64(
-    const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
-    double r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+template <class P, int VEC, int WX, int BY, int PF, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void heat_fused(
+    const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
+    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {
+    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
 }
 
 // One thread per interior node, all seven values loaded from memory: the
 // straightforward form (the paper's collapse(3) loop mapped onto a grid).
-__global__ __launch_bounds__(256) void heat_plain_f64(
-    const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
-    int nz, double r) {
+template <class P>
+__global__ __launch_bounds__(256) void heat_plain(
+    const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
+    int ny, int nz, typename P::C r) {
+    using C = typename P::C;
     const int i = 1 + (int)blockIdx.x * 64 + (int)threadIdx.x;
     const int j = 1 + (int)blockIdx.y * 4 + (int)threadIdx.y;
     const int k = 1 + (int)blockIdx.z;
     if (i > nx - 2 || j > ny - 2 || k > nz - 2) return;
     const long long sy = nx, sz = (long long)nx * ny;
     const long long p = (long long)k * sz + (long long)j * sy + i;
-    const double c = u[p];
-    const double nsum = ((u[p - 1] + u[p + 1]) + (u[p - sy] + u[p + sy])) +
-                        (u[p - sz] + u[p + sz]);
-    const double lap = nsum - 6.0 * c;
-    un[p] = c + r * lap;
+    const C c = P::widen(u[p]);
+    const C nsum = ((P::widen(u[p - 1]) + P::widen(u[p + 1])) +
+                    (P::widen(u[p - sy]) + P::widen(u[p + sy]))) +
+                   (P::widen(u[p - sz]) + P::widen(u[p + sz]));
+    const C lap = nsum - C(6) * c;
+    un[p] = P::narrow(c + r * lap);
 }
 
 // Copy the outermost layer (the Dirichlet data) of u into un.
-__global__ __launch_bounds__(256) void copy_faces_f64(
-    const double *__restrict__ u, double *__restrict__ un, int nx, int ny,
-    int nz) {
+template <class T>
+__global__ __launch_bounds__(256) void copy_faces(const T *__restrict__ u,
+                                                  T *__restrict__ un, int nx,
+                                                  int ny, int nz) {
     const long long plane = (long long)nx * ny;
     const long long per_mid = 2LL * nx + 2LL * (ny - 2);  // per inner plane
     const long long total = 2 * plane + (long long)(nz - 2) * per_mid;
@@ -343,32 +413,41 @@ long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt
     return ntx * nty * (long long)ztable_blocks(zt);
 }
 
-// Every tile shape the library is built with.
-#define HC_HEAT_SHAPES(X)                                                        \
-    X(1, 1, 4, 1, 16) X(1, 1, 4, 2, 16) X(1, 1, 4, 2, 32)                        \
-    X(1, 1, 8, 1, 16) X(1, 1, 8, 2, 16) X(1, 1, 8, 2, 32)                        \
-    X(1, 1, 16, 1, 16) X(1, 1, 16, 2, 16) X(1, 1, 16, 2, 32)                     \
-    X(1, 2, 8, 2, 16) X(1, 4, 4, 2, 16) X(1, 4, 4, 2, 32)                        \
-    X(2, 1, 4, 2, 16) X(2, 1, 8, 1, 16) X(2, 1, 8, 2, 16) X(2, 1, 8, 2, 32)     \
-    X(2, 1, 16, 2, 16) X(2, 2, 4, 2, 16) X(2, 2, 8, 1, 16) X(2, 2, 8, 2, 16)    \
-    X(2, 2, 8, 2, 32) X(2, 4, 4, 1, 16) X(2, 4, 4, 2, 16)                       \
-    X(2, 4, 4, 2, 32) X(2, 2, 8, 2, 64) X(2, 4, 4, 2, 64) X(2, 1, 16, 2, 32)
+// Every tile shape the library is built with, per precision:
+// X(vec, wx, by, pf, zdepth).  Arrays that do not allow wide lanes fall
+// back to (1, 4, 4, 2, 16), which every list holds.
+#define HC_HEAT_SHAPES_F64(X)                                                     \
+    X(1, 4, 4, 2, 16) X(1, 1, 4, 1, 16) X(1, 1, 8, 2, 16) X(1, 1, 16, 2, 16)     \
+    X(1, 4, 4, 2, 32) X(2, 1, 8, 2, 16) X(2, 1, 16, 2, 32) X(2, 2, 8, 2, 16)     \
+    X(2, 2, 8, 2, 32) X(2, 2, 8, 2, 64) X(2, 4, 4, 1, 16) X(2, 4, 4, 2, 16)      \
+    X(2, 4, 4, 2, 32) X(2, 4, 4, 2, 64)
+#define HC_HEAT_SHAPES_F32(X)                                                     \
+    X(1, 4, 4, 2, 16) X(1, 1, 8, 2, 16) X(2, 1, 8, 2, 32) X(2, 4, 4, 2, 32)      \
+    X(4, 1, 8, 2, 32) X(4, 1, 16, 2, 32) X(4, 2, 4, 2, 32) X(4, 2, 8, 2, 16)     \
+    X(4, 2, 8, 2, 32) X(4, 4, 4, 2, 16) X(4, 4, 4, 2, 32) X(4, 2, 8, 1, 32)
+#define HC_HEAT_SHAPES_BF16(X)                                                    \
+    X(1, 4, 4, 2, 16) X(1, 1, 8, 2, 16) X(2, 1, 8, 2, 16) X(4, 1, 8, 2, 16)      \
+    X(4, 2, 8, 2, 32) X(4, 4, 4, 2, 32) X(8, 1, 4, 2, 32) X(8, 1, 8, 2, 16)      \
+    X(8, 1, 8, 2, 32) X(8, 1, 16, 2, 32) X(8, 2, 4, 2, 32) X(8, 2, 8, 2, 32)
 
 #define HC_SHAPE_KEY(V, W, B, P, Z) ((((V * 8 + W) * 32 + B) * 4 + P) * 128 + Z)
 
-bool heat_tiling_supported(const HeatTiling &t) {
+bool heat_tiling_supported(int dtype, const HeatTiling &t) {
     const int key = HC_SHAPE_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
 #define HC_X(V, W, B, P, Z) if (key == HC_SHAPE_KEY(V, W, B, P, Z)) return true;
-    HC_HEAT_SHAPES(HC_X)
+    if (dtype == 0) { HC_HEAT_SHAPES_F64(HC_X) }
+    if (dtype == 1) { HC_HEAT_SHAPES_F32(HC_X) }
+    if (dtype == 2) { HC_HEAT_SHAPES_BF16(HC_X) }
 #undef HC_X
     return false;
 }
 
-hipError_t launch_heat_tile_f64(KernelKind kind, const double *u, double *un,
-                                int nx, int ny, int nz, double r,
-                                const ZTable &zt, const HeatTiling &t,
-                                hipStream_t s) {
-    (void)nz;
+template <class P>
+static hipError_t launch_tile(KernelKind kind, const void *u, void *un, int nx, int ny,
+                              double r, const ZTable &zt, const HeatTiling &t,
+                              hipStream_t s) {
+    using S = typename P::S;
+    using C = typename P::C;
     const long long nb = heat_tile_blocks(nx, ny, t, zt);
     if (nb <= 0) return hipSuccess;
     if (nb > INT_MAX) return hipErrorInvalidConfiguration;
@@ -376,40 +455,91 @@ hipError_t launch_heat_tile_f64(KernelKind kind, const double *u, double *un,
     const int ntx = (nx + txw - 1) / txw;
     const int nty = (ny - 2 + t.by - 1) / t.by;
     const dim3 grid((unsigned)nb), block(64 * t.wx * t.by);
+    const S *us = static_cast<const S *>(u);
+    S *uns = static_cast<S *>(un);
+    const C rc = (C)r;
     const int key = HC_SHAPE_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
-#define HC_X(V, W, B, P, Z)                                                      \
-    if (key == HC_SHAPE_KEY(V, W, B, P, Z)) {                                    \
+#define HC_X(V, W, B, PF, Z)                                                     \
+    if (key == HC_SHAPE_KEY(V, W, B, PF, Z)) {                                   \
         if (kind == K_HEAT_INTERIOR)                                             \
-            heat_interior_f64<V, W, B, P, Z><<<grid, block, 0, s>>>(             \
-                u, un, nx, ny, r, zt, ntx, nty, t.xcd);                          \
+            heat_interior<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(             \
+                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd);                       \
         else if (kind == K_HEAT_BOUNDARY)                                        \
-            heat_boundary_f64<V, W, B, P, Z><<<grid, block, 0, s>>>(             \
-                u, un, nx, ny, r, zt, ntx, nty, t.xcd);                          \
+            heat_boundary<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(             \
+                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd);                       \
         else                                                                     \
-            heat_fused_f64<V, W, B, P, Z><<<grid, block, 0, s>>>(                \
-                u, un, nx, ny, r, zt, ntx, nty, t.xcd);                          \
+            heat_fused<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(                \
+                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd);                       \
         return hipGetLastError();                                                \
     }
-    HC_HEAT_SHAPES(HC_X)
+    if constexpr (std::is_same<P, PrecF64>::value) {
+        HC_HEAT_SHAPES_F64(HC_X)
+    } else if constexpr (std::is_same<P, PrecF32>::value) {
+        HC_HEAT_SHAPES_F32(HC_X)
+    } else {
+        HC_HEAT_SHAPES_BF16(HC_X)
+    }
 #undef HC_X
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_heat_plain_f64(const double *u, double *un, int nx, int ny,
-                                 int nz, double r, hipStream_t s) {
-    const dim3 grid((nx - 2 + 63) / 64, (ny - 2 + 3) / 4, nz - 2),
-        block(64, 4);
-    heat_plain_f64<<<grid, block, 0, s>>>(u, un, nx, ny, nz, r);
+hipError_t launch_heat_tile(int dtype, KernelKind kind, const void *u, void *un, int nx,
+                            int ny, double r, const ZTable &zt, const HeatTiling &t,
+                            hipStream_t s) {
+    switch (dtype) {
+        case 0: return launch_tile<PrecF64>(kind, u, un, nx, ny, r, zt, t, s);
+        case 1: return launch_tile<PrecF32>(kind, u, un, nx, ny, r, zt, t, s);
+        case 2: return launch_tile<PrecBF16>(kind, u, un, nx, ny, r, zt, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny, int nz,
+                             double r, hipStream_t s) {
+    const dim3 grid((nx - 2 + 63) / 64, (ny - 2 + 3) / 4, nz - 2), block(64, 4);
+    switch (dtype) {
+        case 0:
+            heat_plain<PrecF64><<<grid, block, 0, s>>>(static_cast<const double *>(u),
+                                                       static_cast<double *>(un), nx, ny, nz, r);
+            break;
+        case 1:
+            heat_plain<PrecF32><<<grid, block, 0, s>>>(static_cast<const float *>(u),
+                                                       static_cast<float *>(un), nx, ny, nz,
+                                                       (float)r);
+            break;
+        case 2:
+            heat_plain<PrecBF16><<<grid, block, 0, s>>>(
+                static_cast<const unsigned short *>(u), static_cast<unsigned short *>(un), nx,
+                ny, nz, (float)r);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_copy_faces_f64(const double *u, double *un, int nx, int ny,
-                                 int nz, hipStream_t s) {
+hipError_t launch_copy_faces(int elem_bytes, const void *u, void *un, int nx, int ny, int nz,
+                             hipStream_t s) {
     const long long total =
         2LL * nx * ny + (long long)(nz - 2) * (2LL * nx + 2LL * (ny - 2));
     long long nb = (total + 255) / 256;
     if (nb > 4096) nb = 4096;
-    copy_faces_f64<<<(unsigned)nb, 256, 0, s>>>(u, un, nx, ny, nz);
+    switch (elem_bytes) {
+        case 8:
+            copy_faces<unsigned long long><<<(unsigned)nb, 256, 0, s>>>(
+                static_cast<const unsigned long long *>(u), static_cast<unsigned long long *>(un),
+                nx, ny, nz);
+            break;
+        case 4:
+            copy_faces<unsigned int><<<(unsigned)nb, 256, 0, s>>>(
+                static_cast<const unsigned int *>(u), static_cast<unsigned int *>(un), nx, ny, nz);
+            break;
+        case 2:
+            copy_faces<unsigned short><<<(unsigned)nb, 256, 0, s>>>(
+                static_cast<const unsigned short *>(u), static_cast<unsigned short *>(un), nx, ny,
+                nz);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -116,26 +116,19 @@ def batched_fields(dims, rng, dtype=np.float32):
 def to_bf16_bits(x) -> np.ndarray:
     """bfloat16 bit patterns (uint16) of float64 values, rounded once to the
     nearest bfloat16 with ties to even (no double rounding through binary32).
-    Values must be finite and inside the bfloat16 normal range, or zero."""
+    Values must be finite and inside the bfloat16 normal range, or zero.
+
+    x = m 2^e with 1/2 <= |m| < 1 (frexp); m 2^8 holds the 8 significant
+    bits a bfloat16 keeps in its integer part, so rint (ties to even) of it,
+    scaled back, is the rounded value -- every step exact in float64."""
     x = np.ascontiguousarray(x, dtype=np.float64)
-    b = x.view(np.uint64)
-    sign = (b >> np.uint64(63)).astype(np.uint32)
-    exp = ((b >> np.uint64(52)) & np.uint64(0x7FF)).astype(np.int64)
-    man = b & np.uint64((1 << 52) - 1)
-    keep = (man >> np.uint64(45)).astype(np.int64)          # 7 stored bits
-    rest = man & np.uint64((1 << 45) - 1)
-    half = np.uint64(1 << 44)
-    up = (rest > half) | ((rest == half) & ((keep & 1) == 1))
-    keep = keep + up.astype(np.int64)
-    exp = exp + (keep >> 7)
-    keep = keep & 0x7F
-    zero = (x == 0.0)
-    e8 = exp - 1023 + 127
-    if np.any(~zero & ((e8 < 1) | (e8 > 254))):
+    m, e = np.frexp(x)
+    y = np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
+    ay = np.abs(y)
+    if np.any((x != 0.0) & ((ay < 2.0 ** -126) | (ay > (2.0 - 2.0 ** -7) * 2.0 ** 127))) or \
+            not np.all(np.isfinite(x)):
         raise ValueError("value outside the bfloat16 normal range")
-    bits = (sign << 15) | (np.where(zero, 0, e8).astype(np.uint32) << 7) | \
-        np.where(zero, 0, keep).astype(np.uint32)
-    return bits.astype(np.uint16)
+    return (y.astype(np.float32).view(np.uint32) >> np.uint32(16)).astype(np.uint16)
 
 
 def sine_field_lowp(nx: int, ny: int, nz: int, noise: float, seed: int, dtype: str):

@@ -105,14 +105,67 @@ def test_copy_probe_and_lap7_validation(lib):
 
 
 def test_tiling_knob(lib):
-    assert lib.hc_heat_set_tiling(2, 4, 2, 16, 2, 0) == HC_EINVAL   # ring needs more threads
-    assert lib.hc_heat_set_tiling(1, 1, 4, 48, 2, 0) == HC_EINVAL   # depth not built
-    assert lib.hc_heat_set_tiling(3, 1, 4, 16, 2, 0) == HC_EINVAL
-    assert lib.hc_heat_set_tiling(1, 1, 8, 16, 2, 65) == HC_EINVAL  # xcd run length
-    assert lib.hc_heat_set_tiling(1, 4, 4, 32, 2, 1) == HC_OK
+    assert lib.hc_heat_set_tiling(0, 2, 4, 2, 16, 2, 0) == HC_EINVAL   # ring needs more threads
+    assert lib.hc_heat_set_tiling(0, 1, 1, 4, 48, 2, 0) == HC_EINVAL   # depth not built
+    assert lib.hc_heat_set_tiling(0, 3, 1, 4, 16, 2, 0) == HC_EINVAL
+    assert lib.hc_heat_set_tiling(0, 1, 1, 8, 16, 2, 65) == HC_EINVAL  # xcd run length
+    assert lib.hc_heat_set_tiling(0, 4, 4, 4, 32, 2, 0) == HC_EINVAL   # 4-node lanes: FP32 only
+    assert lib.hc_heat_set_tiling(1, 2, 4, 4, 16, 2, 0) == HC_EINVAL   # shape not built for FP32
+    assert lib.hc_heat_set_tiling(3, 1, 4, 4, 16, 2, 0) == HC_EINVAL   # unknown dtype
+    assert lib.hc_heat_get_tiling(3, None, None, None, None, None, None) == HC_EINVAL
+    assert lib.hc_heat_set_tiling(0, 1, 4, 4, 32, 2, 1) == HC_OK
     assert hc.get_tiling() == dict(vec=1, wx=4, by=4, zdepth=32, pf=2, xcd=1)
-    hc.set_tiling()
-    assert hc.get_tiling() == hc.DEFAULT_TILING
+    # the precisions keep separate shapes
+    assert lib.hc_heat_set_tiling(1, 4, 2, 8, 16, 2, 3) == HC_OK
+    assert hc.get_tiling("f32") == dict(vec=4, wx=2, by=8, zdepth=16, pf=2, xcd=3)
+    assert hc.get_tiling("f64") == dict(vec=1, wx=4, by=4, zdepth=32, pf=2, xcd=1)
+    assert lib.hc_heat_set_tiling(2, 8, 2, 4, 32, 2, 0) == HC_OK
+    assert hc.get_tiling("bf16")["vec"] == 8
+    for dt in ("f64", "f32", "bf16"):
+        hc.set_tiling(dtype=dt)
+        assert hc.get_tiling(dt) == hc.DEFAULT_TILING[dt] == hc.AUTO_TILING
+        # the one-node fallback shape is built for every precision
+        hc.set_tiling(1, 4, 4, 16, 2, 0, dtype=dt)
+        hc.set_tiling(dtype=dt)
+
+
+def tiling_for(lib, dtype, nx, u=None, un=None):
+    v = [ctypes.c_int(0) for _ in range(6)]
+    rc = lib.hc_heat_tiling_for(dtype, nx, u, un, *[ctypes.byref(x) for x in v])
+    assert rc == HC_OK
+    return tuple(x.value for x in v)
+
+
+def test_automatic_tiling_choice(lib):
+    """Every shape the automatic choice can return is built, tiles are never
+    more than 1/8 wider than the narrowest candidate's, the widest fitting
+    tile wins, and lanes of vec nodes need whole, aligned lanes."""
+    for dt in (0, 1, 2):
+        for nx in list(range(3, 300)) + [510, 511, 512, 513, 600, 1000, 1023, 1024, 1030, 4096]:
+            vec, wx, by, zd, pf, xcd = tiling_for(lib, dt, nx)
+            assert lib.hc_heat_set_tiling(dt, vec, wx, by, zd, pf, xcd) == HC_OK, (dt, nx)
+            assert nx % vec == 0 or vec == 1
+        assert lib.hc_heat_set_tiling(dt, 0, 0, 0, 0, 0, 0) == HC_OK
+    assert tiling_for(lib, 0, 512) == (2, 4, 4, 32, 2, 8)
+    assert tiling_for(lib, 1, 512) == (2, 4, 4, 32, 2, 8)
+    assert tiling_for(lib, 1, 1024) == (4, 4, 4, 16, 2, 8)
+    assert tiling_for(lib, 2, 1024) == (8, 1, 8, 16, 2, 8)
+    assert tiling_for(lib, 2, 512) == (8, 1, 8, 16, 2, 8)
+    # 1030 needs narrow tiles, which have two-node lanes; 1027 is odd
+    assert tiling_for(lib, 1, 1030) == (2, 1, 8, 32, 2, 8)
+    assert tiling_for(lib, 1, 1027)[0] == 1
+    # misaligned arrays: one-node lanes
+    off = lambda p, b: ctypes.c_void_p(p.value + b)  # noqa: E731
+    assert tiling_for(lib, 0, 512, off(FAKE_U, 8), FAKE_V)[0] == 1
+    assert tiling_for(lib, 2, 1024, FAKE_U, off(FAKE_V, 2))[0] == 1
+    assert tiling_for(lib, 2, 1024, FAKE_U, FAKE_V)[0] == 8
+    # an explicit setting wins over the automatic one
+    assert lib.hc_heat_set_tiling(1, 4, 2, 8, 16, 2, 3) == HC_OK
+    assert tiling_for(lib, 1, 1024) == (4, 2, 8, 16, 2, 3)
+    hc.set_tiling(dtype="f32")
+    v = [ctypes.c_int(0) for _ in range(6)]
+    assert lib.hc_heat_tiling_for(5, 64, None, None, *[ctypes.byref(x) for x in v]) == HC_EINVAL
+    assert lib.hc_heat_tiling_for(0, 2, None, None, *[ctypes.byref(x) for x in v]) == HC_EINVAL
 
 
 def test_cg_tiling_knob(lib):

@@ -1,0 +1,245 @@
+"""GPU parity of the reduced-precision heat sweeps (binary32, and bfloat16
+storage with binary32 arithmetic) against the CPU oracle's binary32 and
+bfloat16 steps.
+
+Both sides evaluate the same written expression in the same order in
+binary32 without contraction, and the bfloat16 rounding is round to
+nearest, ties to even on both, so every comparison is bit-for-bit.  At the
+full 1024^3 size the oracle checks a short run on the first and last planes
+(an output plane after s steps depends only on the input planes within s of
+it), and the 500-step binary32 run is checked against the exact decay of a
+pure sine mode within a rigorous rounding-error bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2608_11882_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24   # unit roundoff of binary32
+
+
+def note(msg):
+    print("[case] " + msg, flush=True)
+
+
+def to_device(a):
+    """uint16 bit patterns become a torch.bfloat16 tensor of the same bits."""
+    if a.dtype == np.uint16:
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int16)).cuda().view(torch.bfloat16)
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def to_host(t):
+    if t.dtype == torch.bfloat16:
+        return t.view(torch.int16).cpu().numpy().view(np.uint16)
+    return t.cpu().numpy()
+
+
+def gpu_heat(hc, u0, r, steps, mode="split", parts=1):
+    u = to_device(u0)
+    un = torch.empty_like(u)
+    hc.heat_step(u, un, r, steps, mode=mode, parts=parts)
+    torch.cuda.synchronize()
+    return to_host(u)
+
+
+def oracle_heat(u0, r, steps):
+    return oracle.heat_bf16(u0, r, steps) if u0.dtype == np.uint16 else oracle.heat_f32(u0, r, steps)
+
+
+def field(dims, seed, dtype, noise=None):
+    nx, ny, nz = dims
+    if noise is None:   # rough data: U[0,1] interior, rounded once
+        u = inputs.uniform_field(nx, ny, nz, seed=seed)
+        return u.astype(np.float32) if dtype == "f32" else inputs.to_bf16_bits(u)
+    return inputs.sine_field_lowp(nx, ny, nz, noise, seed, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("mode", ["split", "fused", "plain"])
+def test_small_config_bitwise(gpu, dtype, mode):
+    cfg = inputs.HEAT_SMALL
+    note("heat %s 66^3 r=0.1 100 steps mode=%s" % (dtype, mode))
+    u0 = inputs.sine_field_lowp(66, 66, 66, 1e-3, cfg["seed"], dtype)
+    want = oracle_heat(u0, cfg["r"], cfg["steps"])
+    got = gpu_heat(gpu, u0, cfg["r"], cfg["steps"], mode=mode)
+    assert got.dtype == want.dtype and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dims", [(67, 35, 20), (130, 9, 40), (3, 3, 3), (64, 6, 70),
+                                  (1030, 13, 5), (520, 66, 37), (1024, 12, 36)])
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_ragged_shapes_bitwise(gpu, dtype, dims, mode):
+    """Widths that end inside a tile, widths that are not a multiple of the
+    lane width (one-node fallback), and very short z-extents."""
+    note("heat %s ragged %s mode=%s" % (dtype, dims, mode))
+    u0 = field(dims, dims[0] * 7 + dims[1] * 3 + dims[2], dtype)
+    want = oracle_heat(u0, 0.15, 7)
+    assert np.array_equal(gpu_heat(gpu, u0, 0.15, 7, mode=mode), want)
+
+
+def test_parts_bitwise(gpu):
+    dims = (256, 20, 67)
+    for dtype in ("f32", "bf16"):
+        u0 = field(dims, 77, dtype)
+        want = oracle_heat(u0, 0.125, 6)
+        for parts in (2, 5, 32):
+            note("heat %s parts=%d" % (dtype, parts))
+            assert np.array_equal(gpu_heat(gpu, u0, 0.125, 6, parts=parts), want)
+
+
+def built_shapes(dtype):
+    import paper_2608_11882_amd as hc
+    lib = hc.load()
+    code = hc.DTYPES[dtype]
+    shapes = []
+    for vec in (1, 2, 4, 8):
+        for wx in (1, 2, 4):
+            for by in (4, 8, 16):
+                for zd in (16, 32, 64):
+                    for pf in (1, 2):
+                        if lib.hc_heat_set_tiling(code, vec, wx, by, zd, pf, 0) == 0:
+                            shapes.append((vec, wx, by, zd, pf))
+    hc.set_tiling(dtype=dtype)
+    return shapes
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_every_tile_shape_is_bitwise_identical(gpu, dtype):
+    dims = (2056, 37, 75)   # ragged against every width (2056 = 8 * 257) and depth
+    u0 = field(dims, 31, dtype)
+    want = oracle_heat(u0, 1.0 / 6.5, 5)
+    shapes = built_shapes(dtype)
+    assert len(shapes) >= 6
+    try:
+        for shape in shapes:
+            for xcd in (0, 3, 8):
+                note("heat %s tiling %s xcd=%d" % (dtype, shape, xcd))
+                gpu.set_tiling(*shape, xcd=xcd, dtype=dtype)
+                for mode in ("split", "fused"):
+                    assert np.array_equal(gpu_heat(gpu, u0, 1.0 / 6.5, 5, mode=mode), want), \
+                        (shape, xcd, mode)
+    finally:
+        gpu.set_tiling(dtype=dtype)
+
+
+def test_misaligned_arrays_fall_back_bitwise(gpu):
+    """Arrays that start off the lane alignment take the one-node shape."""
+    dims = (64, 10, 12)
+    n = dims[0] * dims[1] * dims[2]
+    for dtype, tdt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        u0 = field(dims, 5, dtype)
+        want = oracle_heat(u0, 0.1, 3)
+        big = torch.empty(2 * n + 16, dtype=tdt, device="cuda")
+        u = big[1:1 + n].view(dims[2], dims[1], dims[0])
+        un = big[n + 9:2 * n + 9].view(dims[2], dims[1], dims[0])
+        u.copy_(to_device(u0))
+        note("heat %s misaligned" % dtype)
+        gpu.heat_step(u, un, 0.1, 3)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(u), want)
+
+
+def test_reduced_precision_error_against_fp64_is_within_bound(gpu):
+    """Max error of the binary32 sweep against the FP64 oracle on the small
+    configuration, against the worst-case rounding bound: each step adds at
+    most (1 + 46 r) u32 max|u| to first order (the five additions of the
+    neighbour sum err by at most 16 u32 max|u| together, 6c by 6, the
+    difference and the product by r 12 each with |lap| <= 12 max|u|, the
+    final addition by 1) and the scheme is contractive in the max norm for
+    r <= 1/6, so the errors of the steps add up without amplification."""
+    cfg = inputs.HEAT_SMALL
+    note("heat f32 vs f64 error bound 66^3")
+    u64 = inputs.sine_field(66, 66, 66, noise=1e-3, seed=cfg["seed"])
+    u32 = inputs.sine_field_lowp(66, 66, 66, 1e-3, cfg["seed"], "f32")
+    ref = oracle.heat(u32.astype(np.float64), cfg["r"], cfg["steps"])
+    got = gpu_heat(gpu, u32, cfg["r"], cfg["steps"]).astype(np.float64)
+    m = np.max(np.abs(u64))
+    bound = cfg["steps"] * (1 + 46 * cfg["r"]) * U32 * m + abs(np.float32(cfg["r"]) - cfg["r"]) \
+        * cfg["steps"] * 12 * m
+    err = np.max(np.abs(got - ref))
+    assert err <= bound, (err, bound)
+    assert np.max(np.abs(u32.astype(np.float64) - u64)) <= U32 * m
+
+
+# ---- full size: 1024^3 ------------------------------------------------------------
+
+def full_size_slab_check(hc, dtype, steps=3, planes=24):
+    cfg = inputs.HEAT_PRECISION
+    n, r = cfg["n"], cfg["r"]
+    note("heat %s %d^3 %d steps, oracle on the first and last %d planes" % (dtype, n, steps, planes))
+    u0 = inputs.sine_field_lowp(n, n, n, 1e-3, cfg["seed"], dtype)
+    lo, hi = u0[:planes].copy(), u0[n - planes:].copy()
+    u = to_device(u0)
+    del u0
+    un = torch.empty_like(u)
+    hc.heat_step(u, un, r, steps)
+    torch.cuda.synchronize()
+    got_lo, got_hi = to_host(u[:planes - steps]), to_host(u[n - planes + steps:])
+    want_lo = oracle_heat(lo, r, steps)[:planes - steps]
+    want_hi = oracle_heat(hi, r, steps)[steps:]
+    assert np.array_equal(got_lo, want_lo)
+    assert np.array_equal(got_hi, want_hi)
+
+
+def test_full_size_f32_short_run_bitwise_on_slabs(gpu):
+    full_size_slab_check(gpu, "f32")
+
+
+def test_full_size_bf16_short_run_bitwise_on_slabs(gpu):
+    full_size_slab_check(gpu, "bf16")
+
+
+def test_full_size_f32_pure_mode_500_steps_within_rounding_bound(gpu):
+    cfg = inputs.HEAT_PRECISION
+    n, r, steps = cfg["n"], cfg["r"], cfg["steps"]
+    note("heat f32 %d^3 pure sine mode, %d steps, vs G^steps" % (n, steps))
+    s = torch.sin(torch.pi * torch.from_numpy(inputs.node_coords(n))).cuda()
+    s[0] = 0.0
+    s[-1] = 0.0
+    u64 = s[:, None, None] * s[None, :, None] * s[None, None, :]
+    u = u64.float()
+    del u64
+    un = torch.empty_like(u)
+    u0 = u.clone()
+    gpu.heat_step(u, un, r, steps)
+    torch.cuda.synchronize()
+    del un
+    r32 = float(np.float32(r))
+    g = 1.0 - 3 * 4.0 * r32 * np.sin(np.pi / (2.0 * (n - 1))) ** 2
+    # exact discrete result for the rounded initial field and the rounded r
+    err = 0.0
+    for k0 in range(0, n, 128):
+        want = (g ** steps) * u0[k0:k0 + 128].double()
+        err = max(err, (u[k0:k0 + 128].double() - want).abs().max().item())
+    m = u0.abs().max().item()
+    bound = steps * (1 + 46 * r32) * U32 * m
+    note("f32 pure-mode max error %.3e (bound %.3e)" % (err, bound))
+    assert err <= bound
+    assert torch.isfinite(u).all().item()
+
+
+def test_full_size_bf16_500_steps_keeps_the_maximum_principle(gpu):
+    """bfloat16 storage at 1024^3: the smooth mode changes by less than half
+    a bfloat16 ulp per step, so round-to-nearest leaves most nodes where
+    they are; what must hold at any size is the discrete maximum principle
+    (values stay within [min(0, min u0), max(0, max u0)]) and finiteness."""
+    cfg = inputs.HEAT_PRECISION
+    n, r, steps = cfg["n"], cfg["r"], cfg["steps"]
+    note("heat bf16 %d^3 %d steps, maximum principle" % (n, steps))
+    u0 = inputs.sine_field_lowp(n, n, n, 1e-3, cfg["seed"], "bf16")
+    u = to_device(u0)
+    lo = min(0.0, float(u.float().min().item()))
+    hi = max(0.0, float(u.float().max().item()))
+    del u0
+    un = torch.empty_like(u)
+    gpu.heat_step(u, un, r, steps)
+    torch.cuda.synchronize()
+    uf = u.float()
+    assert torch.isfinite(uf).all().item()
+    assert uf.min().item() >= lo and uf.max().item() <= hi
