@@ -60,6 +60,16 @@ def _configure(lib):
     lib.oracle_heat_bf16.restype = ctypes.c_int
     lib.oracle_bf16_round_array.argtypes = [fp, hp, L]
     lib.oracle_bf16_round_array.restype = None
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    U64 = ctypes.c_uint64
+    lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_sr_bits.argtypes = [U64, U64, U64]
+    lib.oracle_sr_bits.restype = ctypes.c_uint16
+    lib.oracle_bf16_sr_from_f32.argtypes = [ctypes.c_float, ctypes.c_uint16]
+    lib.oracle_bf16_sr_from_f32.restype = ctypes.c_uint16
+    lib.oracle_heat_bf16_sr.argtypes = [hp, L, L, L, ctypes.c_float, L, U64, U64]
+    lib.oracle_heat_bf16_sr.restype = ctypes.c_int
     return lib
 
 
@@ -156,6 +166,40 @@ def heat_bf16(u0_bits: np.ndarray, r: float, steps: int) -> np.ndarray:
     if rc != 0:
         raise MemoryError("oracle_heat_bf16 returned %d" % rc)
     return u
+
+
+def heat_bf16_sr(u0_bits: np.ndarray, r: float, steps: int, seed: int, step0: int = 0) -> np.ndarray:
+    """bfloat16 storage, binary32 arithmetic, stochastic rounding with the
+    Philox4x32-10 bits of (seed, step, node); step s uses t = step0 + s."""
+    u = np.ascontiguousarray(u0_bits, dtype=np.uint16).copy()
+    if u.ndim != 3:
+        raise ValueError("expected a 3-D (nz, ny, nx) array")
+    nz, ny, nx = u.shape
+    rc = _load().oracle_heat_bf16_sr(u.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                     nx, ny, nz, float(np.float32(r)), int(steps),
+                                     int(seed) & (2 ** 64 - 1), int(step0) & (2 ** 64 - 1))
+    if rc != 0:
+        raise MemoryError("oracle_heat_bf16_sr returned %d" % rc)
+    return u
+
+
+def philox4x32_10(ctr, key) -> tuple:
+    """One Philox4x32-10 block: four 32-bit counter words, two key words."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    _load().oracle_philox4x32_10(c, k, o)
+    return tuple(o)
+
+
+def sr_bits(p: int, t: int, seed: int) -> int:
+    """The 16 random bits of node p at step t."""
+    return int(_load().oracle_sr_bits(int(p), int(t), int(seed) & (2 ** 64 - 1)))
+
+
+def bf16_sr(x: float, rho: int) -> int:
+    """Stochastic rounding of one binary32 to bfloat16 with 16 bits rho."""
+    return int(_load().oracle_bf16_sr_from_f32(float(np.float32(x)), int(rho)))
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:

@@ -218,6 +218,128 @@ int oracle_heat_bf16(uint16_t *u, long nx, long ny, long nz, float r, long steps
     return 0;
 }
 
+/*
+ * bfloat16 storage with stochastic rounding.  Round to nearest leaves a node
+ * unchanged whenever its increment is below half a bfloat16 ulp, which for
+ * smooth fields is every step (the sweep stagnates); rounding up with
+ * probability equal to the discarded fraction instead makes the rounding
+ * unbiased, so small increments accumulate on average.
+ *
+ * The random bits come from the counter-based generator Philox4x32-10
+ * (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as
+ * 1, 2, 3", SC 2011), written here from that definition: ten rounds, each
+ * multiplying words 0 and 2 of the counter by two constants, recombining
+ * high and low halves with the other words and the key, with the key bumped
+ * by two Weyl constants between rounds.
+ */
+static void philox_round(uint32_t c[4], const uint32_t k[2])
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k[0];
+    const uint32_t n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+}
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(c, k);
+    }
+    memcpy(out, c, sizeof c);
+}
+
+/*
+ * The 16 random bits of node p (linear index (k*ny + j)*nx + i) at step t
+ * under `seed`: nodes are taken in aligned groups of 8; group g = p / 8 draws
+ * one Philox4x32-10 block with counter (g low, g high, t low, t high) and key
+ * (seed low, seed high); node p takes word (p mod 8) / 2 of the block, its
+ * low half when p is even and its high half when p is odd.
+ */
+uint16_t oracle_sr_bits(uint64_t p, uint64_t t, uint64_t seed)
+{
+    const uint64_t g = p >> 3;
+    const uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), (uint32_t)t, (uint32_t)(t >> 32)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    const uint32_t w = out[(p & 7u) >> 1];
+    return (uint16_t)((p & 1u) ? (w >> 16) : (w & 0xffffu));
+}
+
+/*
+ * Stochastic rounding of a binary32 to bfloat16 with 16 random bits rho:
+ * the magnitude is rounded up exactly when (its discarded 16 bits) + rho
+ * carries into the kept part, i.e. with probability (discarded bits)/2^16.
+ * Values that are already bfloat16 are unchanged.  NaN stays a quiet NaN.
+ */
+uint16_t oracle_bf16_sr_from_f32(float f, uint16_t rho)
+{
+    uint32_t bits;
+    memcpy(&bits, &f, sizeof bits);
+    if ((bits & 0x7fffffffu) > 0x7f800000u)      /* NaN */
+        return (uint16_t)((bits >> 16) | 0x0040u);
+    const uint32_t upper = bits >> 16;
+    const uint32_t lower = bits & 0xffffu;
+    return (uint16_t)(lower + rho >= 0x10000u ? upper + 1u : upper);
+}
+
+/* One bfloat16 step as above, rounding each new value stochastically with
+ * the bits of its node at step t. */
+void oracle_heat_sweep_bf16_sr(const uint16_t *u, uint16_t *un, long nx, long ny,
+                               long nz, float r, uint64_t seed, uint64_t t)
+{
+    const long sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 1; k < nz - 1; ++k)
+        for (long j = 1; j < ny - 1; ++j)
+            for (long i = 1; i < nx - 1; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const float c = oracle_f32_from_bf16(u[p]);
+                const float nsum =
+                    ((oracle_f32_from_bf16(u[p - sx]) + oracle_f32_from_bf16(u[p + sx])) +
+                     (oracle_f32_from_bf16(u[p - sy]) + oracle_f32_from_bf16(u[p + sy]))) +
+                    (oracle_f32_from_bf16(u[p - sz]) + oracle_f32_from_bf16(u[p + sz]));
+                const float lap = nsum - 6.0f * c;
+                un[p] = oracle_bf16_sr_from_f32(c + r * lap, oracle_sr_bits((uint64_t)p, t, seed));
+            }
+}
+
+/* `steps` such steps; step s uses t = step0 + s. */
+int oracle_heat_bf16_sr(uint16_t *u, long nx, long ny, long nz, float r, long steps,
+                        uint64_t seed, uint64_t step0)
+{
+    const long n = nx * ny * nz;
+    if (steps <= 0)
+        return 0;
+    uint16_t *w = (uint16_t *)malloc((size_t)n * sizeof(uint16_t));
+    if (!w)
+        return -4;
+    memcpy(w, u, (size_t)n * sizeof(uint16_t));
+    uint16_t *a = u, *b = w;
+    for (long s = 0; s < steps; ++s) {
+        oracle_heat_sweep_bf16_sr(a, b, nx, ny, nz, r, seed, step0 + (uint64_t)s);
+        uint16_t *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    if (a != u)
+        memcpy(u, a, (size_t)n * sizeof(uint16_t));
+    free(w);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Conjugate Gradient on the 7-point Laplacian                               */
 /* ------------------------------------------------------------------------ */

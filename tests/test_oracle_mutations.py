@@ -12,6 +12,7 @@ import oracle
 import test_oracle_cg as cg_pins
 import test_oracle_heat as heat_pins
 import test_oracle_precision as prec_pins
+import test_oracle_sr as sr_pins
 
 HEAT_PINS = [
     lambda: heat_pins.test_single_sine_mode_decays_by_exact_factor((13, 9, 7), (2, 3, 1), 0.16, 15),
@@ -34,7 +35,22 @@ PREC_PINS = [
     prec_pins.test_bf16_error_against_f64_within_bound_and_stagnation,
 ]
 
+SR_PINS = [
+    sr_pins.test_philox_known_answer_vectors,
+    sr_pins.test_rounding_is_exactly_unbiased_over_all_random_bits,
+    sr_pins.test_step_brackets_the_binary32_step_and_rounds_up_at_the_right_rate,
+    sr_pins.test_steps_compose_and_depend_on_the_seed,
+    sr_pins.test_stochastic_rounding_removes_the_stagnation,
+]
+
 MUTATIONS = {
+    "philox_multiplier": ("(uint64_t)0xD2511F53u * c[0]", "(uint64_t)0xD2511F55u * c[0]", SR_PINS),
+    "philox_key_schedule": ("k[1] += 0xBB67AE85u;", "k[1] += 0x9E3779B9u;", SR_PINS),
+    "philox_word_swap": ("const uint32_t n2 = hi0 ^ c[3] ^ k[1];", "const uint32_t n2 = hi0 ^ c[1] ^ k[1];", SR_PINS),
+    "sr_off_by_one": ("lower + rho >= 0x10000u", "lower + rho > 0x10000u", SR_PINS),
+    "sr_counter_frozen": ("step0 + (uint64_t)s);", "step0);", SR_PINS),
+    "sr_uses_nearest": ("un[p] = oracle_bf16_sr_from_f32(c + r * lap, oracle_sr_bits((uint64_t)p, t, seed));",
+                        "un[p] = oracle_bf16_from_f32(c + r * lap);", SR_PINS),
     "bf16_ties_away": ("if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u)))", "if (lower >= 0x8000u)", PREC_PINS),
     "bf16_truncates": ("out = upper + 1u;", "out = upper;", PREC_PINS),
     "f32_dropped_weight": ("const float lap = nsum - 6.0f * c;\n                un[p] = c + r * lap;",
