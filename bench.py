@@ -128,14 +128,21 @@ def field_errors(got, ref):
     return emax, (e2 / r2) ** 0.5 if r2 > 0 else 0.0
 
 
-def timed_sweep(hc, u, un, u0, r, steps):
-    """Milliseconds of heat_step(u, un, r, steps) started from u0."""
+SR_SEED = 0x5EED
+
+
+def timed_sweep(hc, u, un, u0, r, steps, sr=False):
+    """Milliseconds of heat_step(u, un, r, steps) started from u0 (with
+    sr: the bfloat16 sweep with stochastic rounding)."""
     import torch
     u.copy_(u0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    hc.heat_step(u, un, r, steps, mode="split")
+    if sr:
+        hc.heat_step_sr(u, un, r, steps, SR_SEED)
+    else:
+        hc.heat_step(u, un, r, steps, mode="split")
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
@@ -146,7 +153,8 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
     * 512^3: the same field and steps as the headline in binary32 (and
       bfloat16 storage), GLUP/s and algorithmic GB/s beside FP64's;
     * 1024^3, r = 0.15, 500 steps, sine mode + U[-1e-3, 1e-3] (seed 3):
-      binary32 and bfloat16-storage rates, and their max and relative-L2
+      binary32 and bfloat16-storage rates (nearest and stochastic rounding,
+      the latter keyed by a fixed seed), and their max and relative-L2
       errors against the FP64 path on the full grid (the FP64 kernels are
       bit-identical to the oracle wherever the tests compare them) and
       against the FP64 oracle itself on a 256^3 instance of the same recipe."""
@@ -158,11 +166,13 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
     lups = nsteps_large * (n - 2) ** 3
     rate = {}
     for name, u0 in (("f64", u_init64), ("f32", u_init64.float()),
-                     ("bf16", u_init64.to(torch.float32).to(torch.bfloat16))):
-        # (the bfloat16 rate does not depend on how the field was rounded)
+                     ("bf16", u_init64.to(torch.float32).to(torch.bfloat16)),
+                     ("bf16_sr", u_init64.to(torch.float32).to(torch.bfloat16))):
+        # (the bfloat16 rates do not depend on how the field was rounded)
         u, un = torch.empty_like(u0), torch.empty_like(u0)
-        timed_sweep(hc, u, un, u0, r_large, 10)
-        ms = timed_sweep(hc, u, un, u0, r_large, nsteps_large)
+        sr = name == "bf16_sr"
+        timed_sweep(hc, u, un, u0, r_large, 10, sr)
+        ms = timed_sweep(hc, u, un, u0, r_large, nsteps_large, sr)
         eb = u0.element_size()
         rate[name] = {"tiling": hc.tiling_for(u, un),
                       "glups": round(lups / (ms / 1e3) / 1e9, 2),
@@ -179,7 +189,7 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
     lups = steps * (N - 2) ** 3
     res = {}
     ref = None
-    for name in ("f64", "f32", "bf16"):
+    for name in ("f64", "f32", "bf16", "bf16_sr"):
         if name == "f64":
             u0 = torch.from_numpy(u64h).to(dev)
         elif name == "f32":
@@ -187,8 +197,9 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
         else:
             u0 = to_bf16_device(u64h, dev)
         u, un = torch.empty_like(u0), torch.empty_like(u0)
-        timed_sweep(hc, u, un, u0, r, 5)
-        ms = timed_sweep(hc, u, un, u0, r, steps)
+        sr = name == "bf16_sr"
+        timed_sweep(hc, u, un, u0, r, 5, sr)
+        ms = timed_sweep(hc, u, un, u0, r, steps, sr)
         eb = u0.element_size()
         rec = {"tiling": hc.tiling_for(u, un),
                "glups": round(lups / (ms / 1e3) / 1e9, 2),
@@ -216,11 +227,11 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
         s64 = inputs.sine_field(m, m, m, noise=1e-3, seed=seed)
         want = torch.from_numpy(oracle.heat(s64, r, steps)).to(dev)
         sub = {}
-        for name in ("f32", "bf16"):
+        for name in ("f32", "bf16", "bf16_sr"):
             u0 = (torch.from_numpy(s64).to(dev).float() if name == "f32"
                   else to_bf16_device(s64, dev))
             u, un = torch.empty_like(u0), torch.empty_like(u0)
-            timed_sweep(hc, u, un, u0, r, steps)
+            timed_sweep(hc, u, un, u0, r, steps, name == "bf16_sr")
             emax, el2 = field_errors(u, want)
             sub[name] = {"max_err": emax, "rel_l2_err": el2}
         sub["max_abs_u"] = float(want.abs().max().item())

@@ -112,6 +112,31 @@ int heat_step_ex(void *u, void *u_new, int nx, int ny, int nz, double r,
                  int steps, int dtype, int mode, int parts, hc_stream_t stream);
 
 /*
+ * heat_step_sr -- heat_step_ex for bfloat16 storage (HC_BF16 layout and
+ * rules) with stochastic instead of nearest rounding.  Nearest rounding
+ * drops every increment below half a bfloat16 ulp, so smooth fields stall;
+ * here each new binary32 value v is rounded up in magnitude with
+ * probability (the 16 bits of v a bfloat16 drops) / 2^16, and down
+ * otherwise, which makes the rounding unbiased.  Values that are already
+ * bfloat16 are kept.  NaN stays a quiet NaN; a value within one bfloat16 ulp
+ * of the largest finite one may round to infinity.
+ *
+ * The 16 random bits of node p = (k*ny + j)*nx + i at step t come from the
+ * counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+ * SC 2011): nodes are taken in aligned groups of 8, group g = p / 8 draws
+ * one block with counter words (g mod 2^32, g / 2^32, t mod 2^32, t / 2^32)
+ * and key words (seed mod 2^32, seed / 2^32), and node p takes word
+ * (p mod 8) / 2 of it, the low half for even p and the high half for odd p.
+ * Step s of this call (0 <= s < steps) has t = step0 + s, so a run split
+ * over several calls with step0 advanced by the steps already taken gives
+ * the same bits as one call.  The result depends on (seed, step0) and on
+ * nothing else: not on mode, parts, tile shape or stream.
+ */
+int heat_step_sr(void *u, void *u_new, int nx, int ny, int nz, double r,
+                 int steps, unsigned long long seed, unsigned long long step0,
+                 int mode, int parts, hc_stream_t stream);
+
+/*
  * cg_solve -- solve A x = b with Conjugate Gradient (the CG case study),
  * A the 7-point Laplacian 6 I - (face neighbours) on an n x n x n box with
  * zero Dirichlet data outside the box (no ghost layer is stored).

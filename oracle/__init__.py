@@ -68,7 +68,7 @@ def _configure(lib):
     lib.oracle_sr_bits.restype = ctypes.c_uint16
     lib.oracle_bf16_sr_from_f32.argtypes = [ctypes.c_float, ctypes.c_uint16]
     lib.oracle_bf16_sr_from_f32.restype = ctypes.c_uint16
-    lib.oracle_heat_bf16_sr.argtypes = [hp, L, L, L, ctypes.c_float, L, U64, U64]
+    lib.oracle_heat_bf16_sr.argtypes = [hp, L, L, L, ctypes.c_float, L, U64, U64, U64]
     lib.oracle_heat_bf16_sr.restype = ctypes.c_int
     return lib
 
@@ -168,16 +168,20 @@ def heat_bf16(u0_bits: np.ndarray, r: float, steps: int) -> np.ndarray:
     return u
 
 
-def heat_bf16_sr(u0_bits: np.ndarray, r: float, steps: int, seed: int, step0: int = 0) -> np.ndarray:
+def heat_bf16_sr(u0_bits: np.ndarray, r: float, steps: int, seed: int, step0: int = 0,
+                 node0: int = 0) -> np.ndarray:
     """bfloat16 storage, binary32 arithmetic, stochastic rounding with the
-    Philox4x32-10 bits of (seed, step, node); step s uses t = step0 + s."""
+    Philox4x32-10 bits of (seed, step, node); step s uses t = step0 + s.
+    node0: linear index of u0_bits' first node in the array the bits are
+    keyed to (a slab of planes k0.. of a larger array: k0 * nx * ny)."""
     u = np.ascontiguousarray(u0_bits, dtype=np.uint16).copy()
     if u.ndim != 3:
         raise ValueError("expected a 3-D (nz, ny, nx) array")
     nz, ny, nx = u.shape
     rc = _load().oracle_heat_bf16_sr(u.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
                                      nx, ny, nz, float(np.float32(r)), int(steps),
-                                     int(seed) & (2 ** 64 - 1), int(step0) & (2 ** 64 - 1))
+                                     int(seed) & (2 ** 64 - 1), int(step0) & (2 ** 64 - 1),
+                                     int(node0))
     if rc != 0:
         raise MemoryError("oracle_heat_bf16_sr returned %d" % rc)
     return u

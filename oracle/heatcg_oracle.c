@@ -296,9 +296,11 @@ uint16_t oracle_bf16_sr_from_f32(float f, uint16_t rho)
 }
 
 /* One bfloat16 step as above, rounding each new value stochastically with
- * the bits of its node at step t. */
+ * the bits of its node at step t.  node0 is the linear index of u[0] in the
+ * array the bits are keyed to (0 for a whole array; a slab of planes
+ * k0.. of a larger array has node0 = k0*nx*ny). */
 void oracle_heat_sweep_bf16_sr(const uint16_t *u, uint16_t *un, long nx, long ny,
-                               long nz, float r, uint64_t seed, uint64_t t)
+                               long nz, float r, uint64_t seed, uint64_t t, uint64_t node0)
 {
     const long sx = 1, sy = nx, sz = nx * ny;
 #pragma omp parallel for schedule(static)
@@ -312,13 +314,14 @@ void oracle_heat_sweep_bf16_sr(const uint16_t *u, uint16_t *un, long nx, long ny
                      (oracle_f32_from_bf16(u[p - sy]) + oracle_f32_from_bf16(u[p + sy]))) +
                     (oracle_f32_from_bf16(u[p - sz]) + oracle_f32_from_bf16(u[p + sz]));
                 const float lap = nsum - 6.0f * c;
-                un[p] = oracle_bf16_sr_from_f32(c + r * lap, oracle_sr_bits((uint64_t)p, t, seed));
+                un[p] = oracle_bf16_sr_from_f32(c + r * lap,
+                                                oracle_sr_bits(node0 + (uint64_t)p, t, seed));
             }
 }
 
 /* `steps` such steps; step s uses t = step0 + s. */
 int oracle_heat_bf16_sr(uint16_t *u, long nx, long ny, long nz, float r, long steps,
-                        uint64_t seed, uint64_t step0)
+                        uint64_t seed, uint64_t step0, uint64_t node0)
 {
     const long n = nx * ny * nz;
     if (steps <= 0)
@@ -329,7 +332,7 @@ int oracle_heat_bf16_sr(uint16_t *u, long nx, long ny, long nz, float r, long st
     memcpy(w, u, (size_t)n * sizeof(uint16_t));
     uint16_t *a = u, *b = w;
     for (long s = 0; s < steps; ++s) {
-        oracle_heat_sweep_bf16_sr(a, b, nx, ny, nz, r, seed, step0 + (uint64_t)s);
+        oracle_heat_sweep_bf16_sr(a, b, nx, ny, nz, r, seed, step0 + (uint64_t)s, node0);
         uint16_t *tmp = a;
         a = b;
         b = tmp;

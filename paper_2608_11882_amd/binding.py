@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "cg_solve",
+__all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step_sr", "cg_solve",
            "cg_workspace_bytes", "lap7_apply", "copy_probe", "prof_enable",
            "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV", "set_tiling",
            "get_tiling", "DEFAULT_TILING", "set_cg_tiling", "get_cg_tiling",
@@ -56,6 +56,7 @@ def load():
     sig = {
         "heat_step": (i, [vp, vp, i, i, i, d, i]),
         "heat_step_ex": (i, [vp, vp, i, i, i, d, i, i, i, i, vp]),
+        "heat_step_sr": (i, [vp, vp, i, i, i, d, i, ctypes.c_uint64, ctypes.c_uint64, i, i, vp]),
         "cg_solve": (i, [vp, vp, i, d, i]),
         "cg_solve_ex": (i, [vp, vp, i, i, i, d, i, vp, sz, vp, ip, dp]),
         "cg_workspace_bytes": (sz, [i, i, i]),
@@ -135,6 +136,23 @@ def heat_step(u, u_new, r: float, steps: int, mode: str = "split", parts: int = 
     _check(lib.heat_step_ex(ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(u_new.data_ptr()),
                             nx, ny, nz, float(r), int(steps), _dtype_code(u), MODES[mode],
                             int(parts), _stream_handle(u, stream)))
+
+
+def heat_step_sr(u, u_new, r: float, steps: int, seed: int, step0: int = 0, mode: str = "split",
+                 parts: int = 1, stream=None) -> None:
+    """bfloat16 steps with stochastic rounding (torch.bfloat16 tensors): the
+    random bits of node p at step step0 + s come from Philox4x32-10 keyed by
+    ``seed``.  Otherwise as heat_step."""
+    import torch
+    _require_cuda_3d(u, u_new)
+    if u.dtype != torch.bfloat16:
+        raise TypeError("heat_step_sr needs torch.bfloat16 tensors")
+    nz, ny, nx = u.shape
+    lib = load()
+    _check(lib.heat_step_sr(ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(u_new.data_ptr()),
+                            nx, ny, nz, float(r), int(steps), int(seed) & (2 ** 64 - 1),
+                            int(step0) & (2 ** 64 - 1), MODES[mode], int(parts),
+                            _stream_handle(u, stream)))
 
 
 def cg_workspace_bytes(nx: int, ny: int, nz: int) -> int:

@@ -20,9 +20,13 @@ SOURCES = ["abi.cpp", "heat_kernels.hip", "cg_kernels.hip", "probe.hip"]
 ARCH = "gfx950"
 # No floating-point contraction anywhere: the FP64 results are bit-identical
 # to a serial evaluation of the same written expressions.  Packed FP32
-# instructions are disabled.
+# instructions are disabled.  The z-marching kernels rely on their plane
+# loops being unrolled in full (so the register queue along z is renamed,
+# not indexed); the pragma-unroll size limit is raised so that the widest
+# bodies (8-node lanes with stochastic rounding) still unroll.
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-pragma-unroll-threshold=65536",
          "-Wall", "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
 
 

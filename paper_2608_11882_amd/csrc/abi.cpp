@@ -87,8 +87,9 @@ hc::HeatTiling auto_tiling(int dtype, int nx) {
 // one, then the one-node shape when vec nodes per lane do not fit (rows that
 // are not whole lanes, or arrays not aligned to a lane).
 hc::HeatTiling heat_tiling_for(int dtype, int nx, const void *u, const void *un) {
-    hc::HeatTiling til = current_tiling(dtype);
-    if (til.vec == 0) til = auto_tiling(dtype, nx);
+    const int tdt = dtype == hc::kDtypeBF16SR ? hc::kDtypeBF16 : dtype;  // same storage
+    hc::HeatTiling til = current_tiling(tdt);
+    if (til.vec == 0) til = auto_tiling(tdt, nx);
     const uintptr_t lane_bytes = (uintptr_t)til.vec * (uintptr_t)hc::dtype_bytes(dtype);
     if (til.vec > 1 && ((nx % til.vec) || (reinterpret_cast<uintptr_t>(u) % lane_bytes) ||
                         (reinterpret_cast<uintptr_t>(un) % lane_bytes)))
@@ -288,7 +289,7 @@ double tile_algo_bytes(const hc::ZTable &t, int nx, int ny, int nz, size_t elem)
 }
 
 int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int steps, int mode,
-             int parts, hipStream_t s) {
+             int parts, unsigned long long seed, unsigned long long step0, hipStream_t s) {
     DevState *d = nullptr;
     int rc = device_state(&d);
     if (rc) return rc;
@@ -330,11 +331,12 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     for (int st = 0; st < steps; ++st) {
         if (mode == HC_HEAT_PLAIN) {
             Timed tm(hc::K_HEAT_PLAIN, s, plain_bytes);
-            HC_TRY(hc::launch_heat_plain(dtype, a, b, nx, ny, nz, r, s), "heat_plain launch");
+            HC_TRY(hc::launch_heat_plain(dtype, a, b, nx, ny, nz, r, seed, step0 + st, s), "heat_plain launch");
             tm.done();
         } else if (mode == HC_HEAT_FUSED) {
             Timed tm(hc::K_HEAT_FUSED, s, bytes_in);
-            HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_FUSED, a, b, nx, ny, r, tin, til, s),
+            HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_FUSED, a, b, nx, ny, r, tin, til, seed,
+                                        step0 + st, s),
                    "heat_fused launch");
             tm.done();
         } else {
@@ -343,13 +345,14 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
             {
                 Timed tm(hc::K_HEAT_BOUNDARY, d->aux, bytes_bd);
                 HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_BOUNDARY, a, b, nx, ny, r, tbd, til,
-                                            d->aux),
+                                            seed, step0 + st, d->aux),
                        "heat_boundary launch");
                 tm.done();
             }
             if (tin.n > 0) {
                 Timed tm(hc::K_HEAT_INTERIOR, s, bytes_in);
-                HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_INTERIOR, a, b, nx, ny, r, tin, til, s),
+                HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_INTERIOR, a, b, nx, ny, r, tin, til, seed,
+                                            step0 + st, s),
                        "heat_interior launch");
                 tm.done();
             }
@@ -512,7 +515,21 @@ int heat_step_ex(void *u, void *u_new, int nx, int ny, int nz, double r, int ste
     if (steps == 0) return HC_OK;
     if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
     if ((rc = check_device_buffer(u_new, bytes, "u_new"))) return rc;
-    return heat_run(dtype, u, u_new, nx, ny, nz, r, steps, mode, parts,
+    return heat_run(dtype, u, u_new, nx, ny, nz, r, steps, mode, parts, 0, 0,
+                    reinterpret_cast<hipStream_t>(stream));
+}
+
+int heat_step_sr(void *u, void *u_new, int nx, int ny, int nz, double r, int steps,
+                 unsigned long long seed, unsigned long long step0, int mode, int parts,
+                 hc_stream_t stream) {
+    g_msg.clear();
+    size_t bytes = 0;
+    int rc = validate_heat(u, u_new, nx, ny, nz, r, steps, HC_BF16, mode, parts, &bytes);
+    if (rc) return rc;
+    if (steps == 0) return HC_OK;
+    if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
+    if ((rc = check_device_buffer(u_new, bytes, "u_new"))) return rc;
+    return heat_run(hc::kDtypeBF16SR, u, u_new, nx, ny, nz, r, steps, mode, parts, seed, step0,
                     reinterpret_cast<hipStream_t>(stream));
 }
 

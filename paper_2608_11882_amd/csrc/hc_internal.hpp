@@ -55,17 +55,20 @@ int ztable_blocks(const ZTable &zt);
 // Grid size of a z-marching launch over table zt.
 long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt);
 int tile_width(const HeatTiling &t);
-// Storage precision codes (same values as hc_dtype): 0 FP64, 1 FP32,
-// 2 bfloat16 storage with FP32 arithmetic.
-constexpr int kDtypeF64 = 0, kDtypeF32 = 1, kDtypeBF16 = 2;
+// Storage precision codes (0-2: the values of hc_dtype): 0 FP64, 1 FP32,
+// 2 bfloat16 storage with FP32 arithmetic rounded to nearest even, 3 the
+// same with stochastic rounding (heat_step_sr); 3 shares 2's tile shapes.
+constexpr int kDtypeF64 = 0, kDtypeF32 = 1, kDtypeBF16 = 2, kDtypeBF16SR = 3;
 inline int dtype_bytes(int dtype) { return dtype == 0 ? 8 : dtype == 1 ? 4 : 2; }
 bool heat_tiling_supported(int dtype, const HeatTiling &t);
-// u and un hold nodes of the storage type of `dtype`.
+// u and un hold nodes of the storage type of `dtype`.  seed and step key the
+// random bits of the stochastic rounding (ignored by the other precisions).
 hipError_t launch_heat_tile(int dtype, KernelKind kind, const void *u, void *un, int nx,
                             int ny, double r, const ZTable &zt, const HeatTiling &t,
-                            hipStream_t s);
+                            unsigned long long seed, unsigned long long step, hipStream_t s);
 hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny, int nz,
-                             double r, hipStream_t s);
+                             double r, unsigned long long seed, unsigned long long step,
+                             hipStream_t s);
 hipError_t launch_copy_faces(int elem_bytes, const void *u, void *un, int nx, int ny, int nz,
                              hipStream_t s);
 

@@ -40,12 +40,14 @@ namespace hc {
 struct PrecF64 {
     using S = double;  // stored
     using C = double;  // arithmetic
+    static constexpr bool kStochastic = false;
     __device__ static C widen(S v) { return v; }
     __device__ static S narrow(C v) { return v; }
 };
 struct PrecF32 {
     using S = float;
     using C = float;
+    static constexpr bool kStochastic = false;
     __device__ static C widen(S v) { return v; }
     __device__ static S narrow(C v) { return v; }
 };
@@ -56,12 +58,34 @@ struct PrecF32 {
 struct PrecBF16 {
     using S = unsigned short;
     using C = float;
+    static constexpr bool kStochastic = false;
     __device__ static C widen(S v) { return __uint_as_float((unsigned)v << 16); }
     __device__ static S narrow(C v) {
         const unsigned u = __float_as_uint(v);
         if ((u & 0x7fffffffu) > 0x7f800000u) return (S)((u >> 16) | 0x40u);
         return (S)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
     }
+};
+// bfloat16 storage with stochastic rounding: a new value is rounded up in
+// magnitude exactly when its 16 discarded bits plus 16 random bits carry
+// into the kept part, i.e. with probability (discarded bits) / 2^16, which
+// makes the rounding unbiased; values that are already bfloat16 are kept.
+struct PrecBF16SR {
+    using S = unsigned short;
+    using C = float;
+    static constexpr bool kStochastic = true;
+    __device__ static C widen(S v) { return PrecBF16::widen(v); }
+    __device__ static S narrow_sr(C v, unsigned rho) {
+        const unsigned u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (S)((u >> 16) | 0x40u);
+        return (S)((u + rho) >> 16);
+    }
+};
+
+// Key and step of the stochastic rounding (unused by the other precisions).
+struct SRKey {
+    unsigned k0, k1;  // seed, low and high words
+    unsigned t0, t1;  // step index, low and high words
 };
 
 namespace {
@@ -93,6 +117,64 @@ template <> struct Raw<4> { using T = unsigned int; };
 template <> struct Raw<8> { using T = u32x2; };
 template <> struct Raw<16> { using T = u32x4; };
 
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of
+// two 32x32->64-bit products on counter words 0 and 2, whose halves are
+// recombined with words 1 and 3 and the key; the key advances by two Weyl
+// constants between rounds.  The key is the same in every lane.
+struct U32x4 {
+    unsigned x, y, z, w;
+};
+__device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, unsigned k0, unsigned k1) {
+    // kept as a loop: unrolled, ten rounds per plane would push the fully
+    // unrolled z-march past the compiler's unrolling limit
+#pragma unroll 1
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
+        const U32x4 n = {(unsigned)(p1 >> 32) ^ c.y ^ k0, (unsigned)p1,
+                         (unsigned)(p0 >> 32) ^ c.w ^ k1, (unsigned)p0};
+        c = n;
+    }
+    return c;
+}
+
+// The 16 random bits of nodes p0 .. p0+VEC-1 (p0 a multiple of VEC, VEC a
+// divisor of 8, so all lie in one aligned group of 8 nodes): the group
+// g = p0 / 8 draws the block with counter (g, step) and key seed; node p
+// takes word (p mod 8) / 2, low half for even p, high half for odd p.
+template <int VEC>
+__device__ __forceinline__ void sr_bits(long long p0, const SRKey &key, unsigned *rho) {
+    const unsigned long long g = (unsigned long long)p0 >> 3;
+    const U32x4 w = philox4x32_10({(unsigned)g, (unsigned)(g >> 32), key.t0, key.t1}, key.k0,
+                                  key.k1);
+    const unsigned base = (unsigned)p0 & 7u;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        const unsigned q = base + v;  // < 8
+        const unsigned wd = (q >> 1) == 0 ? w.x : (q >> 1) == 1 ? w.y : (q >> 1) == 2 ? w.z : w.w;
+        rho[v] = (q & 1u) ? (wd >> 16) : (wd & 0xffffu);
+    }
+}
+
+// Round VEC new values of nodes p0.. to storage.
+template <class P, int VEC>
+__device__ __forceinline__ void narrow_vec(const typename P::C *v, typename P::S *o,
+                                           long long p0, const SRKey &key) {
+    if constexpr (P::kStochastic) {
+        unsigned rho[VEC];
+        sr_bits<VEC>(p0, key, rho);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = P::narrow_sr(v[e], rho[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = P::narrow(v[e]);
+    }
+}
+
 template <class P, int VEC>
 __device__ __forceinline__ void load_vec(const typename P::S *__restrict__ p,
                                          typename P::C *o) {
@@ -106,11 +188,11 @@ __device__ __forceinline__ void load_vec(const typename P::S *__restrict__ p,
 
 template <class P, int VEC>
 __device__ __forceinline__ void store_vec_nt(typename P::S *__restrict__ p,
-                                             const typename P::C *v) {
+                                             const typename P::C *v, long long p0,
+                                             const SRKey &key) {
     using R = typename Raw<VEC * sizeof(typename P::S)>::T;
     typename P::S s[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) s[e] = P::narrow(v[e]);
+    narrow_vec<P, VEC>(v, s, p0, key);
     R raw;
     __builtin_memcpy(&raw, s, sizeof raw);
     __builtin_nontemporal_store(raw, reinterpret_cast<R *>(p));
@@ -224,7 +306,7 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
                                                 typename P::S *__restrict__ un, int nx,
                                                 int ny, typename P::C r,
                                                 const ZTable &zt, int ntx,
-                                                int nty, int xcd) {
+                                                int nty, int xcd, const SRKey &key) {
     using C = typename P::C;
     using S = typename P::S;
     using G = TileGeom<VEC, WX, BY>;
@@ -292,7 +374,7 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
             __syncthreads();
             C out[VEC];
             update(q[s], q[s + 1], q[s + 2], out);
-            store_vec_nt<P, VEC>(vo + kp, out);
+            store_vec_nt<P, VEC>(vo + kp, out, g.own + kp, key);
             if (s + 2 + PF <= ZB + 1) load_vec<P, VEC>(uo + kp + (1 + PF) * plane, q[s + 2 + PF]);
         }
         return;
@@ -314,7 +396,7 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
         __syncthreads();
         C out[VEC];
         update(zm, c, zp, out);
-        store_vec_nt<P, VEC>(vo + kp, out);
+        store_vec_nt<P, VEC>(vo + kp, out, g.own + kp, key);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             zm[v] = c[v];
@@ -329,22 +411,22 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
 template <class P, int VEC, int WX, int BY, int PF, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void heat_interior(
     const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
-    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd, SRKey key) {
+    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd, key);
 }
 
 template <class P, int VEC, int WX, int BY, int PF, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void heat_boundary(
     const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
-    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd, SRKey key) {
+    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd, key);
 }
 
 template <class P, int VEC, int WX, int BY, int PF, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void heat_fused(
     const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
-    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {
-    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd);
+    int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd, SRKey key) {
+    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, nx, ny, r, zt, ntx, nty, xcd, key);
 }
 
 // One thread per interior node, all seven values loaded from memory: the
@@ -352,7 +434,7 @@ __global__ __launch_bounds__(64 * WX * BY) void heat_fused(
 template <class P>
 __global__ __launch_bounds__(256) void heat_plain(
     const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
-    int ny, int nz, typename P::C r) {
+    int ny, int nz, typename P::C r, SRKey key) {
     using C = typename P::C;
     const int i = 1 + (int)blockIdx.x * 64 + (int)threadIdx.x;
     const int j = 1 + (int)blockIdx.y * 4 + (int)threadIdx.y;
@@ -365,7 +447,8 @@ __global__ __launch_bounds__(256) void heat_plain(
                     (P::widen(u[p - sy]) + P::widen(u[p + sy]))) +
                    (P::widen(u[p - sz]) + P::widen(u[p + sz]));
     const C lap = nsum - C(6) * c;
-    un[p] = P::narrow(c + r * lap);
+    const C out = c + r * lap;
+    narrow_vec<P, 1>(&out, &un[p], p, key);
 }
 
 // Copy the outermost layer (the Dirichlet data) of u into un.
@@ -437,7 +520,7 @@ bool heat_tiling_supported(int dtype, const HeatTiling &t) {
 #define HC_X(V, W, B, P, Z) if (key == HC_SHAPE_KEY(V, W, B, P, Z)) return true;
     if (dtype == 0) { HC_HEAT_SHAPES_F64(HC_X) }
     if (dtype == 1) { HC_HEAT_SHAPES_F32(HC_X) }
-    if (dtype == 2) { HC_HEAT_SHAPES_BF16(HC_X) }
+    if (dtype == 2 || dtype == 3) { HC_HEAT_SHAPES_BF16(HC_X) }
 #undef HC_X
     return false;
 }
@@ -445,7 +528,7 @@ bool heat_tiling_supported(int dtype, const HeatTiling &t) {
 template <class P>
 static hipError_t launch_tile(KernelKind kind, const void *u, void *un, int nx, int ny,
                               double r, const ZTable &zt, const HeatTiling &t,
-                              hipStream_t s) {
+                              const SRKey &key, hipStream_t s) {
     using S = typename P::S;
     using C = typename P::C;
     const long long nb = heat_tile_blocks(nx, ny, t, zt);
@@ -458,60 +541,67 @@ static hipError_t launch_tile(KernelKind kind, const void *u, void *un, int nx, 
     const S *us = static_cast<const S *>(u);
     S *uns = static_cast<S *>(un);
     const C rc = (C)r;
-    const int key = HC_SHAPE_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
+    const int shape = HC_SHAPE_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
 #define HC_X(V, W, B, PF, Z)                                                     \
-    if (key == HC_SHAPE_KEY(V, W, B, PF, Z)) {                                   \
+    if (shape == HC_SHAPE_KEY(V, W, B, PF, Z)) {                                 \
         if (kind == K_HEAT_INTERIOR)                                             \
             heat_interior<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(             \
-                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd);                       \
+                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd, key);                  \
         else if (kind == K_HEAT_BOUNDARY)                                        \
             heat_boundary<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(             \
-                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd);                       \
+                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd, key);                  \
         else                                                                     \
             heat_fused<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(                \
-                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd);                       \
+                us, uns, nx, ny, rc, zt, ntx, nty, t.xcd, key);                  \
         return hipGetLastError();                                                \
     }
     if constexpr (std::is_same<P, PrecF64>::value) {
         HC_HEAT_SHAPES_F64(HC_X)
     } else if constexpr (std::is_same<P, PrecF32>::value) {
         HC_HEAT_SHAPES_F32(HC_X)
-    } else {
+    } else {  // both bfloat16 forms
         HC_HEAT_SHAPES_BF16(HC_X)
     }
 #undef HC_X
     return hipErrorInvalidValue;
 }
 
+static SRKey make_key(unsigned long long seed, unsigned long long step) {
+    return {(unsigned)seed, (unsigned)(seed >> 32), (unsigned)step, (unsigned)(step >> 32)};
+}
+
 hipError_t launch_heat_tile(int dtype, KernelKind kind, const void *u, void *un, int nx,
                             int ny, double r, const ZTable &zt, const HeatTiling &t,
-                            hipStream_t s) {
+                            unsigned long long seed, unsigned long long step, hipStream_t s) {
+    const SRKey key = make_key(seed, step);
     switch (dtype) {
-        case 0: return launch_tile<PrecF64>(kind, u, un, nx, ny, r, zt, t, s);
-        case 1: return launch_tile<PrecF32>(kind, u, un, nx, ny, r, zt, t, s);
-        case 2: return launch_tile<PrecBF16>(kind, u, un, nx, ny, r, zt, t, s);
+        case kDtypeF64: return launch_tile<PrecF64>(kind, u, un, nx, ny, r, zt, t, key, s);
+        case kDtypeF32: return launch_tile<PrecF32>(kind, u, un, nx, ny, r, zt, t, key, s);
+        case kDtypeBF16: return launch_tile<PrecBF16>(kind, u, un, nx, ny, r, zt, t, key, s);
+        case kDtypeBF16SR: return launch_tile<PrecBF16SR>(kind, u, un, nx, ny, r, zt, t, key, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny, int nz,
-                             double r, hipStream_t s) {
+template <class P>
+static void plain(const void *u, void *un, int nx, int ny, int nz, double r, const SRKey &key,
+                  hipStream_t s) {
+    using S = typename P::S;
+    using C = typename P::C;
     const dim3 grid((nx - 2 + 63) / 64, (ny - 2 + 3) / 4, nz - 2), block(64, 4);
+    heat_plain<P><<<grid, block, 0, s>>>(static_cast<const S *>(u), static_cast<S *>(un), nx, ny,
+                                         nz, (C)r, key);
+}
+
+hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny, int nz,
+                             double r, unsigned long long seed, unsigned long long step,
+                             hipStream_t s) {
+    const SRKey key = make_key(seed, step);
     switch (dtype) {
-        case 0:
-            heat_plain<PrecF64><<<grid, block, 0, s>>>(static_cast<const double *>(u),
-                                                       static_cast<double *>(un), nx, ny, nz, r);
-            break;
-        case 1:
-            heat_plain<PrecF32><<<grid, block, 0, s>>>(static_cast<const float *>(u),
-                                                       static_cast<float *>(un), nx, ny, nz,
-                                                       (float)r);
-            break;
-        case 2:
-            heat_plain<PrecBF16><<<grid, block, 0, s>>>(
-                static_cast<const unsigned short *>(u), static_cast<unsigned short *>(un), nx,
-                ny, nz, (float)r);
-            break;
+        case kDtypeF64: plain<PrecF64>(u, un, nx, ny, nz, r, key, s); break;
+        case kDtypeF32: plain<PrecF32>(u, un, nx, ny, nz, r, key, s); break;
+        case kDtypeBF16: plain<PrecBF16>(u, un, nx, ny, nz, r, key, s); break;
+        case kDtypeBF16SR: plain<PrecBF16SR>(u, un, nx, ny, nz, r, key, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

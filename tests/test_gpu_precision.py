@@ -243,3 +243,85 @@ def test_full_size_bf16_500_steps_keeps_the_maximum_principle(gpu):
     uf = u.float()
     assert torch.isfinite(uf).all().item()
     assert uf.min().item() >= lo and uf.max().item() <= hi
+
+
+# ---- bfloat16 with stochastic rounding ------------------------------------------------
+
+def gpu_heat_sr(hc, u0, r, steps, seed, step0=0, mode="split", parts=1):
+    u = to_device(u0)
+    un = torch.empty_like(u)
+    hc.heat_step_sr(u, un, r, steps, seed, step0=step0, mode=mode, parts=parts)
+    torch.cuda.synchronize()
+    return to_host(u)
+
+
+@pytest.mark.parametrize("mode", ["split", "fused", "plain"])
+def test_sr_small_config_bitwise(gpu, mode):
+    cfg = inputs.HEAT_SMALL
+    note("heat bf16-sr 66^3 r=0.1 100 steps mode=%s" % mode)
+    u0 = inputs.sine_field_lowp(66, 66, 66, 1e-3, cfg["seed"], "bf16")
+    want = oracle.heat_bf16_sr(u0, cfg["r"], cfg["steps"], seed=20260)
+    got = gpu_heat_sr(gpu, u0, cfg["r"], cfg["steps"], 20260, mode=mode)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dims", [(67, 35, 20), (130, 9, 40), (3, 3, 3), (1030, 13, 5),
+                                  (520, 66, 37), (1024, 12, 36), (12, 5, 70)])
+def test_sr_ragged_shapes_bitwise(gpu, dims):
+    note("heat bf16-sr ragged %s" % (dims,))
+    u0 = field(dims, dims[0] + dims[1] + dims[2], "bf16")
+    want = oracle.heat_bf16_sr(u0, 0.15, 7, seed=3, step0=11)
+    for mode in ("split", "fused"):
+        assert np.array_equal(gpu_heat_sr(gpu, u0, 0.15, 7, 3, step0=11, mode=mode), want), mode
+
+
+def test_sr_every_tile_shape_parts_and_64_bit_keys(gpu):
+    dims = (2056, 37, 75)
+    u0 = field(dims, 32, "bf16")
+    seed, step0 = 0x1234_5678_9ABC_DEF0, (1 << 33) + 5
+    want = oracle.heat_bf16_sr(u0, 1.0 / 6.5, 5, seed=seed, step0=step0)
+    shapes = built_shapes("bf16")
+    try:
+        for shape in shapes:
+            note("heat bf16-sr tiling %s" % (shape,))
+            gpu.set_tiling(*shape, xcd=3, dtype="bf16")
+            assert np.array_equal(gpu_heat_sr(gpu, u0, 1.0 / 6.5, 5, seed, step0=step0), want), shape
+    finally:
+        gpu.set_tiling(dtype="bf16")
+    for parts in (2, 7):
+        note("heat bf16-sr parts=%d" % parts)
+        assert np.array_equal(gpu_heat_sr(gpu, u0, 1.0 / 6.5, 5, seed, step0=step0, parts=parts),
+                              want)
+
+
+def test_sr_calls_compose_and_depend_on_seed(gpu):
+    dims = (256, 20, 30)
+    u0 = field(dims, 8, "bf16")
+    note("heat bf16-sr composition")
+    u = to_device(u0)
+    un = torch.empty_like(u)
+    gpu.heat_step_sr(u, un, 0.12, 4, 77, step0=0)
+    gpu.heat_step_sr(u, un, 0.12, 5, 77, step0=4)
+    torch.cuda.synchronize()
+    whole = gpu_heat_sr(gpu, u0, 0.12, 9, 77)
+    assert np.array_equal(to_host(u), whole)
+    assert np.array_equal(whole, oracle.heat_bf16_sr(u0, 0.12, 9, seed=77))
+    assert not np.array_equal(whole, gpu_heat_sr(gpu, u0, 0.12, 9, 78))
+
+
+def test_sr_full_size_short_run_bitwise_on_slabs(gpu):
+    cfg = inputs.HEAT_PRECISION
+    n, r, steps, planes, seed = cfg["n"], cfg["r"], 3, 24, 99
+    note("heat bf16-sr %d^3 %d steps, oracle on the first and last %d planes" % (n, steps, planes))
+    u0 = inputs.sine_field_lowp(n, n, n, 1e-3, cfg["seed"], "bf16")
+    lo, hi = u0[:planes].copy(), u0[n - planes:].copy()
+    u = to_device(u0)
+    del u0
+    un = torch.empty_like(u)
+    gpu.heat_step_sr(u, un, r, steps, seed)
+    torch.cuda.synchronize()
+    got_lo, got_hi = to_host(u[:planes - steps]), to_host(u[n - planes + steps:])
+    want_lo = oracle.heat_bf16_sr(lo, r, steps, seed=seed)[:planes - steps]
+    want_hi = oracle.heat_bf16_sr(hi, r, steps, seed=seed, node0=(n - planes) * n * n)[steps:]
+    assert np.array_equal(got_lo, want_lo)
+    assert np.array_equal(got_hi, want_hi)

@@ -41,6 +41,7 @@ SR_PINS = [
     sr_pins.test_step_brackets_the_binary32_step_and_rounds_up_at_the_right_rate,
     sr_pins.test_steps_compose_and_depend_on_the_seed,
     sr_pins.test_stochastic_rounding_removes_the_stagnation,
+    sr_pins.test_slab_with_node_offset_equals_the_whole_array,
 ]
 
 MUTATIONS = {
@@ -48,8 +49,9 @@ MUTATIONS = {
     "philox_key_schedule": ("k[1] += 0xBB67AE85u;", "k[1] += 0x9E3779B9u;", SR_PINS),
     "philox_word_swap": ("const uint32_t n2 = hi0 ^ c[3] ^ k[1];", "const uint32_t n2 = hi0 ^ c[1] ^ k[1];", SR_PINS),
     "sr_off_by_one": ("lower + rho >= 0x10000u", "lower + rho > 0x10000u", SR_PINS),
-    "sr_counter_frozen": ("step0 + (uint64_t)s);", "step0);", SR_PINS),
-    "sr_uses_nearest": ("un[p] = oracle_bf16_sr_from_f32(c + r * lap, oracle_sr_bits((uint64_t)p, t, seed));",
+    "sr_counter_frozen": ("step0 + (uint64_t)s, node0);", "step0, node0);", SR_PINS),
+    "sr_node_offset_dropped": ("oracle_sr_bits(node0 + (uint64_t)p, t, seed)", "oracle_sr_bits((uint64_t)p, t, seed)", SR_PINS),
+    "sr_uses_nearest": ("un[p] = oracle_bf16_sr_from_f32(c + r * lap,\n                                                oracle_sr_bits(node0 + (uint64_t)p, t, seed));",
                         "un[p] = oracle_bf16_from_f32(c + r * lap);", SR_PINS),
     "bf16_ties_away": ("if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u)))", "if (lower >= 0x8000u)", PREC_PINS),
     "bf16_truncates": ("out = upper + 1u;", "out = upper;", PREC_PINS),

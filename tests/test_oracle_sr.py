@@ -110,3 +110,16 @@ def test_stochastic_rounding_removes_the_stagnation():
     # about one bfloat16 ulp (2^-8 relative) versus a stalled field
     assert e_sr < 2.0 ** -7
     assert e_rne > 10 * e_sr
+
+
+def test_slab_with_node_offset_equals_the_whole_array():
+    """node0 keys a slab's bits to its place in a larger array: the slab
+    [k0, k0 + m) of a whole-array run equals the slab run with node0, away
+    from the slab's cut planes (s steps reach s planes)."""
+    n, k0, m, steps = 12, 5, 7, 2
+    u0 = inputs.to_bf16_bits(inputs.uniform_field(n, n, n, seed=6))
+    whole = oracle.heat_bf16_sr(u0, 0.1, steps, seed=9)
+    part = oracle.heat_bf16_sr(u0[k0:k0 + m], 0.1, steps, seed=9, node0=k0 * n * n)
+    assert np.array_equal(part[steps:m - steps], whole[k0 + steps:k0 + m - steps])
+    unkeyed = oracle.heat_bf16_sr(u0[k0:k0 + m], 0.1, steps, seed=9)
+    assert not np.array_equal(unkeyed[steps:m - steps], whole[k0 + steps:k0 + m - steps])
