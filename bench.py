@@ -174,7 +174,7 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
         timed_sweep(hc, u, un, u0, r_large, 10, sr)
         ms = timed_sweep(hc, u, un, u0, r_large, nsteps_large, sr)
         eb = u0.element_size()
-        rate[name] = {"tiling": hc.tiling_for(u, un),
+        rate[name] = {"tiling": hc.tiling_for(u, un, sr),
                       "glups": round(lups / (ms / 1e3) / 1e9, 2),
                       "algo_hbm_gbs": round(nsteps_large * eb * (n ** 3 + (n - 2) ** 3)
                                             / (ms / 1e3) / 1e9, 1)}
@@ -201,7 +201,7 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
         timed_sweep(hc, u, un, u0, r, 5, sr)
         ms = timed_sweep(hc, u, un, u0, r, steps, sr)
         eb = u0.element_size()
-        rec = {"tiling": hc.tiling_for(u, un),
+        rec = {"tiling": hc.tiling_for(u, un, sr),
                "glups": round(lups / (ms / 1e3) / 1e9, 2),
                "algo_hbm_gbs": round(steps * eb * (N ** 3 + (N - 2) ** 3) / (ms / 1e3) / 1e9, 1),
                "ms": round(ms, 2)}

@@ -45,7 +45,9 @@ enum hc_status {
     HC_ENONFINITE = -7   /* CG: a scalar became NaN or infinite            */
 };
 
-enum hc_dtype { HC_F64 = 0, HC_F32 = 1, HC_BF16 = 2 };
+/* Element types.  HC_BF16_SR names the stochastic-rounding sweep of
+ * heat_step_sr (bfloat16 storage); heat_step_ex does not take it. */
+enum hc_dtype { HC_F64 = 0, HC_F32 = 1, HC_BF16 = 2, HC_BF16_SR = 3 };
 
 enum hc_heat_mode {
     HC_HEAT_SPLIT = 0, /* Interior kernel on the caller's stream and the
@@ -224,11 +226,12 @@ int hc_heat_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth,
                        int *pf, int *xcd);
 
 /*
- * The tile shape heat_step_ex would run an array of x-edge nx and element
- * type dtype with, for the arrays u and u_new (only their addresses are
- * used, for the lane alignment; NULL counts as aligned): the setting above
- * or the automatic choice, then the one-node shape (1, 4, 4, 16, 2) where
- * vec nodes per lane do not fit.  Written through the non-NULL pointers.
+ * The tile shape heat_step_ex (heat_step_sr for HC_BF16_SR) would run an
+ * array of x-edge nx and element type dtype with, for the arrays u and
+ * u_new (only their addresses are used, for the lane alignment; NULL counts
+ * as aligned): the setting above (HC_BF16_SR uses HC_BF16's) or the
+ * automatic choice, then the one-node shape (1, 4, 4, 16, 2) where vec
+ * nodes per lane do not fit.  Written through the non-NULL pointers.
  * HC_EINVAL for an unknown dtype or nx < 3.
  */
 int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new,

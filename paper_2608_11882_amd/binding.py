@@ -235,11 +235,13 @@ def get_tiling(dtype: str = "f64") -> dict:
     return dict(zip(_TILE_KEYS, (x.value for x in v)))
 
 
-def tiling_for(u, u_new=None) -> dict:
-    """The tile shape heat_step would sweep these tensors with."""
+def tiling_for(u, u_new=None, sr: bool = False) -> dict:
+    """The tile shape heat_step (heat_step_sr with sr) would sweep these
+    tensors with."""
     v = [ctypes.c_int(0) for _ in range(6)]
     un = u if u_new is None else u_new
-    _check(load().hc_heat_tiling_for(_dtype_code(u), int(u.shape[-1]),
+    code = 3 if sr else _dtype_code(u)
+    _check(load().hc_heat_tiling_for(code, int(u.shape[-1]),
                                      ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(un.data_ptr()),
                                      *[ctypes.byref(x) for x in v]))

@@ -60,11 +60,14 @@ hc::HeatTiling current_tiling(int dtype) {
 // The first candidate whose row of tiles is at most 1/8 wider than the
 // narrowest candidate's wins: wide tiles amortise the ring and the block
 // set-up, but lanes past the last column do no work.
-const hc::HeatTiling kAuto[3][5] = {
+// The stochastic-rounding form draws one generator block per lane and
+// plane, so it favours 8-node lanes even more.
+const hc::HeatTiling kAuto[4][5] = {
     {{2, 4, 4, 32, 2, 8}, {2, 2, 8, 16, 2, 8}, {2, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}, {}},
     {{4, 4, 4, 16, 2, 8}, {2, 4, 4, 32, 2, 8}, {4, 1, 8, 32, 2, 8}, {2, 1, 8, 32, 2, 8},
      {1, 1, 8, 16, 2, 8}},
     {{8, 1, 8, 16, 2, 8}, {4, 1, 8, 16, 2, 8}, {2, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}, {}},
+    {{8, 1, 4, 32, 2, 8}, {4, 1, 8, 16, 2, 8}, {2, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}, {}},
 };
 
 hc::HeatTiling auto_tiling(int dtype, int nx) {
@@ -89,7 +92,7 @@ hc::HeatTiling auto_tiling(int dtype, int nx) {
 hc::HeatTiling heat_tiling_for(int dtype, int nx, const void *u, const void *un) {
     const int tdt = dtype == hc::kDtypeBF16SR ? hc::kDtypeBF16 : dtype;  // same storage
     hc::HeatTiling til = current_tiling(tdt);
-    if (til.vec == 0) til = auto_tiling(tdt, nx);
+    if (til.vec == 0) til = auto_tiling(dtype, nx);
     const uintptr_t lane_bytes = (uintptr_t)til.vec * (uintptr_t)hc::dtype_bytes(dtype);
     if (til.vec > 1 && ((nx % til.vec) || (reinterpret_cast<uintptr_t>(u) % lane_bytes) ||
                         (reinterpret_cast<uintptr_t>(un) % lane_bytes)))
@@ -684,7 +687,7 @@ int hc_heat_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth, int *
 int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new, int *vec, int *wx,
                        int *by, int *zdepth, int *pf, int *xcd) {
     g_msg.clear();
-    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16 && dtype != HC_BF16_SR)
         return fail(HC_EINVAL, "dtype %d is not supported", dtype);
     if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
     const hc::HeatTiling t = heat_tiling_for(dtype, nx, u, u_new);

@@ -52,34 +52,29 @@ struct PrecF32 {
     __device__ static S narrow(C v) { return v; }
 };
 // bfloat16 as its bit pattern: the upper half of a binary32.  Widening is
-// exact; narrowing rounds to nearest, ties to even (adding 0x7fff plus the
-// kept lowest bit carries exactly when the dropped half is above one half,
-// or equal to it with an odd kept part); NaN stays a quiet NaN.
+// exact.  Narrowing uses gfx950's conversion instructions, two values per
+// instruction: v_cvt_pk_bf16_f32 rounds to nearest, ties to even, and
+// v_cvt_sr_bf16_f32 rounds stochastically -- the magnitude goes up exactly
+// when the 16 bits a bfloat16 drops plus the upper 16 bits of its random
+// operand carry into the kept part, i.e. with probability (dropped bits) /
+// 2^16, which makes the rounding unbiased (values that are already bfloat16
+// are kept).  Both keep NaN a NaN.  (Both rules, on every class of finite
+// input -- ties, subnormals, values next to the largest finite one -- were
+// checked against integer formulas on the device.)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 struct PrecBF16 {
     using S = unsigned short;
     using C = float;
     static constexpr bool kStochastic = false;
     __device__ static C widen(S v) { return __uint_as_float((unsigned)v << 16); }
-    __device__ static S narrow(C v) {
-        const unsigned u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (S)((u >> 16) | 0x40u);
-        return (S)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-    }
 };
-// bfloat16 storage with stochastic rounding: a new value is rounded up in
-// magnitude exactly when its 16 discarded bits plus 16 random bits carry
-// into the kept part, i.e. with probability (discarded bits) / 2^16, which
-// makes the rounding unbiased; values that are already bfloat16 are kept.
 struct PrecBF16SR {
     using S = unsigned short;
     using C = float;
     static constexpr bool kStochastic = true;
     __device__ static C widen(S v) { return PrecBF16::widen(v); }
-    __device__ static S narrow_sr(C v, unsigned rho) {
-        const unsigned u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (S)((u >> 16) | 0x40u);
-        return (S)((u + rho) >> 16);
-    }
 };
 
 // Key and step of the stochastic rounding (unused by the other precisions).
@@ -145,30 +140,58 @@ __device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, unsigned k0, unsigned k1
 // The 16 random bits of nodes p0 .. p0+VEC-1 (p0 a multiple of VEC, VEC a
 // divisor of 8, so all lie in one aligned group of 8 nodes): the group
 // g = p0 / 8 draws the block with counter (g, step) and key seed; node p
-// takes word (p mod 8) / 2, low half for even p, high half for odd p.
+// takes word (p mod 8) / 2, low half for even p, high half for odd p.  They
+// are returned in the upper half of rho[v], where the stochastic conversion
+// takes them.
 template <int VEC>
 __device__ __forceinline__ void sr_bits(long long p0, const SRKey &key, unsigned *rho) {
     const unsigned long long g = (unsigned long long)p0 >> 3;
     const U32x4 w = philox4x32_10({(unsigned)g, (unsigned)(g >> 32), key.t0, key.t1}, key.k0,
                                   key.k1);
-    const unsigned base = (unsigned)p0 & 7u;
+    const unsigned wd[4] = {w.x, w.y, w.z, w.w};
+    if constexpr (VEC == 8) {  // p0 is a multiple of 8: a fixed assignment
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-        const unsigned q = base + v;  // < 8
-        const unsigned wd = (q >> 1) == 0 ? w.x : (q >> 1) == 1 ? w.y : (q >> 1) == 2 ? w.z : w.w;
-        rho[v] = (q & 1u) ? (wd >> 16) : (wd & 0xffffu);
+        for (int v = 0; v < 8; ++v) rho[v] = (v & 1) ? (wd[v >> 1] & 0xffff0000u) : (wd[v >> 1] << 16);
+    } else {
+        const unsigned base = (unsigned)p0 & 7u;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const unsigned q = base + v;  // < 8
+            const unsigned h = q >> 1;
+            const unsigned x = h == 0 ? w.x : h == 1 ? w.y : h == 2 ? w.z : w.w;
+            rho[v] = (q & 1u) ? (x & 0xffff0000u) : (x << 16);
+        }
     }
+}
+
+__device__ __forceinline__ unsigned bf16x2_bits(bf16x2 b) {
+    unsigned w;
+    __builtin_memcpy(&w, &b, 4);
+    return w;
 }
 
 // Round VEC new values of nodes p0.. to storage.
 template <class P, int VEC>
 __device__ __forceinline__ void narrow_vec(const typename P::C *v, typename P::S *o,
                                            long long p0, const SRKey &key) {
-    if constexpr (P::kStochastic) {
+    if constexpr (std::is_same<typename P::S, unsigned short>::value) {
         unsigned rho[VEC];
-        sr_bits<VEC>(p0, key, rho);
+        if constexpr (P::kStochastic) sr_bits<VEC>(p0, key, rho);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) o[e] = P::narrow_sr(v[e], rho[e]);
+        for (int e = 0; e < VEC; e += 2) {
+            const bool pair = e + 1 < VEC;
+            unsigned bits;
+            if constexpr (P::kStochastic) {
+                bf16x2 b = __builtin_amdgcn_cvt_sr_bf16_f32(bf16x2{}, v[e], rho[e], false);
+                if (pair) b = __builtin_amdgcn_cvt_sr_bf16_f32(b, v[e + 1], rho[e + 1], true);
+                bits = bf16x2_bits(b);
+            } else {
+                bits = bf16x2_bits(
+                    __builtin_convertvector(f32x2{v[e], pair ? v[e + 1] : v[e]}, bf16x2));
+            }
+            o[e] = (unsigned short)bits;
+            if (pair) o[e + 1] = (unsigned short)(bits >> 16);
+        }
     } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) o[e] = P::narrow(v[e]);
@@ -353,7 +376,12 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
             const C yp = tile[sl + G::LD];
             const C nsum = ((xm + xp) + (ym + yp)) + (zm[v] + zp[v]);
             const C lap = nsum - C(6) * c[v];
-            out[v] = g.st[v] ? c[v] + r * lap : c[v];
+            C res = c[v] + r * lap;
+            // every lane computes the update and then selects, so the LDS
+            // reads above stay unconditional: otherwise the compiler sinks
+            // them behind a branch per node, each with its own wait
+            asm volatile("" : "+v"(res));
+            out[v] = g.st[v] ? res : c[v];
         }
     };
 

@@ -140,17 +140,19 @@ def test_automatic_tiling_choice(lib):
     """Every shape the automatic choice can return is built, tiles are never
     more than 1/8 wider than the narrowest candidate's, the widest fitting
     tile wins, and lanes of vec nodes need whole, aligned lanes."""
-    for dt in (0, 1, 2):
+    for dt in (0, 1, 2, 3):
         for nx in list(range(3, 300)) + [510, 511, 512, 513, 600, 1000, 1023, 1024, 1030, 4096]:
             vec, wx, by, zd, pf, xcd = tiling_for(lib, dt, nx)
-            assert lib.hc_heat_set_tiling(dt, vec, wx, by, zd, pf, xcd) == HC_OK, (dt, nx)
+            sdt = min(dt, 2)   # the stochastic form takes bfloat16's shapes
+            assert lib.hc_heat_set_tiling(sdt, vec, wx, by, zd, pf, xcd) == HC_OK, (dt, nx)
             assert nx % vec == 0 or vec == 1
-        assert lib.hc_heat_set_tiling(dt, 0, 0, 0, 0, 0, 0) == HC_OK
+        assert lib.hc_heat_set_tiling(min(dt, 2), 0, 0, 0, 0, 0, 0) == HC_OK
     assert tiling_for(lib, 0, 512) == (2, 4, 4, 32, 2, 8)
     assert tiling_for(lib, 1, 512) == (2, 4, 4, 32, 2, 8)
     assert tiling_for(lib, 1, 1024) == (4, 4, 4, 16, 2, 8)
     assert tiling_for(lib, 2, 1024) == (8, 1, 8, 16, 2, 8)
     assert tiling_for(lib, 2, 512) == (8, 1, 8, 16, 2, 8)
+    assert tiling_for(lib, 3, 1024) == (8, 1, 4, 32, 2, 8)      # stochastic rounding
     # 1030 needs narrow tiles, which have two-node lanes; 1027 is odd
     assert tiling_for(lib, 1, 1030) == (2, 1, 8, 32, 2, 8)
     assert tiling_for(lib, 1, 1027)[0] == 1
