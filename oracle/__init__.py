@@ -69,6 +69,14 @@ def _configure(lib):
     lib.oracle_bf16_sr_from_f32.argtypes = [ctypes.c_float, ctypes.c_uint16]
     lib.oracle_bf16_sr_from_f32.restype = ctypes.c_uint16
     lib.oracle_heat_bf16_sr.argtypes = [hp, L, L, L, ctypes.c_float, L, U64, U64, U64]
+    lib.oracle_lap7_apply_f32.argtypes = [fp, fp, L, L, L]
+    lib.oracle_lap7_apply_f32.restype = None
+    lib.oracle_dot_f32.argtypes = [fp, fp, L, L, L]
+    lib.oracle_dot_f32.restype = ctypes.c_double
+    LP = ctypes.POINTER(L)
+    lib.oracle_cg_ir.argtypes = [dp, dp, L, L, L, ctypes.c_double, L, ctypes.c_double,
+                                 ctypes.c_double, L, LP, LP, dp, LP]
+    lib.oracle_cg_ir.restype = ctypes.c_int
     lib.oracle_heat_bf16_sr.restype = ctypes.c_int
     return lib
 
@@ -260,3 +268,52 @@ def cg(b: np.ndarray, tol: float, maxit: int, x0: np.ndarray | None = None) -> C
                            ctypes.byref(iters), ctypes.byref(rel), _ptr(hist))
     return CGResult(x, int(st), int(iters.value), float(rel.value),
                     hist[: iters.value + 1].copy())
+
+
+def lap7_apply_f32(x: np.ndarray) -> np.ndarray:
+    """y = A x in binary32 (each operation rounded), zero outside the box."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty_like(x)
+    nz, ny, nx = x.shape
+    fp = ctypes.POINTER(ctypes.c_float)
+    _load().oracle_lap7_apply_f32(x.ctypes.data_as(fp), y.ctypes.data_as(fp), nx, ny, nz)
+    return y
+
+
+def dot_f32(a: np.ndarray, b: np.ndarray) -> float:
+    """a.b of binary32 arrays, accumulated in binary64."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    if a.shape != b.shape or a.ndim != 3:
+        raise ValueError("expected two 3-D arrays of one shape")
+    nz, ny, nx = a.shape
+    fp = ctypes.POINTER(ctypes.c_float)
+    return float(_load().oracle_dot_f32(a.ctypes.data_as(fp), b.ctypes.data_as(fp), nx, ny, nz))
+
+
+class IRResult:
+    def __init__(self, x, status, iters, outer, relres_true, inner_iters):
+        self.x = x
+        self.status = status
+        self.iters = iters
+        self.outer = outer
+        self.relres_true = relres_true
+        self.inner_iters = inner_iters
+
+
+def cg_ir(b: np.ndarray, tol: float, maxit: int, inner_tol: float = 1e-5,
+          floor: float = 0.5, max_outer: int = 64, x0: np.ndarray | None = None) -> IRResult:
+    """Binary64 iterative refinement around a binary32 inner CG; see
+    ``oracle_cg_ir`` for the steps and statuses."""
+    b = _f64_c(b)
+    x = np.zeros_like(b) if x0 is None else _f64_c(x0).copy()
+    nz, ny, nx = b.shape
+    it, outer = ctypes.c_long(0), ctypes.c_long(0)
+    rel = ctypes.c_double(0.0)
+    hist = (ctypes.c_long * max_outer)()
+    st = _load().oracle_cg_ir(_ptr(b), _ptr(x), nx, ny, nz, float(tol), int(maxit),
+                              float(inner_tol), float(floor), int(max_outer),
+                              ctypes.byref(it), ctypes.byref(outer), ctypes.byref(rel), hist)
+    if st == -4:
+        raise MemoryError("oracle_cg_ir: out of memory")
+    return IRResult(x, st, it.value, outer.value, rel.value, list(hist[:outer.value]))

@@ -510,3 +510,160 @@ int oracle_cg(const double *b, double *x, long nx, long ny, long nz, double tol,
     free(q);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Mixed precision: binary32 inner CG inside binary64 iterative refinement  */
+/* ------------------------------------------------------------------------ */
+
+/* y = A x in binary32: 6 x_p - (((x- + x+) + (y- + y+)) + (z- + z+)), each
+ * operation rounded to binary32, zero outside the box. */
+void oracle_lap7_apply_f32(const float *x, float *y, long nx, long ny, long nz)
+{
+    const long sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nz; ++k)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const float xm = (i > 0) ? x[p - 1] : 0.0f;
+                const float xp = (i < nx - 1) ? x[p + 1] : 0.0f;
+                const float ym = (j > 0) ? x[p - sy] : 0.0f;
+                const float yp = (j < ny - 1) ? x[p + sy] : 0.0f;
+                const float zm = (k > 0) ? x[p - sz] : 0.0f;
+                const float zp = (k < nz - 1) ? x[p + sz] : 0.0f;
+                const float nsum = ((xm + xp) + (ym + yp)) + (zm + zp);
+                y[p] = 6.0f * x[p] - nsum;
+            }
+}
+
+/* a.b of binary32 vectors, accumulated in binary64 (each product of two
+ * binary32 values is exact in binary64), in the order of oracle_dot. */
+double oracle_dot_f32(const float *a, const float *b, long nx, long ny, long nz)
+{
+    const long plane = nx * ny;
+    double *part = (double *)malloc((size_t)nz * sizeof(double));
+    if (!part)
+        return NAN;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nz; ++k) {
+        double s = 0.0, c = 0.0;
+        const float *pa = a + k * plane, *pb = b + k * plane;
+        for (long q = 0; q < plane; ++q)
+            neumaier_add(&s, &c, (double)pa[q] * (double)pb[q]);
+        part[k] = s + c;
+    }
+    double s = 0.0, c = 0.0;
+    for (long k = 0; k < nz; ++k)
+        neumaier_add(&s, &c, part[k]);
+    free(part);
+    return s + c;
+}
+
+/*
+ * Iterative refinement with a binary32 inner CG (the precision direction of
+ * the CG case study: the inner solve moves half the bytes, while residuals,
+ * solution updates and every dot product stay in binary64):
+ *
+ *   outer:  r = b - A x (binary64); stop if ||r|| <= tol ||b||;
+ *           s = r rounded to binary32;
+ *           d = CG in binary32 on A d = s from d = 0 (below);
+ *           x = x + d (binary64)
+ *   inner:  p = s; rho = s.s;
+ *           loop:  q = A p (binary32);  alpha = rho / (p.q)  (binary64,
+ *                  then rounded to binary32 for the updates);
+ *                  d = d + alpha p;  s = s - alpha q  (binary32);
+ *                  rho' = s.s;  stop if sqrt(rho') <= max(inner_tol sqrt(rho_0),
+ *                  floor tol ||b||);  beta = rho'/rho (binary64, rounded);
+ *                  p = s + beta p;  rho = rho'
+ *
+ * Dot products of binary32 vectors are accumulated in binary64.  The inner
+ * stopping floor (`floor` times the outer target) keeps the last inner solve
+ * from reducing the residual far below what the outer test needs.
+ *
+ * `x` holds the initial guess on entry and the last iterate on return.
+ * *iters counts inner iterations over all outer steps (at most maxit);
+ * *outer counts outer steps (inner solves); *relres_true is the binary64
+ * ||b - A x|| / ||b|| of the returned x.  `inner_hist` (optional, up to
+ * max_outer entries) receives the inner iteration count of each outer step.
+ * Returns 0 (converged), 1 (maxit reached, or an outer step that did not
+ * reduce ||r||), -4 (no memory), -6 (p.q <= 0 on an inner solve's first
+ * iteration), -7 (a scalar went non-finite).
+ */
+int oracle_cg_ir(const double *b, double *x, long nx, long ny, long nz, double tol,
+                 long maxit, double inner_tol, double floor_frac, long max_outer,
+                 long *iters, long *outer, double *relres_true, long *inner_hist)
+{
+    const long n = nx * ny * nz;
+    *iters = 0;
+    *outer = 0;
+    *relres_true = 0.0;
+    const double bnorm = sqrt(oracle_dot(b, b, nx, ny, nz));
+    if (bnorm == 0.0) {
+        memset(x, 0, (size_t)n * sizeof(double));
+        return 0;
+    }
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    float *s = (float *)malloc((size_t)n * sizeof(float));
+    float *d = (float *)malloc((size_t)n * sizeof(float));
+    float *p = (float *)malloc((size_t)n * sizeof(float));
+    float *q = (float *)malloc((size_t)n * sizeof(float));
+    if (!r || !s || !d || !p || !q) {
+        free(r); free(s); free(d); free(p); free(q);
+        return -4;
+    }
+    int status = 1;
+    long it = 0;
+    double rprev = INFINITY;
+    for (;;) {
+        oracle_lap7_apply(x, r, nx, ny, nz);
+        for (long t = 0; t < n; ++t)
+            r[t] = b[t] - r[t];
+        const double rnorm = sqrt(oracle_dot(r, r, nx, ny, nz));
+        *relres_true = rnorm / bnorm;
+        if (!isfinite(rnorm)) { status = -7; break; }
+        if (rnorm <= tol * bnorm) { status = 0; break; }
+        if (it >= maxit || *outer >= max_outer || rnorm >= rprev) { status = 1; break; }
+        rprev = rnorm;
+
+        /* inner solve in binary32 */
+        for (long t = 0; t < n; ++t) {
+            s[t] = (float)r[t];
+            d[t] = 0.0f;
+            p[t] = s[t];
+        }
+        double rho = oracle_dot_f32(s, s, nx, ny, nz);
+        const double thresh = fmax(inner_tol * sqrt(rho), floor_frac * tol * bnorm);
+        long inner = 0;
+        int inner_status = 0;
+        while (it < maxit) {
+            oracle_lap7_apply_f32(p, q, nx, ny, nz);
+            const double pq = oracle_dot_f32(p, q, nx, ny, nz);
+            if (!isfinite(pq)) { inner_status = -7; break; }
+            if (pq <= 0.0) { inner_status = -6; break; }
+            const float alpha = (float)(rho / pq);
+            for (long t = 0; t < n; ++t) {
+                d[t] = d[t] + alpha * p[t];
+                s[t] = s[t] - alpha * q[t];
+            }
+            const double rho_new = oracle_dot_f32(s, s, nx, ny, nz);
+            ++it;
+            ++inner;
+            if (!isfinite(rho_new)) { inner_status = -7; break; }
+            if (sqrt(rho_new) <= thresh) break;
+            const float beta = (float)(rho_new / rho);
+            for (long t = 0; t < n; ++t)
+                p[t] = s[t] + beta * p[t];
+            rho = rho_new;
+        }
+        if (inner_hist)
+            inner_hist[*outer] = inner;
+        *outer += 1;
+        if (inner_status == -7) { status = -7; break; }
+        if (inner_status == -6 && inner == 0) { status = -6; break; }
+        for (long t = 0; t < n; ++t)
+            x[t] = x[t] + (double)d[t];
+    }
+    *iters = it;
+    free(r); free(s); free(d); free(p); free(q);
+    return status;
+}

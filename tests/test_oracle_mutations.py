@@ -11,6 +11,7 @@ import pytest
 import oracle
 import test_oracle_cg as cg_pins
 import test_oracle_heat as heat_pins
+import test_oracle_ir as ir_pins
 import test_oracle_precision as prec_pins
 import test_oracle_sr as sr_pins
 
@@ -44,7 +45,22 @@ SR_PINS = [
     sr_pins.test_slab_with_node_offset_equals_the_whole_array,
 ]
 
+IR_PINS = [
+    ir_pins.test_f32_operator_exact_on_small_integers_and_bounded_otherwise,
+    ir_pins.test_f32_dot_is_nearly_exact,
+    ir_pins.test_refined_solution_meets_the_condition_number_bound,
+    ir_pins.test_first_inner_solve_terminates_in_m_iterations,
+    ir_pins.test_refinement_converges_in_few_steps_near_the_f64_iteration_count,
+]
+
 MUTATIONS = {
+    "ir_update_sign": ("x[t] = x[t] + (double)d[t];", "x[t] = x[t] - (double)d[t];", IR_PINS),
+    "ir_alpha_inverted": ("const float alpha = (float)(rho / pq);", "const float alpha = (float)(pq / rho);", IR_PINS),
+    "ir_f32_operator_y_for_z": ("const float zp = (k < nz - 1) ? x[p + sz] : 0.0f;",
+                                "const float zp = (k < nz - 1) ? x[p + sy] : 0.0f;", IR_PINS),
+    "ir_f32_dot_squares_a": ("neumaier_add(&s, &c, (double)pa[q] * (double)pb[q]);",
+                             "neumaier_add(&s, &c, (double)pa[q] * (double)pa[q]);", IR_PINS),
+    "ir_inner_direction_drops_beta": ("p[t] = s[t] + beta * p[t];", "p[t] = s[t] + beta * s[t];", IR_PINS),
     "philox_multiplier": ("(uint64_t)0xD2511F53u * c[0]", "(uint64_t)0xD2511F55u * c[0]", SR_PINS),
     "philox_key_schedule": ("k[1] += 0xBB67AE85u;", "k[1] += 0x9E3779B9u;", SR_PINS),
     "philox_word_swap": ("const uint32_t n2 = hi0 ^ c[3] ^ k[1];", "const uint32_t n2 = hi0 ^ c[1] ^ k[1];", SR_PINS),
