@@ -252,6 +252,60 @@ void hc_cg_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd);
 /* Name of a status code (static string). */
 const char *hc_strerror(int code);
 
+/*
+ * cg_solve_ir -- the same system solved by iterative refinement around a
+ * binary32 inner CG, the precision direction of the CG case study: the
+ * inner iterations move 32 bytes per unknown instead of 64, while the
+ * residual b - A x, the solution updates and every dot product stay in
+ * binary64, so the accuracy reached is that of binary64 CG.
+ *
+ *   outer:  r = b - A x (binary64); stop when ||r|| <= tol ||b|| (the true
+ *           residual: no restart is needed); s = r rounded to binary32;
+ *           d = inner CG on A d = s from d = 0; x = x + d (binary64).
+ *   inner:  textbook CG with binary32 vectors and arithmetic (operator
+ *           6 p - neighbours, updates d + alpha p, s - alpha q, directions
+ *           s + beta p), dot products accumulated in binary64, alpha and
+ *           beta computed in binary64 and rounded to binary32; it stops at
+ *           ||s|| <= max(inner_tol ||s_0||, 0.5 tol ||b||).
+ *
+ *  b, x, nx, ny, nz, tol   as cg_solve_ex.
+ *  maxit      >= 0 inner iterations in total over all outer steps.
+ *  inner_tol  relative reduction of each inner solve, < 1; <= 0 selects
+ *             1e-5.
+ *  work       NULL (the library's cached workspace) or at least
+ *             cg_ir_workspace_bytes(nx, ny, nz) bytes of device memory.
+ *  iters, outer, true_relres  optional outputs: inner iterations, outer
+ *             steps, binary64 ||b - A x|| / ||b|| of the returned x.
+ * Blocks until done.  Returns HC_OK, HC_ENOTCONV (maxit reached, or an
+ * outer step that did not reduce ||r||, or 64 outer steps; x holds the last
+ * iterate), HC_EBREAKDOWN (p.Ap <= 0 at the start of an inner solve) or
+ * HC_ENONFINITE; ||b|| = 0 sets x = 0 and returns HC_OK.
+ */
+int cg_solve_ir(const double *b, double *x, int nx, int ny, int nz, double tol,
+                int maxit, double inner_tol, void *work, size_t work_bytes,
+                hc_stream_t stream, int *iters, int *outer, double *true_relres);
+
+/* Bytes of the workspace cg_solve_ir needs (0 for an empty box). */
+size_t cg_ir_workspace_bytes(int nx, int ny, int nz);
+
+/*
+ * hc_lap7_apply_f32 -- y = A x for binary32 arrays, each operation of
+ * 6 x_p - (((x- + x+) + (y- + y+)) + (z- + z+)) rounded to binary32 (the
+ * inner operator of cg_solve_ir).  Same rules as hc_lap7_apply.
+ */
+int hc_lap7_apply_f32(const float *x, float *y, int nx, int ny, int nz,
+                      hc_stream_t stream);
+
+/*
+ * Tile shape of the binary32 inner CG kernels of cg_solve_ir and of
+ * hc_lap7_apply_f32 (same meaning as hc_cg_set_tiling; vec up to 4, i.e.
+ * 16-byte lanes, used when nx is a multiple of vec and the vectors are
+ * aligned to a lane).  The shapes built are listed in cg_kernels.hip
+ * (HC_CG_SHAPES_F32).  Default: vec 4, wx 1, by 8, zdepth 32, xcd 8.
+ */
+int hc_cg_ir_set_tiling(int vec, int wx, int by, int zdepth, int xcd);
+void hc_cg_ir_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd);
+
 /* Detail of the last failure on the calling thread ("" if none). */
 const char *hc_last_error_message(void);
 
@@ -275,7 +329,11 @@ enum hc_kernel_kind {
     HC_K_CG_RESIDUAL = 6,  /* r = b - A x, r.r, b.b      */
     HC_K_LAP7 = 7,
     HC_K_COPY = 8,
-    HC_K_COUNT = 9
+    HC_K_CG32_DIRECTION = 9,  /* the same, binary32 (refinement) */
+    HC_K_CG32_UPDATE = 10,    /* d += alpha p, s -= alpha A p, s.s */
+    HC_K_IR_RESIDUAL = 11,    /* r = b - A x, s = (float) r, sums */
+    HC_K_IR_UPDATE = 12,      /* x += d                        */
+    HC_K_COUNT = 13
 };
 int hc_prof_enable(int every);
 int hc_prof_read(int kind, double *total_ms, long long *launches,

@@ -16,7 +16,8 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "prof_read", "strerror", "KERNELS", "HC_OK", "HC_ENOTCONV", "set_tiling",
            "get_tiling", "DEFAULT_TILING", "set_cg_tiling", "get_cg_tiling",
            "DEFAULT_CG_TILING", "DTYPES", "HC_F64", "HC_F32", "HC_BF16",
-           "AUTO_TILING", "tiling_for"]
+           "AUTO_TILING", "tiling_for", "cg_solve_ir", "cg_ir_workspace_bytes",
+           "lap7_apply_f32", "set_cg_ir_tiling", "get_cg_ir_tiling", "DEFAULT_CG_IR_TILING"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -25,7 +26,8 @@ HC_OK, HC_ENOTCONV = 0, 1
 HC_F64, HC_F32, HC_BF16 = 0, 1, 2
 MODES = {"split": 0, "fused": 1, "plain": 2}
 KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain": 3,
-           "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8}
+           "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8,
+           "cg32_direction": 9, "cg32_update": 10, "ir_residual": 11, "ir_update": 12}
 
 _lib = None
 
@@ -71,6 +73,11 @@ def load():
         "hc_heat_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
         "hc_heat_tiling_for": (i, [i, i, vp, vp, ip, ip, ip, ip, ip, ip]),
         "hc_cg_set_tiling": (i, [i, i, i, i, i]),
+        "hc_cg_ir_set_tiling": (i, [i, i, i, i, i]),
+        "hc_cg_ir_get_tiling": (None, [ip, ip, ip, ip, ip]),
+        "cg_solve_ir": (i, [vp, vp, i, i, i, d, i, d, vp, sz, vp, ip, ip, dp]),
+        "cg_ir_workspace_bytes": (sz, [i, i, i]),
+        "hc_lap7_apply_f32": (i, [vp, vp, i, i, i, vp]),
         "hc_cg_get_tiling": (None, [ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
@@ -184,6 +191,50 @@ def cg_solve(b, x, tol: float, maxit: int, work=None, stream=None):
     return st, it.value, rel.value
 
 
+def cg_ir_workspace_bytes(nx: int, ny: int, nz: int) -> int:
+    return int(load().cg_ir_workspace_bytes(nx, ny, nz))
+
+
+def cg_solve_ir(b, x, tol: float, maxit: int, inner_tol: float = 0.0, work=None, stream=None):
+    """Solve A x = b by binary64 iterative refinement around a binary32
+    inner CG (in place in ``x``, float64 tensors).
+
+    Returns (status, inner iterations, outer steps, true relative residual);
+    status is 0 (converged) or 1 (not converged).  inner_tol <= 0 takes the
+    library default.  Errors raise HeatCGError.
+    """
+    import torch
+    _require_cuda_3d(b, x)
+    if b.dtype != torch.float64:
+        raise TypeError("cg_solve_ir works on float64 tensors")
+    nz, ny, nx = b.shape
+    it, out = ctypes.c_int(0), ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    wptr, wbytes = None, 0
+    if work is not None:
+        if not work.is_cuda or not work.is_contiguous():
+            raise ValueError("work must be a contiguous CUDA tensor")
+        wptr, wbytes = ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size()
+    st = load().cg_solve_ir(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                            nx, ny, nz, float(tol), int(maxit), float(inner_tol), wptr, wbytes,
+                            _stream_handle(b, stream), ctypes.byref(it), ctypes.byref(out),
+                            ctypes.byref(rel))
+    if st < 0:
+        _check(st)
+    return st, it.value, out.value, rel.value
+
+
+def lap7_apply_f32(x, y, stream=None) -> None:
+    """y = A x in binary32 (float32 tensors); enqueued, no sync."""
+    import torch
+    _require_cuda_3d(x, y)
+    if x.dtype != torch.float32:
+        raise TypeError("lap7_apply_f32 works in float32")
+    nz, ny, nx = x.shape
+    _check(load().hc_lap7_apply_f32(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                    nx, ny, nz, _stream_handle(x, stream)))
+
+
 def lap7_apply(x, y, stream=None) -> None:
     """y = A x (7-point Laplacian, zero outside); enqueued, no sync."""
     import torch
@@ -259,6 +310,21 @@ def set_cg_tiling(vec: int = 2, wx: int = 2, by: int = 8, zdepth: int = 32, xcd:
 def get_cg_tiling() -> dict:
     v = [ctypes.c_int(0) for _ in range(5)]
     load().hc_cg_get_tiling(*[ctypes.byref(x) for x in v])
+    return dict(zip(("vec", "wx", "by", "zdepth", "xcd"), (x.value for x in v)))
+
+
+DEFAULT_CG_IR_TILING = dict(vec=4, wx=1, by=8, zdepth=32, xcd=8)
+
+
+def set_cg_ir_tiling(vec: int = 4, wx: int = 1, by: int = 8, zdepth: int = 32,
+                     xcd: int = 8) -> None:
+    """Tile shape of the binary32 inner CG kernels and of lap7_apply_f32."""
+    _check(load().hc_cg_ir_set_tiling(int(vec), int(wx), int(by), int(zdepth), int(xcd)))
+
+
+def get_cg_ir_tiling() -> dict:
+    v = [ctypes.c_int(0) for _ in range(5)]
+    load().hc_cg_ir_get_tiling(*[ctypes.byref(x) for x in v])
     return dict(zip(("vec", "wx", "by", "zdepth", "xcd"), (x.value for x in v)))
 
 

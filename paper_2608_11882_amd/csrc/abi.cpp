@@ -102,6 +102,28 @@ hc::HeatTiling heat_tiling_for(int dtype, int nx, const void *u, const void *un)
 
 hc::CGTiling g_cg_tiling = {2, 2, 8, 32, 8};
 
+// Tile shape of the refinement's binary32 inner solve: 256 x 8 tiles of
+// 4-node (16-byte) lanes, z-blocks of 32 planes (the fastest built shape at
+// 256^3 on MI355X).
+hc::CGTiling g_cg_ir_tiling = {4, 1, 8, 32, 8};
+
+// The inner solve's shape for these arrays: vec-node lanes need an x-edge
+// that is a multiple of vec and arrays aligned to a lane, else the one-node
+// shape of the same tile height.
+hc::CGTiling cg_ir_tiling_for(int nx, const void *a, const void *b, const void *c,
+                              const void *e) {
+    hc::CGTiling t;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        t = g_cg_ir_tiling;
+    }
+    const uintptr_t lane = (uintptr_t)t.vec * sizeof(float);
+    const uintptr_t mis = (reinterpret_cast<uintptr_t>(a) % lane) | (reinterpret_cast<uintptr_t>(b) % lane) |
+                          (reinterpret_cast<uintptr_t>(c) % lane) | (reinterpret_cast<uintptr_t>(e) % lane);
+    if (t.vec > 1 && ((nx % t.vec) || mis)) t = {1, 1, 4, 16, t.xcd};
+    return t;
+}
+
 // The CG tile shape for these arrays: two-node lanes need an even x-edge and
 // 16-byte aligned vectors, else the one-node shape of the same tile height.
 hc::CGTiling cg_tiling_for(int nx, const void *a, const void *b, const void *c) {
@@ -121,7 +143,7 @@ struct DevState {
     bool ready = false;
     hipStream_t aux = nullptr;   // the Boundary kernels' stream
     hipEvent_t ev_main = nullptr, ev_aux = nullptr;
-    void *cg_work = nullptr;
+    void *cg_work = nullptr;     // default workspace of cg_solve_ex and cg_solve_ir
     size_t cg_work_size = 0;
     hc::CGScalars *host_sc = nullptr;  // pinned
     double *sink = nullptr;  // store target of lanes outside a CG box
@@ -373,6 +395,112 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     return HC_OK;
 }
 
+// Iterative refinement with a binary32 inner CG: see cg_solve_ir.
+int cg_run_ir(const double *b, double *x, int nx, int ny, int nz, double tol, int maxit,
+              double inner_tol, void *work, hipStream_t s, int *iters_out, int *outer_out,
+              double *relres_out) {
+    DevState *d = nullptr;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    const hc::CGWorkF32 w = hc::cg_ir_work_carve(work, nx, ny, nz);
+    const hc::CGTiling t64 = cg_tiling_for(nx, b, x, x);
+    const hc::CGTiling t32 = cg_ir_tiling_for(nx, w.r, w.p[0], w.p[1], w.d);
+    hc::CGScalars *h = d->host_sc;
+    const double n = (double)nx * ny * nz;
+    constexpr int kMaxOuter = 64;
+    constexpr double kFloor = 0.5;
+    *iters_out = 0;
+    *outer_out = 0;
+    *relres_out = 0.0;
+
+    auto read_scalars = [&]() -> int {
+        HC_TRY(hipMemcpyAsync(h, w.sc, sizeof(hc::CGScalars), hipMemcpyDeviceToHost, s),
+               "hipMemcpyAsync");
+        HC_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return HC_OK;
+    };
+    {
+        const size_t plane_bytes = (size_t)nx * ny * sizeof(float);
+        float *vecs[3] = {w.r, w.p[0], w.p[1]};
+        for (float *v : vecs) {
+            HC_TRY(hipMemsetAsync(v - (size_t)nx * ny, 0, plane_bytes, s), "hipMemsetAsync");
+            HC_TRY(hipMemsetAsync(v + (size_t)nz * nx * ny, 0, plane_bytes, s), "hipMemsetAsync");
+        }
+    }
+    HC_TRY(hc::launch_cg_init(w.sc, tol, inner_tol, kFloor, s), "cg_init launch");
+    double rprev = INFINITY;
+    int outer = 0;
+    int status = HC_ENOTCONV;
+    for (;;) {
+        {
+            Timed tm(hc::K_IR_RESIDUAL, s, 20.0 * n);
+            HC_TRY(hc::launch_cg_ir_residual(b, x, w, nx, ny, nz, t64, d->sink, s),
+                   "cg_ir_residual launch");
+            tm.done();
+        }
+        if ((rc = read_scalars())) return rc;
+        if (h->state == -7) {
+            status = fail(HC_ENONFINITE, "non-finite residual after %d outer steps", outer);
+            break;
+        }
+        if (h->bnorm2 == 0.0) {
+            HC_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s), "hipMemsetAsync");
+            HC_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+            *iters_out = h->iter;
+            *outer_out = outer;
+            return HC_OK;
+        }
+        const double rnorm = std::sqrt(h->rtrue2);
+        if (h->state == 1) {
+            status = HC_OK;
+            break;
+        }
+        if (h->iter >= maxit || outer >= kMaxOuter || rnorm >= rprev) break;  // not converged
+        rprev = rnorm;
+        HC_TRY(hipMemsetAsync(w.d, 0, (size_t)n * sizeof(float), s), "hipMemsetAsync");
+        const int start = h->iter;
+        int cur = 0, first = 1;
+        while (h->state == 0 && h->iter < maxit) {
+            const int batch = std::min(16, maxit - h->iter);
+            for (int q = 0; q < batch; ++q) {
+                {
+                    Timed tm(hc::K_CG32_DIRECTION, s, (first ? 8.0 : 12.0) * n);
+                    HC_TRY(hc::launch_cg_direction_f32(w, cur, first, nx, ny, nz, t32, d->sink, s),
+                           "cg_direction (binary32) launch");
+                    tm.done();
+                }
+                {
+                    Timed tm(hc::K_CG32_UPDATE, s, 20.0 * n);
+                    HC_TRY(hc::launch_cg_update_f32(w, cur, nx, ny, nz, t32, d->sink, s),
+                           "cg_update (binary32) launch");
+                    tm.done();
+                }
+                cur ^= 1;
+                first = 0;
+            }
+            if ((rc = read_scalars())) return rc;
+        }
+        ++outer;
+        if (h->state == -7) {
+            status = fail(HC_ENONFINITE, "non-finite inner scalar at iteration %d", h->iter);
+            break;
+        }
+        if (h->state == -6 && h->iter == start) {
+            status = fail(HC_EBREAKDOWN, "p.Ap = %g <= 0 at the start of an inner solve", h->pap);
+            break;
+        }
+        {
+            Timed tm(hc::K_IR_UPDATE, s, 20.0 * n);
+            HC_TRY(hc::launch_ir_axpy(x, w.d, (long long)n, s), "ir_axpy launch");
+            tm.done();
+        }
+    }
+    *iters_out = h->iter;
+    *outer_out = outer;
+    *relres_out = h->bnorm2 > 0.0 ? std::sqrt(h->rtrue2) / std::sqrt(h->bnorm2) : 0.0;
+    return status;
+}
+
 int validate_heat(const void *u, const void *un, int nx, int ny, int nz, double r, int steps,
                   int dtype, int mode, int parts, size_t *bytes) {
     if (!u || !un) return fail(HC_EINVAL, "u and u_new must be non-NULL");
@@ -427,7 +555,7 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
             HC_TRY(hipMemsetAsync(v + (size_t)nz * nx * ny, 0, plane_bytes, s), "hipMemsetAsync");
         }
     }
-    HC_TRY(hc::launch_cg_init(w, tol, s), "cg_init launch");
+    HC_TRY(hc::launch_cg_init(w.sc, tol, 0.0, 0.0, s), "cg_init launch");
     if ((rc = residual(1))) return rc;
     if ((rc = read_scalars())) return rc;
     if (h->bnorm2 == 0.0) {
@@ -549,6 +677,37 @@ size_t cg_workspace_bytes(int nx, int ny, int nz) {
     return hc::cg_work_bytes(nx, ny, nz);
 }
 
+// The caller's workspace (checked), or the library's cached one (grown to
+// `need` bytes on demand).
+int cg_workspace(const double *b, const double *x, size_t bytes, size_t need, void **work) {
+    int rc = HC_OK;
+    if (*work) {
+        if ((rc = check_device_buffer(*work, need, "work"))) return rc;
+        if (overlaps(*work, need, b, bytes) || overlaps(*work, need, x, bytes))
+            return fail(HC_EALIAS, "workspace overlaps b or x");
+        return HC_OK;
+    }
+    DevState *d = nullptr;
+    if ((rc = device_state(&d))) return rc;
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    if (d->cg_work_size < need) {
+        if (d->cg_work) {
+            HC_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+            HC_TRY(hipFree(d->cg_work), "hipFree");
+            d->cg_work = nullptr;
+            d->cg_work_size = 0;
+        }
+        if (hipMalloc(&d->cg_work, need) != hipSuccess) {
+            (void)hipGetLastError();
+            d->cg_work = nullptr;
+            return fail(HC_ENOMEM, "CG workspace of %zu bytes", need);
+        }
+        d->cg_work_size = need;
+    }
+    *work = d->cg_work;
+    return HC_OK;
+}
+
 int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol, int maxit,
                 void *work, size_t work_bytes, hc_stream_t stream, int *iters,
                 double *true_relres) {
@@ -569,30 +728,7 @@ int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol, 
         return fail(HC_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
     if ((rc = check_device_buffer(b, bytes, "b"))) return rc;
     if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
-    if (work) {
-        if ((rc = check_device_buffer(work, need, "work"))) return rc;
-        if (overlaps(work, need, b, bytes) || overlaps(work, need, x, bytes))
-            return fail(HC_EALIAS, "workspace overlaps b or x");
-    } else {
-        DevState *d = nullptr;
-        if ((rc = device_state(&d))) return rc;
-        std::lock_guard<std::mutex> g(g_dev_mu);
-        if (d->cg_work_size < need) {
-            if (d->cg_work) {
-                HC_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
-                HC_TRY(hipFree(d->cg_work), "hipFree");
-                d->cg_work = nullptr;
-                d->cg_work_size = 0;
-            }
-            if (hipMalloc(&d->cg_work, need) != hipSuccess) {
-                (void)hipGetLastError();
-                d->cg_work = nullptr;
-                return fail(HC_ENOMEM, "CG workspace of %zu bytes", need);
-            }
-            d->cg_work_size = need;
-        }
-        work = d->cg_work;
-    }
+    if ((rc = cg_workspace(b, x, bytes, need, &work))) return rc;
     int it = 0;
     double rel = 0.0;
     rc = cg_run(b, x, nx, ny, nz, tol, maxit, work, reinterpret_cast<hipStream_t>(stream), &it, &rel);
@@ -610,6 +746,67 @@ int cg_solve(const double *b, double *x, int n, double tol, int maxit) {
 void hc_cg_last_info(int *iters, double *true_relres) {
     if (iters) *iters = g_cg_iters;
     if (true_relres) *true_relres = g_cg_relres;
+}
+
+int cg_solve_ir(const double *b, double *x, int nx, int ny, int nz, double tol, int maxit,
+                double inner_tol, void *work, size_t work_bytes, hc_stream_t stream, int *iters,
+                int *outer, double *true_relres) {
+    g_msg.clear();
+    if (iters) *iters = 0;
+    if (outer) *outer = 0;
+    if (true_relres) *true_relres = 0.0;
+    if (!b || !x) return fail(HC_EINVAL, "b and x must be non-NULL");
+    size_t bytes = 0;
+    int rc = check_dims(nx, ny, nz, 1, 8, &bytes);
+    if (rc) return rc;
+    if (!std::isfinite(tol) || tol <= 0.0) return fail(HC_EINVAL, "tol = %g must be > 0", tol);
+    if (maxit < 0) return fail(HC_EINVAL, "maxit = %d < 0", maxit);
+    if (!std::isfinite(inner_tol) || inner_tol >= 1.0)
+        return fail(HC_EINVAL, "inner_tol = %g must be < 1", inner_tol);
+    if (inner_tol <= 0.0) inner_tol = 1e-5;
+    if (overlaps(b, bytes, x, bytes)) return fail(HC_EALIAS, "b and x overlap");
+    const size_t need = hc::cg_ir_work_bytes(nx, ny, nz);
+    if (hc::cg_blocks(nx, ny, nz, {1, 1, 4, 8, 0}) > 2147483647LL)
+        return fail(HC_EINVAL, "grid too large");
+    if (work && work_bytes < need)
+        return fail(HC_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
+    if ((rc = check_device_buffer(b, bytes, "b"))) return rc;
+    if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
+    if ((rc = cg_workspace(b, x, bytes, need, &work))) return rc;
+    int it = 0, out = 0;
+    double rel = 0.0;
+    rc = cg_run_ir(b, x, nx, ny, nz, tol, maxit, inner_tol, work,
+                   reinterpret_cast<hipStream_t>(stream), &it, &out, &rel);
+    if (iters) *iters = it;
+    if (outer) *outer = out;
+    if (true_relres) *true_relres = rel;
+    return rc;
+}
+
+size_t cg_ir_workspace_bytes(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    return hc::cg_ir_work_bytes(nx, ny, nz);
+}
+
+int hc_lap7_apply_f32(const float *x, float *y, int nx, int ny, int nz, hc_stream_t stream) {
+    g_msg.clear();
+    if (!x || !y) return fail(HC_EINVAL, "x and y must be non-NULL");
+    size_t bytes = 0;
+    int rc = check_dims(nx, ny, nz, 1, 4, &bytes);
+    if (rc) return rc;
+    if (overlaps(x, bytes, y, bytes)) return fail(HC_EALIAS, "x and y overlap");
+    if (hc::cg_blocks(nx, ny, nz, {1, 1, 4, 8, 0}) > 2147483647LL)
+        return fail(HC_EINVAL, "grid too large");
+    if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
+    if ((rc = check_device_buffer(y, bytes, "y"))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DevState *d = nullptr;
+    if ((rc = device_state(&d))) return rc;
+    const hc::CGTiling til = cg_ir_tiling_for(nx, x, y, x, y);
+    Timed tm(hc::K_LAP7, s, 8.0 * nx * ny * nz);
+    HC_TRY(hc::launch_lap7_f32(x, y, nx, ny, nz, til, d->sink, s), "lap7 (binary32) launch");
+    tm.done();
+    return HC_OK;
 }
 
 int hc_lap7_apply(const double *x, double *y, int nx, int ny, int nz, hc_stream_t stream) {
@@ -698,6 +895,31 @@ int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new, int 
     if (pf) *pf = t.pf;
     if (xcd) *xcd = t.xcd;
     return HC_OK;
+}
+
+int hc_cg_ir_set_tiling(int vec, int wx, int by, int zdepth, int xcd) {
+    g_msg.clear();
+    const hc::CGTiling t = {vec, wx, by, zdepth, xcd};
+    if (!hc::cg_tiling_supported_f32(t))
+        return fail(HC_EINVAL, "binary32 CG tile shape (vec %d, wx %d, by %d, zdepth %d) is not built",
+                    vec, wx, by, zdepth);
+    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_cg_ir_tiling = t;
+    return HC_OK;
+}
+
+void hc_cg_ir_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd) {
+    hc::CGTiling t;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        t = g_cg_ir_tiling;
+    }
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (xcd) *xcd = t.xcd;
 }
 
 int hc_cg_set_tiling(int vec, int wx, int by, int zdepth, int xcd) {

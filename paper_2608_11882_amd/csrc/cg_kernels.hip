@@ -51,38 +51,35 @@ __device__ __forceinline__ int block_order(int b, int nb, int g) {
     return w * win + (o & 7) * g + (o >> 3);
 }
 
-typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int VEC>
-__device__ __forceinline__ void load_vec(const double *__restrict__ p, double *o) {
-    if (VEC == 2) {
-        const f64x2 v = *reinterpret_cast<const f64x2 *>(p);
-        o[0] = v.x;
-        o[1] = v.y;
-    } else {
-        o[0] = *p;
-    }
+// One access of N bytes as a single load or store.
+template <int N> struct Raw;
+template <> struct Raw<4> { using T = unsigned int; };
+template <> struct Raw<8> { using T = u32x2; };
+template <> struct Raw<16> { using T = u32x4; };
+
+template <class T, int VEC>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, T *o) {
+    using R = typename Raw<VEC * sizeof(T)>::T;
+    const R raw = *reinterpret_cast<const R *>(p);
+    __builtin_memcpy(o, &raw, sizeof raw);
 }
 
-// Store VEC values.  With two-node lanes the x-edge is even, so a lane is
-// either inside the box or wholly outside it; a lane outside stores into
-// its own slot of a sink buffer instead, so no store sits under a branch.
-template <int VEC>
-__device__ __forceinline__ void store_vec(double *__restrict__ p, const double *v, bool nt) {
-    if (VEC == 2) {
-        f64x2 x;
-        x.x = v[0];
-        x.y = v[VEC - 1];
-        if (nt)
-            __builtin_nontemporal_store(x, reinterpret_cast<f64x2 *>(p));
-        else
-            *reinterpret_cast<f64x2 *>(p) = x;
-    } else {
-        if (nt)
-            __builtin_nontemporal_store(v[0], p);
-        else
-            p[0] = v[0];
-    }
+// Store VEC values.  With multi-node lanes the x-edge is a multiple of VEC,
+// so a lane is either inside the box or wholly outside it; a lane outside
+// stores into its own slot of a sink buffer instead, so no store sits under
+// a branch.
+template <class T, int VEC>
+__device__ __forceinline__ void store_vec(T *__restrict__ p, const T *v, bool nt) {
+    using R = typename Raw<VEC * sizeof(T)>::T;
+    R raw;
+    __builtin_memcpy(&raw, v, sizeof raw);
+    if (nt)
+        __builtin_nontemporal_store(raw, reinterpret_cast<R *>(p));
+    else
+        *reinterpret_cast<R *>(p) = raw;
 }
 
 // Address of a node: a uniform base (array + plane k, in scalar registers)
@@ -96,7 +93,9 @@ __device__ __forceinline__ T *node(T *base, long long plane, int k, unsigned off
             base + (long long)k * plane) + off);
 }
 
-template <int VEC, int WX, int BY>
+// Offsets are kept in nodes (own, ring) and, for the field's element type
+// T, in bytes (own_b, ring_b).
+template <class T, int VEC, int WX, int BY>
 struct BoxGeom {
     static constexpr int TX = 64 * VEC * WX;
     static constexpr int LD = TX + 2;
@@ -168,19 +167,20 @@ struct BoxGeom {
             rj = j;
         }
         ring = (long long)max(0, min(rj, ny - 1)) * nx + ri;
-        own_b = (unsigned)(own * (long long)sizeof(double));
-        ring_b = (unsigned)(ring * (long long)sizeof(double));
+        own_b = (unsigned)(own * (long long)sizeof(T));
+        ring_b = (unsigned)(ring * (long long)sizeof(T));
     }
 };
 
 // Walk the block's tile through its z-block.
 //
-//  field.template load<V>(off, out)   V field values from the in-box node
-//                        `off` on (clamped offsets; loads unconditional)
-//  epi.prefetch(off)     the epilogue's own loads for a plane, as Epi::Pre
-//  epi.finish(ok, off, c, nsum, pre)  own nodes: field values, ordered
-//                        neighbour sums, prefetched values; ok[v] false off
-//                        the box
+//  field.template load<V>(k, off, out)  V field values (type T) from the
+//                        in-box node at byte offset `off` of plane k
+//                        (clamped offsets; loads unconditional)
+//  epi.prefetch(k, off)  the epilogue's own loads for a plane, as Epi::Pre
+//  epi.finish(ok, lane_in, k, off, sink, c, nsum, pre)  own nodes: field
+//                        values, ordered neighbour sums (type T),
+//                        prefetched values; ok[v] false off the box
 //
 // ZPAD: the field's arrays carry one zero plane below plane 0 and one above
 // plane nz-1, so planes -1 and nz are read from memory and no plane index
@@ -188,61 +188,70 @@ struct BoxGeom {
 // load, and a load under a branch makes it wait for every load in flight).
 // UNROLL: take the unrolled path for full-depth z-blocks (false keeps the
 // plain loop, for kernels that run once or twice per solve).
-template <int VEC, int WX, int BY, int ZB, bool ZPAD, bool UNROLL = true, class Field,
-          class Epi>
+template <class T, int VEC, int WX, int BY, int ZB, bool ZPAD, bool UNROLL = true,
+          class Field, class Epi>
 __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
                                            double *sink, Field &field, Epi &epi) {
-    using G = BoxGeom<VEC, WX, BY>;
+    using G = BoxGeom<T, VEC, WX, BY>;
     using Pre = typename Epi::Pre;
-    static_assert(G::NT * VEC <= kSinkDoubles, "sink holds one slot per lane");
-    __shared__ double tile[(BY + 2) * G::LD];
+    static_assert(G::NT * VEC * sizeof(T) <= kSinkDoubles * sizeof(double),
+                  "sink holds one slot per lane");
+    __shared__ T tile[(BY + 2) * G::LD];
     const G g(nx, ny, nz, ZB, xcd);
-    // a lane outside the box writes its own sink slot
-    double *const lane_sink = sink + (long long)threadIdx.x * VEC;
+    // a lane outside the box writes its own sink slot of VEC field values
+    // (the epilogues store at most that many bytes per lane and vector)
+    double *const lane_sink = reinterpret_cast<double *>(
+        reinterpret_cast<char *>(sink) + (long long)threadIdx.x * VEC * sizeof(T));
 
     // column values of plane k (0 outside the box)
-    auto col = [&](int k, double *o) {
+    auto col = [&](int k, T *o) {
         const int kc = ZPAD ? k : max(0, min(k, nz - 1));
         const bool kin = ZPAD || ((k >= 0) && (k < nz));
-        double v[VEC];
+        T v[VEC];
         field.template load<VEC>(kc, g.own_b, v);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) o[e] = (kin && g.in[e]) ? v[e] : 0.0;
+        for (int e = 0; e < VEC; ++e) o[e] = (kin && g.in[e]) ? v[e] : T(0);
     };
     // one aligned VEC-wide load in every lane; a column node is picked out
-    auto ringv = [&](int k, double *o) {
+    auto ringv = [&](int k, T *o) {
         const int kc = ZPAD ? k : max(0, min(k, nz - 1));
         const bool kin = ZPAD || ((k >= 0) && (k < nz));
-        double v[VEC];
+        T v[VEC];
         field.template load<VEC>(kc, g.ring_b, v);
-        if (VEC == 2 && g.rsel) v[0] = v[VEC - 1];
+        T sel = v[0];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) o[e] = (kin && g.rin[e]) ? v[e] : 0.0;
+        for (int e = 1; e < VEC; ++e) sel = (g.rsel == e) ? v[e] : sel;
+        v[0] = sel;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = (kin && g.rin[e]) ? v[e] : T(0);
     };
-    auto put = [&](const double *c, const double *rv) {
+    auto put = [&](const T *c, const T *rv) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) tile[g.own_slot + e] = c[e];
         if (g.rslot >= 0) {
             tile[g.rslot] = rv[0];
-            if (VEC == 2 && g.rvec) tile[g.rslot + VEC - 1] = rv[VEC - 1];
+            if (g.rvec) {
+#pragma unroll
+                for (int e = 1; e < VEC; ++e) tile[g.rslot + e] = rv[e];
+            }
         }
     };
-    auto nsums = [&](const double *zm, const double *zp, double *ns) {
+    auto nsums = [&](const T *zm, const T *zp, T *ns) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const int sl = g.own_slot + e;
-            const double xm = tile[sl - 1];
-            const double xp = tile[sl + 1];
-            const double ym = tile[sl - G::LD];
-            const double yp = tile[sl + G::LD];
+            const T xm = tile[sl - 1];
+            const T xp = tile[sl + 1];
+            const T ym = tile[sl - G::LD];
+            const T yp = tile[sl + G::LD];
             ns[e] = ((xm + xp) + (ym + yp)) + (zm[e] + zp[e]);
         }
     };
     const int kb = g.kb, ke = g.ke;
 
     if (UNROLL && ke - kb + 1 == ZB) {
-        double q[ZB + 2][VEC];  // q[s]: column at plane kb-1+s
-        double rg[ZB][VEC];     // ring values of plane kb+s
+        T q[ZB + 2][VEC];  // q[s]: column at plane kb-1+s
+        T rg[ZB][VEC];     // ring values of plane kb+s
         Pre pre[ZB];
 #pragma unroll
         for (int s = 0; s < kPF + 2; ++s) col(kb - 1 + s, q[s]);
@@ -256,7 +265,7 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
             if (s + kPF < ZB) ringv(kb + s + kPF, rg[s + kPF]);
             if (s + 1 < ZB) pre[s + 1] = epi.prefetch(kb + s + 1, g.own_b);
             __syncthreads();
-            double ns[VEC];
+            T ns[VEC];
             nsums(q[s], q[s + 2], ns);
             epi.finish(g.in, g.lane_in, kb + s, g.own_b, lane_sink, q[s + 1], ns, pre[s]);
             if (s + 2 + kPF <= ZB + 1) col(kb + s + 1 + kPF, q[s + 2 + kPF]);
@@ -264,20 +273,20 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
         return;
     }
 
-    double zm[VEC], c[VEC], zp[VEC], rc[VEC];
+    T zm[VEC], c[VEC], zp[VEC], rc[VEC];
     col(kb - 1, zm);
     col(kb, c);
     col(kb + 1, zp);
     ringv(kb, rc);
     for (int k = kb; k <= ke; ++k) {
-        double nn[VEC], rn[VEC];
+        T nn[VEC], rn[VEC];
         col(k + 2, nn);
         ringv(min(k + 1, ke), rn);
         const Pre pr = epi.prefetch(k, g.own_b);
         __syncthreads();
         put(c, rc);
         __syncthreads();
-        double ns[VEC];
+        T ns[VEC];
         nsums(zm, zp, ns);
         epi.finish(g.in, g.lane_in, k, g.own_b, lane_sink, c, ns, pr);
 #pragma unroll
@@ -342,7 +351,8 @@ __device__ __forceinline__ double gather(const double *partial, int nsum, int q)
     return block_sum<NT>(t);
 }
 
-__global__ __launch_bounds__(64) void cg_init(CGScalars *sc, double tol) {
+__global__ __launch_bounds__(64) void cg_init(CGScalars *sc, double tol, double inner_tol,
+                                              double floor_frac) {
     if (threadIdx.x == 0) {
         sc->rho = 0.0;
         sc->pap = 0.0;
@@ -352,33 +362,37 @@ __global__ __launch_bounds__(64) void cg_init(CGScalars *sc, double tol) {
         sc->tol = tol;
         sc->thresh = 0.0;
         sc->rtrue2 = 0.0;
+        sc->inner_tol = inner_tol;
+        sc->floor_frac = floor_frac;
         sc->iter = 0;
         sc->state = 0;
         sc->ticket = 0u;
     }
 }
 
+template <class T>
 struct PlainField {
-    const double *__restrict__ x;
+    const T *__restrict__ x;
     long long plane;
     template <int V>
-    __device__ void load(int k, unsigned off, double *out) const {
-        load_vec<V>(node(x, plane, k, off), out);
+    __device__ void load(int k, unsigned off, T *out) const {
+        load_vec<T, V>(node(x, plane, k, off), out);
     }
 };
 
 // p' = r + beta p (p' = r on the first iteration)
+template <class T>
 struct DirectionField {
-    const double *__restrict__ r;
-    const double *__restrict__ p;
+    const T *__restrict__ r;
+    const T *__restrict__ p;
     long long plane;
-    double beta;
+    T beta;
     int first;
     template <int V>
-    __device__ void load(int k, unsigned off, double *out) const {
-        double rv[V], pv[V];
-        load_vec<V>(node(r, plane, k, off), rv);
-        load_vec<V>(node(p, plane, k, off), pv);
+    __device__ void load(int k, unsigned off, T *out) const {
+        T rv[V], pv[V];
+        load_vec<T, V>(node(r, plane, k, off), rv);
+        load_vec<T, V>(node(p, plane, k, off), pv);
 #pragma unroll
         for (int e = 0; e < V; ++e) out[e] = first ? rv[e] : rv[e] + beta * pv[e];
     }
@@ -402,7 +416,7 @@ struct ResidualEpi {
     __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
                            const double *c, const double *ns, const Pre &) {
         double bo[VEC], ro[VEC];
-        load_vec<VEC>(node(b, plane, k, off), bo);
+        load_vec<double, VEC>(node(b, plane, k, off), bo);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const double q = 6.0 * c[e] - ns[e];
@@ -412,73 +426,110 @@ struct ResidualEpi {
                 bb += bo[e] * bo[e];
             }
         }
-        store_vec<VEC>(lane_in ? node(r, plane, k, off) : sink, ro, false);
+        store_vec<double, VEC>(lane_in ? node(r, plane, k, off) : sink, ro, false);
     }
 };
 
+// Refinement residual: r = b - A x in binary64, its binary32 rounding s
+// (the right-hand side of the inner solve) stored, and r.r, s.s, b.b
+// accumulated in binary64.
 template <int VEC>
+struct IRResidualEpi {
+    using Pre = NoPre;
+    const double *__restrict__ b;
+    float *__restrict__ s;
+    long long plane;
+    double rr = 0.0, ss = 0.0, bb = 0.0;
+    __device__ Pre prefetch(int, unsigned) const { return Pre{0}; }
+    __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
+                           const double *c, const double *ns, const Pre &) {
+        double bo[VEC];
+        float so[VEC];
+        load_vec<double, VEC>(node(b, plane, k, off), bo);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const double q = 6.0 * c[e] - ns[e];
+            const double r = bo[e] - q;
+            so[e] = (float)r;
+            if (ok[e]) {
+                rr += r * r;
+                ss += (double)so[e] * (double)so[e];
+                bb += bo[e] * bo[e];
+            }
+        }
+        // off is a byte offset into binary64 planes; s holds binary32
+        store_vec<float, VEC>(lane_in ? node(s, plane, k, off / 2) : reinterpret_cast<float *>(sink),
+                              so, false);
+    }
+};
+
+template <class T, int VEC>
 struct DirectionEpi {
     using Pre = NoPre;
-    double *__restrict__ pnew;
+    T *__restrict__ pnew;
     long long plane;
     double acc = 0.0;
     __device__ Pre prefetch(int, unsigned) const { return Pre{0}; }
     __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
-                           const double *c, const double *ns, const Pre &) {
+                           const T *c, const T *ns, const Pre &) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            const double q = 6.0 * c[e] - ns[e];
-            if (ok[e]) acc += c[e] * q;
+            const T q = T(6) * c[e] - ns[e];
+            if (ok[e]) acc += (double)c[e] * (double)q;
         }
-        store_vec<VEC>(lane_in ? node(pnew, plane, k, off) : sink, c, true);
+        store_vec<T, VEC>(lane_in ? node(pnew, plane, k, off) : reinterpret_cast<T *>(sink), c,
+                          true);
     }
 };
 
-// x += alpha p', r -= alpha A p', and r.r of the new residual
-template <int VEC>
+// x += alpha p', r -= alpha A p', and r.r of the new residual (accumulated
+// in binary64)
+template <class T, int VEC>
 struct UpdateEpi {
     struct Pre {
-        double x[VEC], r[VEC];
+        T x[VEC], r[VEC];
     };
-    double *__restrict__ x;
-    double *__restrict__ r;
+    T *__restrict__ x;
+    T *__restrict__ r;
     long long plane;
-    double alpha;
+    T alpha;
     double acc = 0.0;
     __device__ Pre prefetch(int k, unsigned off) const {
         Pre p;
-        load_vec<VEC>(node(x, plane, k, off), p.x);
-        load_vec<VEC>(node(r, plane, k, off), p.r);
+        load_vec<T, VEC>(node(x, plane, k, off), p.x);
+        load_vec<T, VEC>(node(r, plane, k, off), p.r);
         return p;
     }
     __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
-                           const double *c, const double *ns, const Pre &p) {
-        double xn[VEC], rn[VEC];
+                           const T *c, const T *ns, const Pre &p) {
+        T xn[VEC], rn[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            const double q = 6.0 * c[e] - ns[e];
+            const T q = T(6) * c[e] - ns[e];
             xn[e] = p.x[e] + alpha * c[e];
             rn[e] = p.r[e] - alpha * q;
-            if (ok[e]) acc += rn[e] * rn[e];
+            if (ok[e]) acc += (double)rn[e] * (double)rn[e];
         }
-        store_vec<VEC>(lane_in ? node(x, plane, k, off) : sink, xn, false);
-        store_vec<VEC>(lane_in ? node(r, plane, k, off) : sink, rn, false);
+        T *const sk = reinterpret_cast<T *>(sink);
+        store_vec<T, VEC>(lane_in ? node(x, plane, k, off) : sk, xn, false);
+        store_vec<T, VEC>(lane_in ? node(r, plane, k, off) : sk, rn, false);
     }
 };
 
-template <int VEC>
+template <class T, int VEC>
 struct Lap7Epi {
     using Pre = NoPre;
-    double *__restrict__ y;
+    T *__restrict__ y;
     long long plane;
     __device__ Pre prefetch(int, unsigned) const { return Pre{0}; }
     __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
-                           const double *c, const double *ns, const Pre &) {
+                           const T *c, const T *ns, const Pre &) {
         (void)ok;
-        double out[VEC];
+        T out[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) out[e] = 6.0 * c[e] - ns[e];
-        store_vec<VEC>(lane_in ? node(y, plane, k, off) : sink, out, false);
+        for (int e = 0; e < VEC; ++e) out[e] = T(6) * c[e] - ns[e];
+        store_vec<T, VEC>(lane_in ? node(y, plane, k, off) : reinterpret_cast<T *>(sink), out,
+                          false);
     }
 };
 
@@ -493,9 +544,9 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_residual_f64(
     int nz, int xcd, double *sink, int mode) {
     constexpr int NT = 64 * WX * BY;
     const long long plane = (long long)nx * ny;
-    PlainField f{x, plane};
+    PlainField<double> f{x, plane};
     ResidualEpi<VEC> epi{b, r, plane};
-    box_zmarch<VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi);
+    box_zmarch<double, VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi);
     double v[2];
     v[0] = block_sum<NT>(epi.rr);
     v[1] = block_sum<NT>(epi.bb);
@@ -519,17 +570,55 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_residual_f64(
     }
 }
 
+// Refinement step: r = b - A x (binary64), s = r rounded to binary32 for
+// the inner solve.  Outer test ||r|| <= tol ||b|| (state 1); otherwise the
+// inner solve starts with rho = s.s and stops at
+// max(inner_tol sqrt(rho), floor tol ||b||) (state 0).
 template <int VEC, int WX, int BY, int ZB>
-__global__ __launch_bounds__(64 * WX * BY) void cg_direction_f64(
-    const double *__restrict__ r, const double *__restrict__ pold,
-    double *__restrict__ pnew, double *partial, CGScalars *sc, int nx, int ny,
-    int nz, int xcd, double *sink, int first) {
+__global__ __launch_bounds__(64 * WX * BY) void cg_ir_residual(
+    const double *__restrict__ b, const double *__restrict__ x, float *__restrict__ s,
+    double *partial, CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink) {
+    constexpr int NT = 64 * WX * BY;
+    const long long plane = (long long)nx * ny;
+    PlainField<double> f{x, plane};
+    IRResidualEpi<VEC> epi{b, s, plane};
+    box_zmarch<double, VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi);
+    double v[3];
+    v[0] = block_sum<NT>(epi.rr);
+    v[1] = block_sum<NT>(epi.ss);
+    v[2] = block_sum<NT>(epi.bb);
+    if (arrive(sc, partial, 3, v)) {
+        const double srr = gather<NT>(partial, 3, 0);
+        const double sss = gather<NT>(partial, 3, 1);
+        const double sbb = gather<NT>(partial, 3, 2);
+        if (threadIdx.x == 0) {
+            sc->rtrue2 = srr;
+            sc->bnorm2 = sbb;
+            const double target = sc->tol * sqrt(sbb);
+            if (!isfinite(srr) || !isfinite(sss) || !isfinite(sbb)) {
+                sc->state = -7;
+            } else if (sqrt(srr) <= target) {
+                sc->state = 1;
+            } else {
+                sc->rho = sss;
+                sc->thresh = fmax(sc->inner_tol * sqrt(sss), sc->floor_frac * target);
+                sc->state = 0;
+            }
+            sc->ticket = 0u;
+        }
+    }
+}
+
+template <class T, int VEC, int WX, int BY, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void cg_direction(
+    const T *__restrict__ r, const T *__restrict__ pold, T *__restrict__ pnew, double *partial,
+    CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int first) {
     constexpr int NT = 64 * WX * BY;
     if (load_state(sc) != 0) return;  // converged or failed: nothing to do
     const long long plane = (long long)nx * ny;
-    DirectionField f{r, first ? r : pold, plane, first ? 0.0 : sc->beta, first};
-    DirectionEpi<VEC> epi{pnew, plane};
-    box_zmarch<VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
+    DirectionField<T> f{r, first ? r : pold, plane, first ? T(0) : (T)sc->beta, first};
+    DirectionEpi<T, VEC> epi{pnew, plane};
+    box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
     double v[1];
     v[0] = block_sum<NT>(epi.acc);
     if (arrive(sc, partial, 1, v)) {
@@ -547,17 +636,16 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_direction_f64(
     }
 }
 
-template <int VEC, int WX, int BY, int ZB>
-__global__ __launch_bounds__(64 * WX * BY) void cg_update_f64(
-    double *__restrict__ x, double *__restrict__ r,
-    const double *__restrict__ p, double *partial, CGScalars *sc, int nx,
-    int ny, int nz, int xcd, double *sink) {
+template <class T, int VEC, int WX, int BY, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void cg_update(
+    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, double *partial,
+    CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink) {
     constexpr int NT = 64 * WX * BY;
     if (load_state(sc) != 0) return;
     const long long plane = (long long)nx * ny;
-    PlainField f{p, plane};
-    UpdateEpi<VEC> epi{x, r, plane, sc->alpha};
-    box_zmarch<VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
+    PlainField<T> f{p, plane};
+    UpdateEpi<T, VEC> epi{x, r, plane, (T)sc->alpha};
+    box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
     double v[1];
     v[0] = block_sum<NT>(epi.acc);
     if (arrive(sc, partial, 1, v)) {
@@ -576,25 +664,43 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_update_f64(
     }
 }
 
-template <int VEC, int WX, int BY, int ZB>
-__global__ __launch_bounds__(64 * WX * BY) void lap7_f64(
-    const double *__restrict__ x, double *__restrict__ y, int nx, int ny,
-    int nz, int xcd, double *sink) {
+template <class T, int VEC, int WX, int BY, int ZB>
+__global__ __launch_bounds__(64 * WX * BY) void lap7(
+    const T *__restrict__ x, T *__restrict__ y, int nx, int ny, int nz, int xcd, double *sink) {
     const long long plane = (long long)nx * ny;
-    PlainField f{x, plane};
-    Lap7Epi<VEC> epi{y, plane};
-    box_zmarch<VEC, WX, BY, ZB, false>(nx, ny, nz, xcd, sink, f, epi);
+    PlainField<T> f{x, plane};
+    Lap7Epi<T, VEC> epi{y, plane};
+    box_zmarch<T, VEC, WX, BY, ZB, false>(nx, ny, nz, xcd, sink, f, epi);
+}
+
+// x += d (binary64 += widened binary32), four nodes per thread
+__global__ __launch_bounds__(256) void ir_axpy(double *__restrict__ x, const float *__restrict__ d,
+                                               long long n) {
+    const long long stride = (long long)gridDim.x * 256 * 4;
+    for (long long i = ((long long)blockIdx.x * 256 + threadIdx.x) * 4; i < n; i += stride) {
+        if (i + 4 <= n) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[i + e] = x[i + e] + (double)d[i + e];
+        } else {
+            for (long long e = i; e < n; ++e) x[e] = x[e] + (double)d[e];
+        }
+    }
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
-// Every CG tile shape the library is built with (vec, wx, by, zdepth).
+// Every CG tile shape the library is built with (vec, wx, by, zdepth):
+// binary64 vectors, and binary32 vectors of the refinement's inner solve.
 #define HC_CG_SHAPES(X)                                                          \
     X(1, 1, 4, 16) X(1, 1, 4, 32) X(1, 4, 4, 16) X(2, 1, 4, 16) X(2, 1, 8, 16)   \
     X(2, 2, 4, 8) X(2, 2, 4, 16) X(2, 2, 4, 32) X(2, 2, 8, 8) X(2, 2, 8, 16)     \
     X(2, 2, 8, 32) X(2, 4, 4, 8) X(2, 4, 4, 16) X(2, 1, 16, 16)
+#define HC_CG_SHAPES_F32(X)                                                      \
+    X(1, 1, 4, 16) X(1, 4, 4, 16) X(2, 2, 8, 16) X(2, 2, 8, 32) X(2, 4, 4, 16)   \
+    X(4, 1, 8, 16) X(4, 1, 8, 32) X(4, 2, 4, 16) X(4, 2, 4, 32) X(4, 2, 8, 16)   \
+    X(4, 1, 16, 16) X(4, 4, 4, 16)
 
 #define HC_CG_KEY(V, W, B, Z) (((V * 8 + W) * 32 + B) * 128 + Z)
 
@@ -602,6 +708,14 @@ bool cg_tiling_supported(const CGTiling &t) {
     const int key = HC_CG_KEY(t.vec, t.wx, t.by, t.zdepth);
 #define HC_X(V, W, B, Z) if (key == HC_CG_KEY(V, W, B, Z)) return true;
     HC_CG_SHAPES(HC_X)
+#undef HC_X
+    return false;
+}
+
+bool cg_tiling_supported_f32(const CGTiling &t) {
+    const int key = HC_CG_KEY(t.vec, t.wx, t.by, t.zdepth);
+#define HC_X(V, W, B, Z) if (key == HC_CG_KEY(V, W, B, Z)) return true;
+    HC_CG_SHAPES_F32(HC_X)
 #undef HC_X
     return false;
 }
@@ -640,15 +754,39 @@ CGWork cg_work_carve(void *base, int nx, int ny, int nz) {
     return w;
 }
 
-// Launch kernel template KER<V, W, B, Z> for the tile shape t.
-#define HC_CG_DISPATCH(KER)                                                       \
+// Refinement workspace: s, p0, p1 (binary32, padded like above), d
+// (binary32), three partial sums per block, the scalars.
+size_t cg_ir_work_bytes(int nx, int ny, int nz) {
+    const size_t plane = (size_t)nx * ny;
+    const size_t vec = align256((size_t)(nz + 2) * plane * sizeof(float));
+    const size_t part = align256((size_t)max_blocks(nx, ny, nz) * 3 * sizeof(double));
+    return 4 * vec + part + align256(sizeof(CGScalars));
+}
+
+CGWorkF32 cg_ir_work_carve(void *base, int nx, int ny, int nz) {
+    const size_t plane = (size_t)nx * ny;
+    const size_t vec = align256((size_t)(nz + 2) * plane * sizeof(float));
+    const size_t part = align256((size_t)max_blocks(nx, ny, nz) * 3 * sizeof(double));
+    char *c = static_cast<char *>(base);
+    CGWorkF32 w;
+    w.r = reinterpret_cast<float *>(c) + plane;
+    w.p[0] = reinterpret_cast<float *>(c + vec) + plane;
+    w.p[1] = reinterpret_cast<float *>(c + 2 * vec) + plane;
+    w.d = reinterpret_cast<float *>(c + 3 * vec) + plane;
+    w.partial = reinterpret_cast<double *>(c + 4 * vec);
+    w.sc = reinterpret_cast<CGScalars *>(c + 4 * vec + part);
+    return w;
+}
+
+// Launch the kernel KER for the tile shape t out of the shape list LIST.
+#define HC_CG_DISPATCH(LIST, KER)                                                 \
     do {                                                                          \
         const long long nb = cg_blocks(nx, ny, nz, t);                            \
         if (nb <= 0 || nb > INT_MAX) return hipErrorInvalidConfiguration;         \
         const dim3 grid((unsigned)nb), block(64 * t.wx * t.by);                   \
         const int key = HC_CG_KEY(t.vec, t.wx, t.by, t.zdepth);                   \
         bool done = false;                                                        \
-        HC_CG_SHAPES(HC_CG_ONE_##KER)                                             \
+        LIST(HC_CG_ONE_##KER)                                                     \
         if (!done) return hipErrorInvalidValue;                                   \
         return hipGetLastError();                                                 \
     } while (0)
@@ -660,51 +798,92 @@ CGWork cg_work_carve(void *base, int nx, int ny, int nz) {
             sink, store_r ? 0 : 1);                                               \
         done = true;                                                              \
     }
+#define HC_CG_ONE_IRRES(V, W, B, Z)                                               \
+    if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
+        cg_ir_residual<V, W, B, Z><<<grid, block, 0, s>>>(                        \
+            b, x, w.r, w.partial, w.sc, nx, ny, nz, t.xcd, sink);                 \
+        done = true;                                                              \
+    }
 #define HC_CG_ONE_DIR(V, W, B, Z)                                                 \
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
-        cg_direction_f64<V, W, B, Z><<<grid, block, 0, s>>>(                      \
+        cg_direction<ELEM, V, W, B, Z><<<grid, block, 0, s>>>(                    \
             w.r, w.p[cur], w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd,      \
             sink, first);                                                         \
         done = true;                                                              \
     }
 #define HC_CG_ONE_UPD(V, W, B, Z)                                                 \
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
-        cg_update_f64<V, W, B, Z><<<grid, block, 0, s>>>(                         \
+        cg_update<ELEM, V, W, B, Z><<<grid, block, 0, s>>>(                       \
             x, w.r, w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd, sink);      \
         done = true;                                                              \
     }
 #define HC_CG_ONE_LAP(V, W, B, Z)                                                 \
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
-        lap7_f64<V, W, B, Z><<<grid, block, 0, s>>>(x, y, nx, ny, nz, t.xcd,      \
-                                                    sink);                        \
+        lap7<ELEM, V, W, B, Z><<<grid, block, 0, s>>>(x, y, nx, ny, nz, t.xcd,    \
+                                                      sink);                      \
         done = true;                                                              \
     }
 
-hipError_t launch_cg_init(const CGWork &w, double tol, hipStream_t s) {
-    cg_init<<<1, 64, 0, s>>>(w.sc, tol);
+hipError_t launch_cg_init(CGScalars *sc, double tol, double inner_tol, double floor_frac,
+                          hipStream_t s) {
+    cg_init<<<1, 64, 0, s>>>(sc, tol, inner_tol, floor_frac);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_residual(const double *b, const double *x, const CGWork &w,
                               int nx, int ny, int nz, int store_r,
                               const CGTiling &t, double *sink, hipStream_t s) {
-    HC_CG_DISPATCH(RES);
+    HC_CG_DISPATCH(HC_CG_SHAPES, RES);
 }
 
+hipError_t launch_cg_ir_residual(const double *b, const double *x, const CGWorkF32 &w, int nx,
+                                 int ny, int nz, const CGTiling &t, double *sink,
+                                 hipStream_t s) {
+    HC_CG_DISPATCH(HC_CG_SHAPES, IRRES);
+}
+
+#define ELEM double
 hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int nx,
                                int ny, int nz, const CGTiling &t, double *sink,
                                hipStream_t s) {
-    HC_CG_DISPATCH(DIR);
+    HC_CG_DISPATCH(HC_CG_SHAPES, DIR);
 }
 
 hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx, int ny,
                             int nz, const CGTiling &t, double *sink, hipStream_t s) {
-    HC_CG_DISPATCH(UPD);
+    HC_CG_DISPATCH(HC_CG_SHAPES, UPD);
 }
 
 hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
                            const CGTiling &t, double *sink, hipStream_t s) {
-    HC_CG_DISPATCH(LAP);
+    HC_CG_DISPATCH(HC_CG_SHAPES, LAP);
+}
+#undef ELEM
+
+#define ELEM float
+hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int nx, int ny,
+                                   int nz, const CGTiling &t, double *sink, hipStream_t s) {
+    HC_CG_DISPATCH(HC_CG_SHAPES_F32, DIR);
+}
+
+hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int nx, int ny, int nz,
+                                const CGTiling &t, double *sink, hipStream_t s) {
+    float *const x = w.d;
+    HC_CG_DISPATCH(HC_CG_SHAPES_F32, UPD);
+}
+
+hipError_t launch_lap7_f32(const float *x, float *y, int nx, int ny, int nz, const CGTiling &t,
+                           double *sink, hipStream_t s) {
+    HC_CG_DISPATCH(HC_CG_SHAPES_F32, LAP);
+}
+#undef ELEM
+
+hipError_t launch_ir_axpy(double *x, const float *d, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 1023) / 1024;
+    if (nb > 8192) nb = 8192;
+    ir_axpy<<<(unsigned)nb, 256, 0, s>>>(x, d, n);
+    return hipGetLastError();
 }
 
 }  // namespace hc

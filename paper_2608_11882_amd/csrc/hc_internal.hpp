@@ -47,7 +47,11 @@ enum KernelKind {
     K_CG_RESIDUAL = 6,
     K_LAP7 = 7,
     K_COPY = 8,
-    K_COUNT = 9
+    K_CG32_DIRECTION = 9,
+    K_CG32_UPDATE = 10,
+    K_IR_RESIDUAL = 11,
+    K_IR_UPDATE = 12,
+    K_COUNT = 13
 };
 
 // ---- heat (heat_kernels.hip) ------------------------------------------------
@@ -84,6 +88,8 @@ struct CGScalars {
     double tol;       // relative tolerance
     double thresh;    // tol * ||b||
     double rtrue2;    // |b - A x|^2 of the last true-residual pass
+    double inner_tol; // refinement: relative reduction of each inner solve
+    double floor_frac;// refinement: inner solves stop at floor_frac * tol ||b||
     int iter;         // completed iterations
     int state;        // 0 running, 1 converged, -6 breakdown, -7 non-finite
     unsigned ticket;  // arrival counter of the reductions (0 between kernels)
@@ -99,6 +105,17 @@ struct CGWork {
     CGScalars *sc;
 };
 
+// Refinement (binary32 inner solve): s (the inner residual, first the
+// rounded outer residual), p[0], p[1] padded like CGWork's vectors; d the
+// inner solution (no padding needed: only read at its own nodes).
+struct CGWorkF32 {
+    float *r;
+    float *p[2];
+    float *d;
+    double *partial;   // three doubles per block
+    CGScalars *sc;
+};
+
 // Tile shape of the CG kernels (same meaning as HeatTiling, one plane of
 // epilogue loads and two of field loads in flight).
 struct CGTiling {
@@ -110,11 +127,15 @@ struct CGTiling {
 };
 
 bool cg_tiling_supported(const CGTiling &t);
+bool cg_tiling_supported_f32(const CGTiling &t);
 size_t cg_work_bytes(int nx, int ny, int nz);
 // Carve a CGWork out of `base` (at least cg_work_bytes bytes).
 CGWork cg_work_carve(void *base, int nx, int ny, int nz);
+size_t cg_ir_work_bytes(int nx, int ny, int nz);
+CGWorkF32 cg_ir_work_carve(void *base, int nx, int ny, int nz);
 long long cg_blocks(int nx, int ny, int nz, const CGTiling &t);
-hipError_t launch_cg_init(const CGWork &w, double tol, hipStream_t s);
+hipError_t launch_cg_init(CGScalars *sc, double tol, double inner_tol, double floor_frac,
+                          hipStream_t s);
 // `sink`: a device buffer of at least kSinkDoubles doubles that lanes outside
 // the box store into (never read).
 constexpr int kSinkDoubles = 2048;
@@ -128,6 +149,18 @@ hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx, int ny,
                             int nz, const CGTiling &t, double *sink, hipStream_t s);
 hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
                            const CGTiling &t, double *sink, hipStream_t s);
+// refinement kernels (t from the binary32 shape list, except the residual,
+// whose field is binary64: t from the binary64 list)
+hipError_t launch_cg_ir_residual(const double *b, const double *x, const CGWorkF32 &w, int nx,
+                                 int ny, int nz, const CGTiling &t, double *sink,
+                                 hipStream_t s);
+hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int nx, int ny,
+                                   int nz, const CGTiling &t, double *sink, hipStream_t s);
+hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int nx, int ny, int nz,
+                                const CGTiling &t, double *sink, hipStream_t s);
+hipError_t launch_lap7_f32(const float *x, float *y, int nx, int ny, int nz, const CGTiling &t,
+                           double *sink, hipStream_t s);
+hipError_t launch_ir_axpy(double *x, const float *d, long long n, hipStream_t s);
 
 // ---- probes (probe.hip) ---------------------------------------------------------
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes,

@@ -89,6 +89,33 @@ def test_cg_validation(lib):
     assert lib.cg_solve_ex(b, x, 8, 8, 8, 1e-10, 10, FAKE_U, small, None, None, None) == HC_EINVAL
 
 
+def test_cg_ir_validation(lib):
+    b, x = FAKE_U, FAKE_V
+    f = lib.cg_solve_ir
+    out = (None, None, None)
+    assert f(None, x, 8, 8, 8, 1e-10, 10, 0.0, None, 0, None, *out) == HC_EINVAL
+    assert f(b, x, 0, 8, 8, 1e-10, 10, 0.0, None, 0, None, *out) == HC_EINVAL
+    assert f(b, x, 8, 8, 8, 0.0, 10, 0.0, None, 0, None, *out) == HC_EINVAL
+    assert f(b, x, 8, 8, 8, 1e-10, -1, 0.0, None, 0, None, *out) == HC_EINVAL
+    assert f(b, x, 8, 8, 8, 1e-10, 10, 1.0, None, 0, None, *out) == HC_EINVAL     # inner_tol
+    assert f(b, x, 8, 8, 8, 1e-10, 10, float("nan"), None, 0, None, *out) == HC_EINVAL
+    assert f(b, b, 8, 8, 8, 1e-10, 10, 0.0, None, 0, None, *out) == HC_EALIAS
+    assert f(b, x, 8, 8, 8, 1e-10, 10, 0.0, FAKE_U, 16, None, *out) == HC_EINVAL  # small work
+    n = 64
+    need = lib.cg_ir_workspace_bytes(n, n, n)
+    assert 4 * 4 * n ** 3 <= need < lib.cg_workspace_bytes(n, n, n)
+    assert lib.cg_ir_workspace_bytes(0, 4, 4) == 0
+    assert lib.hc_lap7_apply_f32(FAKE_U, FAKE_U, 4, 4, 4, None) == HC_EALIAS
+    assert lib.hc_lap7_apply_f32(None, FAKE_V, 4, 4, 4, None) == HC_EINVAL
+    assert lib.hc_cg_ir_set_tiling(8, 1, 8, 16, 0) == HC_EINVAL     # 8-node float lanes
+    assert lib.hc_cg_ir_set_tiling(4, 1, 8, 12, 0) == HC_EINVAL
+    assert lib.hc_cg_ir_set_tiling(4, 1, 8, 16, 65) == HC_EINVAL
+    assert lib.hc_cg_ir_set_tiling(2, 2, 8, 32, 3) == HC_OK
+    assert hc.get_cg_ir_tiling() == dict(vec=2, wx=2, by=8, zdepth=32, xcd=3)
+    hc.set_cg_ir_tiling()
+    assert hc.get_cg_ir_tiling() == hc.DEFAULT_CG_IR_TILING
+
+
 def test_workspace_size_formula(lib):
     n = 64
     need = lib.cg_workspace_bytes(n, n, n)
