@@ -306,6 +306,83 @@ int hc_lap7_apply_f32(const float *x, float *y, int nx, int ny, int nz,
 int hc_cg_ir_set_tiling(int vec, int wx, int by, int zdepth, int xcd);
 void hc_cg_ir_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd);
 
+/*
+ * Batched heat: many independent problems of uneven size advanced together,
+ * one launch per time step (each problem's sweep is heat_step's, bit for
+ * bit; only its launches are shared).
+ *
+ * The problems' arrays are packed one after another in one buffer per
+ * state: problem p (edges nx, ny, nz = dims[3p .. 3p+2], each >= 3, layout
+ * as for heat_step) starts hc_batch_layout's offsets[p] elements in, and
+ * every offset is a multiple of 64 bytes.
+ */
+typedef struct hc_batch hc_batch;
+
+/*
+ * hc_batch_create -- describe `count` (1 .. 2^20) problems: dims[3*count]
+ * edges, r[count] coefficients (finite, 0 <= r <= 1/6, else
+ * HC_EUNSTABLE), element type dtype (HC_F64, HC_F32 or HC_BF16 with
+ * heat_step_ex's arithmetic).  The library copies the description and keeps
+ * device tables (the problems, the work list of the current tile shape) and
+ * a stream for its graphs, all released by hc_batch_destroy.  The batch
+ * belongs to the current device.
+ */
+int hc_batch_create(int count, const int *dims, const double *r, int dtype,
+                    hc_batch **out);
+void hc_batch_destroy(hc_batch *b);
+
+/*
+ * Packed layout: offsets[count] (elements; may be NULL), the total number
+ * of elements each state buffer must hold, and the algorithmic bytes of one
+ * step of every problem (every stored node read once, every updated node
+ * written once).
+ */
+int hc_batch_layout(const hc_batch *b, long long *offsets, long long *total_elems,
+                    double *step_bytes);
+
+/*
+ * hc_batch_step -- advance every problem by `steps` steps.
+ *  u, u_new  device buffers of total_elems elements, 64-byte aligned, not
+ *            overlapping; u holds the states on entry and on return, u_new
+ *            is scratch (its Dirichlet layers are first copied from u: the
+ *            whole buffer is copied once).
+ *  use_graph 0: one kernel launch per step on `stream`; 1: the step loop is
+ *            captured once in a HIP graph (kept by the batch for these
+ *            buffers, this step count and tile shape) and launched as one
+ *            graph, joined to `stream` through events.
+ * Each launch runs a persistent kernel whose blocks walk the work list of
+ * (problem, x-tile, y-tile, z-block) entries.  Enqueued; does not wait.
+ * A problem whose nx is not a multiple of the shape's vec makes the batch
+ * fall back to one-node lanes.
+ */
+int hc_batch_step(hc_batch *b, void *u, void *u_new, int steps, int use_graph,
+                  hc_stream_t stream);
+
+/*
+ * Tile shape of the batch (as hc_heat_set_tiling, from the batch shape list
+ * of batch_kernels.hip, HC_BATCH_SHAPES_*) and `grid`, the persistent grid
+ * size (0: one block per work-list entry).  vec must divide every nx.
+ */
+int hc_batch_set_tiling(hc_batch *b, int vec, int wx, int by, int zdepth, int pf,
+                        int xcd, int grid);
+int hc_batch_get_tiling(const hc_batch *b, int *vec, int *wx, int *by, int *zdepth,
+                        int *pf, int *xcd, int *grid);
+
+/*
+ * hc_batch_autotune -- time every built batch shape whose lanes fit the
+ * problems, each with one block per work-list entry and with persistent
+ * grids of 2, 4 and 8 blocks per compute unit, over trial_steps (rounded up
+ * to even) steps of the states in u (on two scratch buffers the call
+ * allocates and frees; u is not written), and keep the fastest.  Blocks
+ * until done; *best_ms (may be NULL) receives its time per step.
+ * hc_batch_tune_result(b, i, shape7, ms) returns candidate i's shape
+ * {vec, wx, by, zdepth, pf, xcd, grid} and time per step; with i < 0 it
+ * returns the number of candidates.
+ */
+int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t stream,
+                      double *best_ms);
+int hc_batch_tune_result(const hc_batch *b, int index, int *shape7, double *ms_per_step);
+
 /* Detail of the last failure on the calling thread ("" if none). */
 const char *hc_last_error_message(void);
 
@@ -333,7 +410,8 @@ enum hc_kernel_kind {
     HC_K_CG32_UPDATE = 10,    /* d += alpha p, s -= alpha A p, s.s */
     HC_K_IR_RESIDUAL = 11,    /* r = b - A x, s = (float) r, sums */
     HC_K_IR_UPDATE = 12,      /* x += d                        */
-    HC_K_COUNT = 13
+    HC_K_BATCH = 13,          /* a batch step (graph: all steps) */
+    HC_K_COUNT = 14
 };
 int hc_prof_enable(int every);
 int hc_prof_read(int kind, double *total_ms, long long *launches,

@@ -17,7 +17,8 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "get_tiling", "DEFAULT_TILING", "set_cg_tiling", "get_cg_tiling",
            "DEFAULT_CG_TILING", "DTYPES", "HC_F64", "HC_F32", "HC_BF16",
            "AUTO_TILING", "tiling_for", "cg_solve_ir", "cg_ir_workspace_bytes",
-           "lap7_apply_f32", "set_cg_ir_tiling", "get_cg_ir_tiling", "DEFAULT_CG_IR_TILING"]
+           "lap7_apply_f32", "set_cg_ir_tiling", "get_cg_ir_tiling", "DEFAULT_CG_IR_TILING",
+           "Batch"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -27,7 +28,8 @@ HC_F64, HC_F32, HC_BF16 = 0, 1, 2
 MODES = {"split": 0, "fused": 1, "plain": 2}
 KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain": 3,
            "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8,
-           "cg32_direction": 9, "cg32_update": 10, "ir_residual": 11, "ir_update": 12}
+           "cg32_direction": 9, "cg32_update": 10, "ir_residual": 11, "ir_update": 12,
+           "batch": 13}
 
 _lib = None
 
@@ -78,6 +80,14 @@ def load():
         "cg_solve_ir": (i, [vp, vp, i, i, i, d, i, d, vp, sz, vp, ip, ip, dp]),
         "cg_ir_workspace_bytes": (sz, [i, i, i]),
         "hc_lap7_apply_f32": (i, [vp, vp, i, i, i, vp]),
+        "hc_batch_create": (i, [i, ctypes.POINTER(i), dp, i, ctypes.POINTER(vp)]),
+        "hc_batch_destroy": (None, [vp]),
+        "hc_batch_layout": (i, [vp, llp, llp, dp]),
+        "hc_batch_step": (i, [vp, vp, vp, i, i, vp]),
+        "hc_batch_set_tiling": (i, [vp, i, i, i, i, i, i, i]),
+        "hc_batch_get_tiling": (i, [vp, ip, ip, ip, ip, ip, ip, ip]),
+        "hc_batch_autotune": (i, [vp, vp, i, vp, dp]),
+        "hc_batch_tune_result": (i, [vp, i, ip, dp]),
         "hc_cg_get_tiling": (None, [ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
@@ -340,3 +350,94 @@ def prof_read(kind: str):
     b = ctypes.c_double(0.0)
     _check(load().hc_prof_read(KERNELS[kind], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
     return ms.value, n.value, b.value
+
+
+class Batch:
+    """Many independent heat problems advanced together (hc_batch_*).
+
+    ``dims``: sequence of (nx, ny, nz) storage edges; ``r``: one coefficient
+    per problem; ``dtype``: "f64", "f32" or "bf16".  States live in packed
+    buffers of ``total`` elements (``empty()`` allocates one, ``views(buf)``
+    gives each problem's (nz, ny, nx) view, ``pack`` fills one).
+    """
+
+    _TORCH = {"f64": "float64", "f32": "float32", "bf16": "bfloat16"}
+
+    def __init__(self, dims, r, dtype: str = "f32"):
+        import numpy as np
+        dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+        r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).ravel())
+        if len(r) != len(dims):
+            raise ValueError("one r per problem")
+        self.dtype = dtype
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.count = len(self.dims)
+        self._h = ctypes.c_void_p(None)
+        _check(load().hc_batch_create(self.count, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                      r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      DTYPES[dtype], ctypes.byref(self._h)))
+        offs = (ctypes.c_longlong * self.count)()
+        total = ctypes.c_longlong(0)
+        step_bytes = ctypes.c_double(0.0)
+        _check(load().hc_batch_layout(self._h, offs, ctypes.byref(total), ctypes.byref(step_bytes)))
+        self.offsets = list(offs)
+        self.total = total.value
+        self.step_bytes = step_bytes.value
+
+    def close(self):
+        if self._h:
+            load().hc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self, device="cuda"):
+        import torch
+        return torch.empty(self.total, dtype=getattr(torch, self._TORCH[self.dtype]), device=device)
+
+    def views(self, buf):
+        out = []
+        for (nx, ny, nz), off in zip(self.dims, self.offsets):
+            out.append(buf[off:off + nx * ny * nz].view(nz, ny, nx))
+        return out
+
+    def step(self, u, u_new, steps: int, graph: bool = True, stream=None) -> None:
+        for t in (u, u_new):
+            if not t.is_cuda or not t.is_contiguous() or t.numel() < self.total:
+                raise ValueError("expected contiguous CUDA buffers of %d elements" % self.total)
+        _check(load().hc_batch_step(self._h, ctypes.c_void_p(u.data_ptr()),
+                                    ctypes.c_void_p(u_new.data_ptr()), int(steps), int(bool(graph)),
+                                    _stream_handle(u, stream)))
+
+    def set_tiling(self, vec, wx, by, zdepth, pf=2, xcd=8, grid=0) -> None:
+        _check(load().hc_batch_set_tiling(self._h, int(vec), int(wx), int(by), int(zdepth), int(pf),
+                                          int(xcd), int(grid)))
+
+    def get_tiling(self) -> dict:
+        v = [ctypes.c_int(0) for _ in range(7)]
+        _check(load().hc_batch_get_tiling(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("vec", "wx", "by", "zdepth", "pf", "xcd", "grid"), (x.value for x in v)))
+
+    def autotune(self, u, trial_steps: int = 4, stream=None) -> float:
+        """Time every candidate shape on copies of u; keep the fastest.
+        Returns its milliseconds per step."""
+        best = ctypes.c_double(0.0)
+        _check(load().hc_batch_autotune(self._h, ctypes.c_void_p(u.data_ptr()), int(trial_steps),
+                                        _stream_handle(u, stream), ctypes.byref(best)))
+        return best.value
+
+    def tune_results(self) -> list:
+        lib = load()
+        n = lib.hc_batch_tune_result(self._h, -1, None, None)
+        out = []
+        for i in range(max(n, 0)):
+            sh = (ctypes.c_int * 7)()
+            ms = ctypes.c_double(0.0)
+            _check(lib.hc_batch_tune_result(self._h, i, sh, ctypes.byref(ms)))
+            out.append((dict(zip(("vec", "wx", "by", "zdepth", "pf", "xcd", "grid"), list(sh))),
+                        ms.value))
+        return out

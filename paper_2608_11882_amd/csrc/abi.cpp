@@ -6,6 +6,8 @@
 #include "hc_internal.hpp"
 
 #include <algorithm>
+#include <cstdint>
+#include <new>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -180,6 +182,7 @@ struct Pending {
     int kind;
     hipEvent_t a, b;
     double bytes;
+    long long launches;  // launches the events bracket
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -205,7 +208,8 @@ hipEvent_t pool_event() {
 // Brackets one launch with timing events while profiling is enabled.
 class Timed {
   public:
-    Timed(KernelKind kind, hipStream_t s, double bytes) : kind_(kind), s_(s), bytes_(bytes) {
+    Timed(KernelKind kind, hipStream_t s, double bytes, long long launches = 1)
+        : kind_(kind), s_(s), bytes_(bytes), launches_(launches) {
         std::lock_guard<std::mutex> g(g_prof_mu);
         if (!g_prof_on) return;
         if (g_prof_seen[kind]++ % g_prof_every != 0) return;
@@ -216,7 +220,8 @@ class Timed {
     void done() {
         if (!on_) return;
         std::lock_guard<std::mutex> g(g_prof_mu);
-        if (hipEventRecord(b_, s_) == hipSuccess) g_pending.push_back({(int)kind_, a_, b_, bytes_});
+        if (hipEventRecord(b_, s_) == hipSuccess)
+            g_pending.push_back({(int)kind_, a_, b_, bytes_, launches_});
         on_ = false;
     }
 
@@ -224,6 +229,7 @@ class Timed {
     KernelKind kind_;
     hipStream_t s_;
     double bytes_;
+    long long launches_;
     hipEvent_t a_ = nullptr, b_ = nullptr;
     bool on_ = false;
 };
@@ -616,6 +622,178 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
     return HC_ENOTCONV;
 }
 
+
+// ---- batched heat ------------------------------------------------------------
+// Automatic batch shapes per precision (the first one that is built and
+// fits; the autotuner measures them all).
+const hc::HeatTiling kBatchDefault[3] = {{2, 1, 8, 16, 2, 8}, {4, 1, 8, 16, 2, 8}, {8, 1, 8, 16, 2, 8}};
+
+}  // namespace
+
+struct hc_batch {
+    int device = 0;
+    int dtype = 0;
+    int count = 0;
+    std::vector<int> dims;          // nx, ny, nz per problem
+    std::vector<double> r;
+    std::vector<long long> offset;  // elements
+    long long total = 0;            // elements
+    double step_bytes = 0.0;        // algorithmic bytes of one step of all problems
+    hc::HeatTiling tiling{};
+    int grid = 0;                   // persistent blocks (0: one per entry)
+    hc::BatchProblem *d_probs = nullptr;
+    hc::BatchItem *d_items = nullptr;
+    int nitems = 0, items_cap = 0;
+    bool items_ok = false;
+    hipStream_t gstream = nullptr;  // capture and launch stream of the graph
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *g_u = nullptr;
+    const void *g_un = nullptr;
+    int g_steps = -1, g_key = 0, g_grid = -1;
+    std::vector<std::pair<hc::HeatTiling, int>> tune_cand;
+    std::vector<double> tune_ms;
+};
+
+namespace {
+
+int batch_shape_key(const hc::HeatTiling &t) {
+    return ((((t.vec * 8 + t.wx) * 32 + t.by) * 4 + t.pf) * 128 + t.zdepth) * 64 + t.xcd;
+}
+
+// Build the work list of the batch's current shape and upload it.
+int batch_items(hc_batch *b) {
+    if (b->items_ok) return HC_OK;
+    const hc::HeatTiling &t = b->tiling;
+    const int tx = hc::tile_width(t);
+    std::vector<hc::BatchItem> items;
+    for (int p = 0; p < b->count; ++p) {
+        const int nx = b->dims[3 * p], ny = b->dims[3 * p + 1], nz = b->dims[3 * p + 2];
+        const int ntx = (nx + tx - 1) / tx, nty = (ny - 2 + t.by - 1) / t.by;
+        if (ntx > 65535 || nty > 65535) return fail(HC_EINVAL, "problem %d has too many tiles", p);
+        const int m = nz - 2, zb = t.zdepth;
+        const int nzb = (m + zb - 1) / zb;
+        for (int z = 0; z < nzb; ++z) {
+            int kb = 1 + z * zb;
+            if (m >= zb) kb = std::min(kb, nz - 1 - zb);  // full-depth last block
+            const int ke = std::min(kb + zb - 1, nz - 2);
+            for (int x = 0; x < ntx; ++x)
+                for (int y = 0; y < nty; ++y)
+                    items.push_back({p, (unsigned short)x, (unsigned short)y, kb, ke});
+        }
+    }
+    if (items.size() > (size_t)INT32_MAX) return fail(HC_EINVAL, "work list too long");
+    if ((int)items.size() > b->items_cap) {
+        if (b->d_items) HC_TRY(hipFree(b->d_items), "hipFree");
+        b->d_items = nullptr;
+        b->items_cap = 0;
+        if (hipMalloc(&b->d_items, items.size() * sizeof(hc::BatchItem)) != hipSuccess) {
+            (void)hipGetLastError();
+            b->d_items = nullptr;
+            return fail(HC_ENOMEM, "batch work list of %zu entries", items.size());
+        }
+        b->items_cap = (int)items.size();
+    }
+    HC_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(hc::BatchItem),
+                     hipMemcpyHostToDevice),
+           "hipMemcpy (work list)");
+    b->nitems = (int)items.size();
+    b->items_ok = true;
+    return HC_OK;
+}
+
+void batch_drop_graph(hc_batch *b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->g_steps = -1;
+}
+
+// The step loop on stream s: `steps` launches alternating the buffers, then
+// the copy that leaves the result in u when steps is odd.
+int batch_enqueue(hc_batch *b, void *u, void *un, int steps, hipStream_t s) {
+    const int eb = hc::dtype_bytes(b->dtype);
+    void *a = u, *c = un;
+    for (int st = 0; st < steps; ++st) {
+        HC_TRY(hc::launch_heat_batch(b->dtype, a, c, b->d_probs, b->d_items, b->nitems, b->grid,
+                                     b->tiling, s),
+               "heat_batch launch");
+        std::swap(a, c);
+    }
+    if (a != u)
+        HC_TRY(hipMemcpyAsync(u, a, (size_t)b->total * eb, hipMemcpyDeviceToDevice, s),
+               "hipMemcpyAsync");
+    return HC_OK;
+}
+
+int batch_check_device(const hc_batch *b) {
+    int dev = 0;
+    HC_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != b->device)
+        return fail(HC_EINVAL, "batch was created on device %d, current device is %d", b->device, dev);
+    return HC_OK;
+}
+
+int batch_run(hc_batch *b, void *u, void *un, int steps, int use_graph, hipStream_t s) {
+    int rc = batch_items(b);
+    if (rc) return rc;
+    const int eb = hc::dtype_bytes(b->dtype);
+    // u_new takes u's Dirichlet layer (a copy of the whole buffer)
+    HC_TRY(hipMemcpyAsync(un, u, (size_t)b->total * eb, hipMemcpyDeviceToDevice, s),
+           "hipMemcpyAsync");
+    if (!use_graph) {
+        Timed tm(hc::K_BATCH, s, b->step_bytes * steps, steps);
+        if ((rc = batch_enqueue(b, u, un, steps, s))) return rc;
+        tm.done();
+        return HC_OK;
+    }
+    const int key = batch_shape_key(b->tiling);
+    if (!b->gexec || b->g_u != u || b->g_un != un || b->g_steps != steps || b->g_key != key ||
+        b->g_grid != b->grid) {
+        batch_drop_graph(b);
+        hipGraph_t graph = nullptr;
+        HC_TRY(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+        const int erc = batch_enqueue(b, u, un, steps, b->gstream);
+        const hipError_t ce = hipStreamEndCapture(b->gstream, &graph);
+        if (erc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return erc;
+        }
+        HC_TRY(ce, "hipStreamEndCapture");
+        const hipError_t ie = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HC_TRY(ie, "hipGraphInstantiate");
+        b->g_u = u;
+        b->g_un = un;
+        b->g_steps = steps;
+        b->g_key = key;
+        b->g_grid = b->grid;
+    }
+    // join the caller's stream in and out of the graph's stream
+    HC_TRY(hipEventRecord(b->ev_in, s), "hipEventRecord");
+    HC_TRY(hipStreamWaitEvent(b->gstream, b->ev_in, 0), "hipStreamWaitEvent");
+    {
+        Timed tm(hc::K_BATCH, b->gstream, b->step_bytes * steps, steps);
+        HC_TRY(hipGraphLaunch(b->gexec, b->gstream), "hipGraphLaunch");
+        tm.done();
+    }
+    HC_TRY(hipEventRecord(b->ev_out, b->gstream), "hipEventRecord");
+    HC_TRY(hipStreamWaitEvent(s, b->ev_out, 0), "hipStreamWaitEvent");
+    return HC_OK;
+}
+
+int batch_check_buffers(const hc_batch *b, const void *u, const void *un) {
+    if (!u || !un) return fail(HC_EINVAL, "u and u_new must be non-NULL");
+    const size_t bytes = (size_t)b->total * hc::dtype_bytes(b->dtype);
+    if (overlaps(u, bytes, un, bytes)) return fail(HC_EALIAS, "u and u_new overlap");
+    int rc = check_device_buffer(u, bytes, "u");
+    if (rc) return rc;
+    rc = check_device_buffer(un, bytes, "u_new");
+    if (rc) return rc;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(u) | reinterpret_cast<uintptr_t>(un);
+    if (a & 63) return fail(HC_EINVAL, "u and u_new must be 64-byte aligned");
+    return HC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -976,7 +1154,7 @@ int hc_prof_read(int kind, double *total_ms, long long *launches, double *algo_b
         float ms = 0.f;
         HC_TRY(hipEventElapsedTime(&ms, p.a, p.b), "hipEventElapsedTime");
         g_prof_ms[p.kind] += ms;
-        g_prof_n[p.kind] += 1;
+        g_prof_n[p.kind] += p.launches;
         g_prof_bytes[p.kind] += p.bytes;
         g_event_pool.push_back(p.a);
         g_event_pool.push_back(p.b);
@@ -985,6 +1163,248 @@ int hc_prof_read(int kind, double *total_ms, long long *launches, double *algo_b
     if (total_ms) *total_ms = g_prof_ms[kind];
     if (launches) *launches = g_prof_n[kind];
     if (algo_bytes) *algo_bytes = g_prof_bytes[kind];
+    return HC_OK;
+}
+
+// ---- batched heat -----------------------------------------------------------------
+
+int hc_batch_create(int count, const int *dims, const double *r, int dtype, hc_batch **out) {
+    g_msg.clear();
+    if (!out) return fail(HC_EINVAL, "out must be non-NULL");
+    *out = nullptr;
+    if (count < 1 || count > (1 << 20)) return fail(HC_EINVAL, "count = %d outside [1, 2^20]", count);
+    if (!dims || !r) return fail(HC_EINVAL, "dims and r must be non-NULL");
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    const long long align = 64 / hc::dtype_bytes(dtype);  // elements per 64 bytes
+    hc_batch *b = new (std::nothrow) hc_batch;
+    if (!b) return fail(HC_ENOMEM, "batch descriptor");
+    b->dtype = dtype;
+    b->count = count;
+    b->dims.assign(dims, dims + 3 * (size_t)count);
+    b->r.assign(r, r + count);
+    b->offset.resize(count);
+    long long off = 0;
+    double bytes = 0.0;
+    std::vector<hc::BatchProblem> probs(count);
+    for (int p = 0; p < count; ++p) {
+        const int nx = dims[3 * p], ny = dims[3 * p + 1], nz = dims[3 * p + 2];
+        size_t pb = 0;
+        int rc = check_dims(nx, ny, nz, 3, hc::dtype_bytes(dtype), &pb);
+        if (rc) {
+            delete b;
+            return fail(HC_EINVAL, "problem %d: edges (%d, %d, %d) must each be >= 3", p, nx, ny, nz);
+        }
+        if (!std::isfinite(r[p]) || r[p] < 0.0 || r[p] > 1.0 / 6.0) {
+            delete b;
+            return fail(HC_EUNSTABLE, "problem %d: r = %g is outside [0, 1/6]", p, r[p]);
+        }
+        b->offset[p] = off;
+        probs[p] = {off, nx, ny, nz, 0, r[p]};
+        const long long n = (long long)nx * ny * nz;
+        off += (n + align - 1) / align * align;
+        bytes += (double)hc::dtype_bytes(dtype) * ((double)n + (double)(nx - 2) * (ny - 2) * (nz - 2));
+    }
+    b->total = off;
+    b->step_bytes = bytes;
+    b->tiling = kBatchDefault[dtype];
+    int rc = HC_OK;
+    if (hipGetDevice(&b->device) != hipSuccess ||
+        hipMalloc(&b->d_probs, sizeof(hc::BatchProblem) * count) != hipSuccess ||
+        hipMemcpy(b->d_probs, probs.data(), sizeof(hc::BatchProblem) * count,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        const hipError_t e = hipGetLastError();
+        rc = fail(HC_EHIP, "batch set-up: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        hc_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return HC_OK;
+}
+
+void hc_batch_destroy(hc_batch *b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    batch_drop_graph(b);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_probs) (void)hipFree(b->d_probs);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->gstream) (void)hipStreamDestroy(b->gstream);
+    delete b;
+}
+
+int hc_batch_layout(const hc_batch *b, long long *offsets, long long *total_elems,
+                    double *step_bytes) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
+    if (offsets) std::copy(b->offset.begin(), b->offset.end(), offsets);
+    if (total_elems) *total_elems = b->total;
+    if (step_bytes) *step_bytes = b->step_bytes;
+    return HC_OK;
+}
+
+int hc_batch_set_tiling(hc_batch *b, int vec, int wx, int by, int zdepth, int pf, int xcd,
+                        int grid) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
+    const hc::HeatTiling t = {vec, wx, by, zdepth, pf, xcd};
+    if (!hc::batch_tiling_supported(b->dtype, t))
+        return fail(HC_EINVAL, "batch tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built",
+                    vec, wx, by, zdepth, pf);
+    if (grid < 0) return fail(HC_EINVAL, "grid = %d < 0", grid);
+    for (int p = 0; p < b->count; ++p)
+        if (b->dims[3 * p] % vec)
+            return fail(HC_EINVAL, "problem %d: nx = %d is not a multiple of vec = %d", p,
+                        b->dims[3 * p], vec);
+    if (batch_shape_key(t) != batch_shape_key(b->tiling)) b->items_ok = false;
+    b->tiling = t;
+    b->grid = grid;
+    return HC_OK;
+}
+
+int hc_batch_get_tiling(const hc_batch *b, int *vec, int *wx, int *by, int *zdepth, int *pf,
+                        int *xcd, int *grid) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
+    if (vec) *vec = b->tiling.vec;
+    if (wx) *wx = b->tiling.wx;
+    if (by) *by = b->tiling.by;
+    if (zdepth) *zdepth = b->tiling.zdepth;
+    if (pf) *pf = b->tiling.pf;
+    if (xcd) *xcd = b->tiling.xcd;
+    if (grid) *grid = b->grid;
+    return HC_OK;
+}
+
+int hc_batch_step(hc_batch *b, void *u, void *u_new, int steps, int use_graph,
+                  hc_stream_t stream) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
+    if (steps < 0) return fail(HC_EINVAL, "steps = %d < 0", steps);
+    int rc = batch_check_device(b);
+    if (rc) return rc;
+    if ((rc = batch_check_buffers(b, u, u_new))) return rc;
+    for (int p = 0; p < b->count; ++p)
+        if (b->dims[3 * p] % b->tiling.vec) {
+            b->tiling = {1, 1, 4, 16, 2, b->tiling.xcd};  // rows that are not whole lanes
+            b->items_ok = false;
+            break;
+        }
+    if (steps == 0) return HC_OK;
+    return batch_run(b, u, u_new, steps, use_graph, reinterpret_cast<hipStream_t>(stream));
+}
+
+int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t stream,
+                      double *best_ms) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
+    if (trial_steps < 1) return fail(HC_EINVAL, "trial_steps = %d < 1", trial_steps);
+    int rc = batch_check_device(b);
+    if (rc) return rc;
+    const size_t bytes = (size_t)b->total * hc::dtype_bytes(b->dtype);
+    if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // candidates: every built shape whose lanes fit every problem's rows,
+    // each with one block per work-list entry and with persistent grids
+    int ncu = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
+            ncu = prop.multiProcessorCount;
+    }
+    std::vector<std::pair<hc::HeatTiling, int>> cand;
+    const int vecs[4] = {1, 2, 4, 8}, wxs[3] = {1, 2, 4}, bys[3] = {4, 8, 16}, zds[2] = {16, 32};
+    for (int v : vecs)
+        for (int w : wxs)
+            for (int by : bys)
+                for (int zd : zds) {
+                    const hc::HeatTiling t = {v, w, by, zd, 2, 8};
+                    if (!hc::batch_tiling_supported(b->dtype, t)) continue;
+                    bool fits = true;
+                    for (int p = 0; p < b->count && fits; ++p) fits = b->dims[3 * p] % v == 0;
+                    if (!fits) continue;
+                    for (int g : {0, 2 * ncu, 4 * ncu, 8 * ncu}) cand.push_back({t, g});
+                }
+    if (cand.empty()) return fail(HC_EINVAL, "no built batch shape fits these problems");
+    void *sa = nullptr, *sb = nullptr;
+    if (hipMalloc(&sa, bytes) != hipSuccess || hipMalloc(&sb, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (sa) (void)hipFree(sa);
+        return fail(HC_ENOMEM, "autotuner scratch of 2 x %zu bytes", bytes);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const hc::HeatTiling keep_t = b->tiling;
+    const int keep_g = b->grid;
+    double best = INFINITY;
+    size_t best_i = 0;
+    b->tune_cand = cand;
+    b->tune_ms.assign(cand.size(), INFINITY);
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(sa);
+        (void)hipFree(sb);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(HC_EHIP, "hipEventCreate");
+    }
+    for (size_t i = 0; i < cand.size(); ++i) {
+        b->tiling = cand[i].first;
+        b->grid = cand[i].second;
+        b->items_ok = false;
+        rc = batch_items(b);
+        if (!rc && hipMemcpyAsync(sa, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            rc = fail(HC_EHIP, "hipMemcpyAsync");
+        if (!rc && hipMemcpyAsync(sb, sa, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            rc = fail(HC_EHIP, "hipMemcpyAsync");
+        if (!rc) rc = batch_enqueue(b, sa, sb, 1, s);  // warm-up
+        if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = fail(HC_EHIP, "hipEventRecord");
+        if (!rc) rc = batch_enqueue(b, sa, sb, 2 * ((trial_steps + 1) / 2), s);
+        if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(HC_EHIP, "hipEventRecord");
+        float ms = 0.f;
+        if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = fail(HC_EHIP, "timing a candidate");
+        if (rc) {
+            b->tiling = keep_t;
+            b->grid = keep_g;
+            b->items_ok = false;
+            cleanup();
+            return rc;
+        }
+        b->tune_ms[i] = ms / (2 * ((trial_steps + 1) / 2));
+        if (b->tune_ms[i] < best) {
+            best = b->tune_ms[i];
+            best_i = i;
+        }
+    }
+    cleanup();
+    b->tiling = cand[best_i].first;
+    b->grid = cand[best_i].second;
+    b->items_ok = false;
+    batch_drop_graph(b);
+    if (best_ms) *best_ms = best;
+    return batch_items(b);
+}
+
+int hc_batch_tune_result(const hc_batch *b, int index, int *shape7, double *ms_per_step) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
+    if (index < 0) return (int)b->tune_cand.size();
+    if (index >= (int)b->tune_cand.size()) return fail(HC_EINVAL, "index %d out of range", index);
+    const hc::HeatTiling &t = b->tune_cand[index].first;
+    if (shape7) {
+        const int v[7] = {t.vec, t.wx, t.by, t.zdepth, t.pf, t.xcd, b->tune_cand[index].second};
+        std::copy(v, v + 7, shape7);
+    }
+    if (ms_per_step) *ms_per_step = b->tune_ms[index];
     return HC_OK;
 }
 

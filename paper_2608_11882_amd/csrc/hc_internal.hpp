@@ -51,7 +51,8 @@ enum KernelKind {
     K_CG32_UPDATE = 10,
     K_IR_RESIDUAL = 11,
     K_IR_UPDATE = 12,
-    K_COUNT = 13
+    K_BATCH = 13,
+    K_COUNT = 14
 };
 
 // ---- heat (heat_kernels.hip) ------------------------------------------------
@@ -75,6 +76,27 @@ hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny,
                              hipStream_t s);
 hipError_t launch_copy_faces(int elem_bytes, const void *u, void *un, int nx, int ny, int nz,
                              hipStream_t s);
+
+// ---- batched heat (batch_kernels.hip) ------------------------------------------
+// One problem of a batch: its array starts `offset` elements into the packed
+// buffers.
+struct BatchProblem {
+    long long offset;
+    int nx, ny, nz, pad;
+    double r;
+};
+// One work-list entry: tile (tx, ty) of `problem`, planes kb .. ke.
+struct BatchItem {
+    int problem;
+    unsigned short tx, ty;
+    int kb, ke;
+};
+bool batch_tiling_supported(int dtype, const HeatTiling &t);
+// One time step of every problem; grid <= 0 or >= nitems: one block per
+// entry, else a persistent grid of `grid` blocks walking the list.
+hipError_t launch_heat_batch(int dtype, const void *u, void *un, const BatchProblem *probs,
+                             const BatchItem *items, int nitems, int grid,
+                             const HeatTiling &t, hipStream_t s);
 
 // ---- CG (cg_kernels.hip) ------------------------------------------------------
 // Device-resident scalars of one CG solve.  Written by the last block of

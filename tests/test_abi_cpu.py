@@ -212,3 +212,25 @@ def test_binding_raises_without_tensors():
     with pytest.raises(ValueError):
         hc.heat_step(torch.zeros(4, 4, 4, dtype=torch.float64),
                      torch.zeros(4, 4, 4, dtype=torch.float64), 0.1, 1)
+
+
+def test_batch_validation_happens_before_device_work(lib):
+    import numpy as np
+    h = ctypes.c_void_p(None)
+
+    def create(dims, r, dtype=1, count=None):
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+        rr = np.ascontiguousarray(np.asarray(r, dtype=np.float64))
+        n = len(d) if count is None else count
+        return lib.hc_batch_create(n, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   rr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), dtype,
+                                   ctypes.byref(h))
+    assert create([[10, 10, 10], [2, 5, 5]], [0.1, 0.1]) == HC_EINVAL          # edge < 3
+    assert create([[10, 10, 10]], [0.2]) == HC_EUNSTABLE
+    assert create([[10, 10, 10]], [float("nan")]) == HC_EUNSTABLE
+    assert create([[10, 10, 10]], [0.1], dtype=3) == HC_EINVAL                  # no SR batch
+    assert create([[10, 10, 10]], [0.1], count=0) == HC_EINVAL
+    assert lib.hc_batch_create(1, None, None, 1, ctypes.byref(h)) == HC_EINVAL
+    assert lib.hc_batch_step(None, FAKE_U, FAKE_V, 1, 0, None) == HC_EINVAL
+    assert lib.hc_batch_layout(None, None, None, None) == HC_EINVAL
+    lib.hc_batch_destroy(None)                                                   # no-op
