@@ -281,6 +281,76 @@ def ir_section(hc, b, xs, it64, ms64):
     }
 
 
+def batch_section(hc, dev):
+    """The batched configuration, outside the timed region: 256 FP32
+    problems with edges U{32..192} per axis, r ~ U[0.05, 0.16], U[0,1]
+    fields, 200 steps.  The batch is autotuned on its own states, then timed
+    as one captured graph of 200 persistent launches (median of 3), beside
+    the same 200 steps as direct launches and 256 sequential single-problem
+    solves (plain one-thread-per-node launches, and the fused z-march)."""
+    import numpy as np
+    import torch
+    from paper_2608_11882_amd import inputs
+    cfg = inputs.BATCHED
+    dims, rs, rng = inputs.batched_problems(cfg["count"], cfg["lo"], cfg["hi"], cfg["seed"],
+                                            cfg["r_lo"], cfg["r_hi"])
+    fields = inputs.batched_fields(dims, rng, dtype=np.float32)
+    steps = cfg["steps"]
+    batch = hc.Batch(dims, rs, "f32")
+    u0, u, un = batch.empty(dev), batch.empty(dev), batch.empty(dev)
+    for v, f in zip(batch.views(u0), fields):
+        v.copy_(torch.from_numpy(f))
+    lups = steps * sum((int(d[0]) - 2) * (int(d[1]) - 2) * (int(d[2]) - 2) for d in dims)
+    algo = steps * batch.step_bytes
+
+    def timed(fn, reps=3):
+        out = []
+        for _ in range(reps):
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return statistics.median(out)
+
+    log("batch: autotune")
+    tuned_ms = batch.autotune(u0, trial_steps=4)
+    ms_graph = timed(lambda: batch.step(u, un, steps, graph=True))
+    ms_direct = timed(lambda: batch.step(u, un, steps, graph=False))
+    log("batch: sequential single-problem solves")
+    views_u, views_un = batch.views(u), batch.views(un)
+
+    def sequential(mode):
+        for p, (a, b) in enumerate(zip(views_u, views_un)):
+            hc.heat_step(a, b, float(rs[p]), steps, mode=mode)
+    ms_plain = timed(lambda: sequential("plain"), reps=1)
+    ms_fused = timed(lambda: sequential("fused"), reps=1)
+    res = {
+        "problems": len(dims),
+        "steps": steps,
+        "lups": lups,
+        "algo_bytes_per_step": batch.step_bytes,
+        "tiling": batch.get_tiling(),
+        "autotune_ms_per_step": round(tuned_ms, 4),
+        "autotune_candidates": len(batch.tune_results()),
+        "graph": {"ms": round(ms_graph, 3), "glups": round(lups / (ms_graph / 1e3) / 1e9, 2),
+                  "algo_hbm_gbs": round(algo / (ms_graph / 1e3) / 1e9, 1),
+                  "pct_of_hbm_peak": round(100 * algo / (ms_graph / 1e3) / 1e9 / PEAK_HBM_GBS, 2)},
+        "direct_launches": {"ms": round(ms_direct, 3),
+                            "glups": round(lups / (ms_direct / 1e3) / 1e9, 2)},
+        "sequential_plain": {"ms": round(ms_plain, 3),
+                             "glups": round(lups / (ms_plain / 1e3) / 1e9, 2)},
+        "sequential_fused": {"ms": round(ms_fused, 3),
+                             "glups": round(lups / (ms_fused / 1e3) / 1e9, 2)},
+    }
+    res["speedup_vs_sequential_plain"] = round(ms_plain / ms_graph, 2)
+    batch.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +474,8 @@ def main():
         prec["cg_ir_256"] = ir_section(hc, b, xs, cg_iters, statistics.median(cg_ms))
         prec["cg_ir_256"]["f64_cg_err_vs_manufactured"] = (
             torch.linalg.norm(x - xs) / torch.linalg.norm(xs)).item()
+        log("batched configuration")
+        prec["batch_256_f32"] = batch_section(hc, dev)
 
     cpu = None
     if args.cpu_seconds > 0:

@@ -209,7 +209,7 @@ int hc_copy_probe(const void *src, void *dst, size_t bytes, hc_stream_t stream);
  *  wx      wavefronts per tile row
  *  by      rows per tile
  *  zdepth  planes per z-block
- *  pf      planes of loads kept in flight ahead of the computed one (1, 2)
+ *  pf      planes of loads kept in flight ahead of the computed one (1 to 4)
  *  xcd     0..64: runs of this many y-neighbouring tiles are dealt to one
  *          XCD (so their shared halo rows are read through one L2); 0 or 1
  *          keeps the hardware order
@@ -312,33 +312,35 @@ void hc_cg_ir_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd);
  * bit; only its launches are shared).
  *
  * The problems' arrays are packed one after another in one buffer per
- * state: problem p (edges nx, ny, nz = dims[3p .. 3p+2], each >= 3, layout
- * as for heat_step) starts hc_batch_layout's offsets[p] elements in, and
- * every offset is a multiple of 64 bytes.
+ * state.  Problem p (edges nx, ny, nz = dims[3p .. 3p+2]) starts
+ * offsets[p] elements in (a multiple of 64 bytes); node (i, j, k) is at
+ * offsets[p] + (k*ny + j)*pitches[p] + i, where pitches[p] >= nx rounds nx
+ * up to 16 bytes.  Elements i = nx .. pitch-1 of a row are padding: never
+ * read by an update, their contents are unspecified on return.
  */
 typedef struct hc_batch hc_batch;
 
 /*
  * hc_batch_create -- describe `count` (1 .. 2^20) problems: dims[3*count]
- * edges, r[count] coefficients (finite, 0 <= r <= 1/6, else
- * HC_EUNSTABLE), element type dtype (HC_F64, HC_F32 or HC_BF16 with
- * heat_step_ex's arithmetic).  The library copies the description and keeps
- * device tables (the problems, the work list of the current tile shape) and
- * a stream for its graphs, all released by hc_batch_destroy.  The batch
- * belongs to the current device.
+ * edges (each in [3, 2^20], else HC_EINVAL), r[count] coefficients
+ * (finite, 0 <= r <= 1/6, else HC_EUNSTABLE), element type dtype (HC_F64,
+ * HC_F32 or HC_BF16 with heat_step_ex's arithmetic).  The library copies
+ * the description and keeps device tables (the problems, the work list of
+ * the current tile shape) and a stream for its graphs, all released by
+ * hc_batch_destroy.  The batch belongs to the current device.
  */
 int hc_batch_create(int count, const int *dims, const double *r, int dtype,
                     hc_batch **out);
 void hc_batch_destroy(hc_batch *b);
 
 /*
- * Packed layout: offsets[count] (elements; may be NULL), the total number
- * of elements each state buffer must hold, and the algorithmic bytes of one
- * step of every problem (every stored node read once, every updated node
- * written once).
+ * Packed layout: offsets[count] and pitches[count] (elements; either may be
+ * NULL), the total number of elements each state buffer must hold, and the
+ * algorithmic bytes of one step of every problem (every stored node read
+ * once, every updated node written once; padding not counted).
  */
-int hc_batch_layout(const hc_batch *b, long long *offsets, long long *total_elems,
-                    double *step_bytes);
+int hc_batch_layout(const hc_batch *b, long long *offsets, int *pitches,
+                    long long *total_elems, double *step_bytes);
 
 /*
  * hc_batch_step -- advance every problem by `steps` steps.
@@ -351,37 +353,51 @@ int hc_batch_layout(const hc_batch *b, long long *offsets, long long *total_elem
  *            buffers, this step count and tile shape) and launched as one
  *            graph, joined to `stream` through events.
  * Each launch runs a persistent kernel whose blocks walk the work list of
- * (problem, x-tile, y-tile, z-block) entries.  Enqueued; does not wait.
- * A problem whose nx is not a multiple of the shape's vec makes the batch
- * fall back to one-node lanes.
+ * (problem, x-tile, y-tile, run of planes) entries.  Enqueued; does not
+ * wait.
  */
 int hc_batch_step(hc_batch *b, void *u, void *u_new, int steps, int use_graph,
                   hc_stream_t stream);
 
 /*
- * Tile shape of the batch (as hc_heat_set_tiling, from the batch shape list
- * of batch_kernels.hip, HC_BATCH_SHAPES_*) and `grid`, the persistent grid
- * size (0: one block per work-list entry).  vec must divide every nx.
+ * Block shape of the batch (from the list in batch_kernels.hip,
+ * HC_BATCH_SHAPES_*): vec nodes per lane (16 bytes), `threads` per block,
+ * runs walked in unrolled sub-blocks of zdepth planes, pf planes of loads
+ * in flight; `xcd` (0..64): runs of that many consecutive work-list entries
+ * dealt to the blocks of one XCD (0 or 1: hardware order);
+ * `width_class`: -1 gives every problem the tile width whose tiles cover
+ * its nx columns and ny-2 updated rows with the fewest idle threads (the
+ * wider on a tie), c = 0..4 gives every problem rows of 8 << c lanes (threads >> (3+c)
+ * rows; a class exists when that is at least 4 rows and the tile has one
+ * thread per halo element); `grid`: the persistent grid size (0: one block
+ * per work-list entry); `item_depth`: the planes per work-list entry (0: a
+ * problem's whole column; else near-equal runs of at least
+ * max(item_depth, zdepth) planes).  hc_batch_classes writes the width
+ * class each problem gets (classes[count]).
  */
-int hc_batch_set_tiling(hc_batch *b, int vec, int wx, int by, int zdepth, int pf,
-                        int xcd, int grid);
-int hc_batch_get_tiling(const hc_batch *b, int *vec, int *wx, int *by, int *zdepth,
-                        int *pf, int *xcd, int *grid);
+int hc_batch_set_tiling(hc_batch *b, int vec, int threads, int zdepth, int pf,
+                        int xcd, int width_class, int grid, int item_depth);
+int hc_batch_get_tiling(const hc_batch *b, int *vec, int *threads, int *zdepth,
+                        int *pf, int *xcd, int *width_class, int *grid,
+                        int *item_depth);
+int hc_batch_classes(hc_batch *b, int *classes);
 
 /*
- * hc_batch_autotune -- time every built batch shape whose lanes fit the
- * problems, each with one block per work-list entry and with persistent
- * grids of 2, 4 and 8 blocks per compute unit, over trial_steps (rounded up
- * to even) steps of the states in u (on two scratch buffers the call
- * allocates and frees; u is not written), and keep the fastest.  Blocks
- * until done; *best_ms (may be NULL) receives its time per step.
- * hc_batch_tune_result(b, i, shape7, ms) returns candidate i's shape
- * {vec, wx, by, zdepth, pf, xcd, grid} and time per step; with i < 0 it
- * returns the number of candidates.
+ * hc_batch_autotune -- time every built block shape with each problem's
+ * best-fitting width, hardware and XCD-grouped (8) order, whole-column and
+ * 64-plane entries, one block per entry or a persistent grid of 2 blocks
+ * per compute unit, and with every width class for all problems, over
+ * trial_steps (rounded up to even) steps of the states in u (on two
+ * scratch buffers the call allocates and frees; u is not written), and
+ * keep the fastest.  Blocks until done; *best_ms (may be NULL) receives
+ * its time per step.  hc_batch_tune_result(b, i, shape8, ms) returns
+ * candidate i's setting {vec, threads, zdepth, pf, xcd, width_class, grid,
+ * item_depth} and time per step; with i < 0 it returns the number of
+ * candidates.
  */
 int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t stream,
                       double *best_ms);
-int hc_batch_tune_result(const hc_batch *b, int index, int *shape7, double *ms_per_step);
+int hc_batch_tune_result(const hc_batch *b, int index, int *shape8, double *ms_per_step);
 
 /* Detail of the last failure on the calling thread ("" if none). */
 const char *hc_last_error_message(void);

@@ -82,10 +82,11 @@ def load():
         "hc_lap7_apply_f32": (i, [vp, vp, i, i, i, vp]),
         "hc_batch_create": (i, [i, ctypes.POINTER(i), dp, i, ctypes.POINTER(vp)]),
         "hc_batch_destroy": (None, [vp]),
-        "hc_batch_layout": (i, [vp, llp, llp, dp]),
+        "hc_batch_layout": (i, [vp, llp, ip, llp, dp]),
         "hc_batch_step": (i, [vp, vp, vp, i, i, vp]),
-        "hc_batch_set_tiling": (i, [vp, i, i, i, i, i, i, i]),
-        "hc_batch_get_tiling": (i, [vp, ip, ip, ip, ip, ip, ip, ip]),
+        "hc_batch_set_tiling": (i, [vp, i, i, i, i, i, i, i, i]),
+        "hc_batch_get_tiling": (i, [vp, ip, ip, ip, ip, ip, ip, ip, ip]),
+        "hc_batch_classes": (i, [vp, ip]),
         "hc_batch_autotune": (i, [vp, vp, i, vp, dp]),
         "hc_batch_tune_result": (i, [vp, i, ip, dp]),
         "hc_cg_get_tiling": (None, [ip, ip, ip, ip, ip]),
@@ -377,10 +378,13 @@ class Batch:
                                       r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       DTYPES[dtype], ctypes.byref(self._h)))
         offs = (ctypes.c_longlong * self.count)()
+        pitches = (ctypes.c_int * self.count)()
         total = ctypes.c_longlong(0)
         step_bytes = ctypes.c_double(0.0)
-        _check(load().hc_batch_layout(self._h, offs, ctypes.byref(total), ctypes.byref(step_bytes)))
+        _check(load().hc_batch_layout(self._h, offs, pitches, ctypes.byref(total),
+                                      ctypes.byref(step_bytes)))
         self.offsets = list(offs)
+        self.pitches = list(pitches)
         self.total = total.value
         self.step_bytes = step_bytes.value
 
@@ -400,9 +404,11 @@ class Batch:
         return torch.empty(self.total, dtype=getattr(torch, self._TORCH[self.dtype]), device=device)
 
     def views(self, buf):
+        """Each problem's (nz, ny, nx) view of a packed buffer (rows
+        ``pitch`` elements apart, so the views are strided)."""
         out = []
-        for (nx, ny, nz), off in zip(self.dims, self.offsets):
-            out.append(buf[off:off + nx * ny * nz].view(nz, ny, nx))
+        for (nx, ny, nz), off, pitch in zip(self.dims, self.offsets, self.pitches):
+            out.append(buf[off:off + pitch * ny * nz].view(nz, ny, pitch)[:, :, :nx])
         return out
 
     def step(self, u, u_new, steps: int, graph: bool = True, stream=None) -> None:
@@ -413,14 +419,23 @@ class Batch:
                                     ctypes.c_void_p(u_new.data_ptr()), int(steps), int(bool(graph)),
                                     _stream_handle(u, stream)))
 
-    def set_tiling(self, vec, wx, by, zdepth, pf=2, xcd=8, grid=0) -> None:
-        _check(load().hc_batch_set_tiling(self._h, int(vec), int(wx), int(by), int(zdepth), int(pf),
-                                          int(xcd), int(grid)))
+    _KEYS = ("vec", "threads", "zdepth", "pf", "xcd", "width_class", "grid", "item_depth")
+
+    def set_tiling(self, vec, threads, zdepth=16, pf=2, xcd=8, width_class=-1, grid=0,
+                   item_depth=0) -> None:
+        _check(load().hc_batch_set_tiling(self._h, int(vec), int(threads), int(zdepth), int(pf),
+                                          int(xcd), int(width_class), int(grid), int(item_depth)))
+
+    def classes(self) -> list:
+        """The tile width class (rows of 8 << c lanes) of every problem."""
+        out = (ctypes.c_int * self.count)()
+        _check(load().hc_batch_classes(self._h, out))
+        return list(out)
 
     def get_tiling(self) -> dict:
-        v = [ctypes.c_int(0) for _ in range(7)]
+        v = [ctypes.c_int(0) for _ in range(8)]
         _check(load().hc_batch_get_tiling(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(("vec", "wx", "by", "zdepth", "pf", "xcd", "grid"), (x.value for x in v)))
+        return dict(zip(self._KEYS, (x.value for x in v)))
 
     def autotune(self, u, trial_steps: int = 4, stream=None) -> float:
         """Time every candidate shape on copies of u; keep the fastest.
@@ -435,9 +450,8 @@ class Batch:
         n = lib.hc_batch_tune_result(self._h, -1, None, None)
         out = []
         for i in range(max(n, 0)):
-            sh = (ctypes.c_int * 7)()
+            sh = (ctypes.c_int * 8)()
             ms = ctypes.c_double(0.0)
             _check(lib.hc_batch_tune_result(self._h, i, sh, ctypes.byref(ms)))
-            out.append((dict(zip(("vec", "wx", "by", "zdepth", "pf", "xcd", "grid"), list(sh))),
-                        ms.value))
+            out.append((dict(zip(self._KEYS, list(sh))), ms.value))
         return out

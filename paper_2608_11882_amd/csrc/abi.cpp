@@ -624,9 +624,11 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
 
 
 // ---- batched heat ------------------------------------------------------------
-// Automatic batch shapes per precision (the first one that is built and
-// fits; the autotuner measures them all).
-const hc::HeatTiling kBatchDefault[3] = {{2, 1, 8, 16, 2, 8}, {4, 1, 8, 16, 2, 8}, {8, 1, 8, 16, 2, 8}};
+// Default batch shapes per precision: 16-byte lanes, blocks of 512 threads,
+// each problem with the width class that fits its rows; the autotuner
+// measures all the built ones.
+const hc::BatchTiling kBatchDefault[3] = {{2, 512, 16, 2, 8, -1}, {4, 512, 16, 2, 8, -1},
+                                          {8, 512, 16, 2, 8, -1}};
 
 }  // namespace
 
@@ -637,10 +639,13 @@ struct hc_batch {
     std::vector<int> dims;          // nx, ny, nz per problem
     std::vector<double> r;
     std::vector<long long> offset;  // elements
+    std::vector<int> pitch;         // elements between rows
     long long total = 0;            // elements
     double step_bytes = 0.0;        // algorithmic bytes of one step of all problems
-    hc::HeatTiling tiling{};
+    hc::BatchTiling tiling{};
     int grid = 0;                   // persistent blocks (0: one per entry)
+    int item_depth = 0;             // planes per work-list entry (0: whole column)
+    std::vector<hc::BatchProblem> probs;  // host copy of the problem table
     hc::BatchProblem *d_probs = nullptr;
     hc::BatchItem *d_items = nullptr;
     int nitems = 0, items_cap = 0;
@@ -650,38 +655,79 @@ struct hc_batch {
     hipGraphExec_t gexec = nullptr;
     const void *g_u = nullptr;
     const void *g_un = nullptr;
-    int g_steps = -1, g_key = 0, g_grid = -1;
-    std::vector<std::pair<hc::HeatTiling, int>> tune_cand;
+    int g_steps = -1, g_grid = -1, g_depth = -1;
+    long long g_key = 0;
+    struct Cand {
+        hc::BatchTiling t;
+        int grid, depth;
+    };
+    std::vector<Cand> tune_cand;
     std::vector<double> tune_ms;
 };
 
 namespace {
 
-int batch_shape_key(const hc::HeatTiling &t) {
-    return ((((t.vec * 8 + t.wx) * 32 + t.by) * 4 + t.pf) * 128 + t.zdepth) * 64 + t.xcd;
+long long batch_shape_key(const hc::BatchTiling &t) {
+    return (((((t.vec * 2048LL + t.threads) * 8 + t.pf) * 128 + t.zdepth) * 65 + t.xcd) * 8 +
+            (t.cls + 1));
+}
+
+// Width class of a problem with nx columns and ny - 2 updated rows, for
+// blocks of `threads`: among the valid classes whose tile covers a whole
+// row (a row split over x-tiles is read in short segments that straddle
+// cache lines), the one whose tiles cover the fewest nodes (the fewest idle
+// threads), the wider one on a tie; the widest valid class when no tile
+// covers a row.
+int batch_auto_class(int nx, int ny, int vec, int threads) {
+    int best = -1, widest = -1;
+    long long best_a = 0;
+    for (int c = 0; c <= 4; ++c) {
+        if (!hc::batch_class_valid(threads, c)) continue;
+        widest = c;
+        const long long tx = (long long)vec * (8 << c), by = threads / (8 << c);
+        if (tx < nx) continue;
+        const long long a = tx * ((ny - 2 + by - 1) / by * by);
+        if (best < 0 || a <= best_a) {
+            best = c;
+            best_a = a;
+        }
+    }
+    return best >= 0 ? best : widest;
 }
 
 // Build the work list of the batch's current shape and upload it.
 int batch_items(hc_batch *b) {
     if (b->items_ok) return HC_OK;
-    const hc::HeatTiling &t = b->tiling;
-    const int tx = hc::tile_width(t);
-    std::vector<hc::BatchItem> items;
+    const hc::BatchTiling &t = b->tiling;
+    // one list per width class, concatenated widest class first: blocks that
+    // run at the same time mostly run one class's code (the classes' unrolled
+    // bodies do not all fit the instruction cache), and the smallest tiles
+    // come last, where they even out the tail
+    std::vector<hc::BatchItem> per_class[5];
     for (int p = 0; p < b->count; ++p) {
         const int nx = b->dims[3 * p], ny = b->dims[3 * p + 1], nz = b->dims[3 * p + 2];
-        const int ntx = (nx + tx - 1) / tx, nty = (ny - 2 + t.by - 1) / t.by;
+        const int cls = t.cls >= 0 ? t.cls : batch_auto_class(nx, ny, t.vec, t.threads);
+        if (!hc::batch_class_valid(t.threads, cls))
+            return fail(HC_EINVAL, "width class %d does not exist for %d threads", cls, t.threads);
+        b->probs[p].cls = cls;
+        const int tx = t.vec * (8 << cls), by = t.threads / (8 << cls);
+        const int ntx = (nx + tx - 1) / tx, nty = (ny - 2 + by - 1) / by;
         if (ntx > 65535 || nty > 65535) return fail(HC_EINVAL, "problem %d has too many tiles", p);
-        const int m = nz - 2, zb = t.zdepth;
-        const int nzb = (m + zb - 1) / zb;
+        // planes 1 .. nz-2 in nzb near-equal runs of at least `depth`
+        // planes (the kernel walks a run in unrolled sub-blocks of zdepth)
+        const int m = nz - 2;
+        const int depth = b->item_depth > 0 ? std::max(b->item_depth, t.zdepth) : m;
+        const int nzb = std::max(1, m / depth);
         for (int z = 0; z < nzb; ++z) {
-            int kb = 1 + z * zb;
-            if (m >= zb) kb = std::min(kb, nz - 1 - zb);  // full-depth last block
-            const int ke = std::min(kb + zb - 1, nz - 2);
+            const int kb = 1 + (int)((long long)z * m / nzb);
+            const int ke = (int)((long long)(z + 1) * m / nzb);
             for (int x = 0; x < ntx; ++x)
                 for (int y = 0; y < nty; ++y)
-                    items.push_back({p, (unsigned short)x, (unsigned short)y, kb, ke});
+                    per_class[cls].push_back({p, (unsigned short)x, (unsigned short)y, kb, ke});
         }
     }
+    std::vector<hc::BatchItem> items;
+    for (int c = 4; c >= 0; --c) items.insert(items.end(), per_class[c].begin(), per_class[c].end());
     if (items.size() > (size_t)INT32_MAX) return fail(HC_EINVAL, "work list too long");
     if ((int)items.size() > b->items_cap) {
         if (b->d_items) HC_TRY(hipFree(b->d_items), "hipFree");
@@ -697,6 +743,9 @@ int batch_items(hc_batch *b) {
     HC_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(hc::BatchItem),
                      hipMemcpyHostToDevice),
            "hipMemcpy (work list)");
+    HC_TRY(hipMemcpy(b->d_probs, b->probs.data(), b->probs.size() * sizeof(hc::BatchProblem),
+                     hipMemcpyHostToDevice),
+           "hipMemcpy (problem table)");
     b->nitems = (int)items.size();
     b->items_ok = true;
     return HC_OK;
@@ -746,9 +795,9 @@ int batch_run(hc_batch *b, void *u, void *un, int steps, int use_graph, hipStrea
         tm.done();
         return HC_OK;
     }
-    const int key = batch_shape_key(b->tiling);
+    const long long key = batch_shape_key(b->tiling);
     if (!b->gexec || b->g_u != u || b->g_un != un || b->g_steps != steps || b->g_key != key ||
-        b->g_grid != b->grid) {
+        b->g_grid != b->grid || b->g_depth != b->item_depth) {
         batch_drop_graph(b);
         hipGraph_t graph = nullptr;
         HC_TRY(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
@@ -767,6 +816,7 @@ int batch_run(hc_batch *b, void *u, void *un, int steps, int use_graph, hipStrea
         b->g_steps = steps;
         b->g_key = key;
         b->g_grid = b->grid;
+        b->g_depth = b->item_depth;
     }
     // join the caller's stream in and out of the graph's stream
     HC_TRY(hipEventRecord(b->ev_in, s), "hipEventRecord");
@@ -1176,7 +1226,17 @@ int hc_batch_create(int count, const int *dims, const double *r, int dtype, hc_b
     if (!dims || !r) return fail(HC_EINVAL, "dims and r must be non-NULL");
     if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
         return fail(HC_EINVAL, "dtype %d is not supported", dtype);
-    const long long align = 64 / hc::dtype_bytes(dtype);  // elements per 64 bytes
+    const int eb = hc::dtype_bytes(dtype);
+    const long long align = 64 / eb;  // elements per 64 bytes
+    const int row_align = 16 / eb;    // elements per 16 bytes
+    for (int p = 0; p < count; ++p) {
+        const int nx = dims[3 * p], ny = dims[3 * p + 1], nz = dims[3 * p + 2];
+        if (nx < 3 || ny < 3 || nz < 3 || nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20))
+            return fail(HC_EINVAL, "problem %d: edges (%d, %d, %d) must each be in [3, 2^20]", p,
+                        nx, ny, nz);
+        if (!std::isfinite(r[p]) || r[p] < 0.0 || r[p] > 1.0 / 6.0)
+            return fail(HC_EUNSTABLE, "problem %d: r = %g is outside [0, 1/6]", p, r[p]);
+    }
     hc_batch *b = new (std::nothrow) hc_batch;
     if (!b) return fail(HC_ENOMEM, "batch descriptor");
     b->dtype = dtype;
@@ -1184,30 +1244,24 @@ int hc_batch_create(int count, const int *dims, const double *r, int dtype, hc_b
     b->dims.assign(dims, dims + 3 * (size_t)count);
     b->r.assign(r, r + count);
     b->offset.resize(count);
+    b->pitch.resize(count);
     long long off = 0;
     double bytes = 0.0;
     std::vector<hc::BatchProblem> probs(count);
     for (int p = 0; p < count; ++p) {
         const int nx = dims[3 * p], ny = dims[3 * p + 1], nz = dims[3 * p + 2];
-        size_t pb = 0;
-        int rc = check_dims(nx, ny, nz, 3, hc::dtype_bytes(dtype), &pb);
-        if (rc) {
-            delete b;
-            return fail(HC_EINVAL, "problem %d: edges (%d, %d, %d) must each be >= 3", p, nx, ny, nz);
-        }
-        if (!std::isfinite(r[p]) || r[p] < 0.0 || r[p] > 1.0 / 6.0) {
-            delete b;
-            return fail(HC_EUNSTABLE, "problem %d: r = %g is outside [0, 1/6]", p, r[p]);
-        }
+        const int pitch = (nx + row_align - 1) / row_align * row_align;
         b->offset[p] = off;
-        probs[p] = {off, nx, ny, nz, 0, r[p]};
-        const long long n = (long long)nx * ny * nz;
+        b->pitch[p] = pitch;
+        probs[p] = {off, nx, ny, nz, pitch, 0, 0, r[p]};
+        const long long n = (long long)pitch * ny * nz;
         off += (n + align - 1) / align * align;
-        bytes += (double)hc::dtype_bytes(dtype) * ((double)n + (double)(nx - 2) * (ny - 2) * (nz - 2));
+        bytes += (double)eb * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
     }
     b->total = off;
     b->step_bytes = bytes;
     b->tiling = kBatchDefault[dtype];
+    b->probs = probs;
     int rc = HC_OK;
     if (hipGetDevice(&b->device) != hipSuccess ||
         hipMalloc(&b->d_probs, sizeof(hc::BatchProblem) * count) != hipSuccess ||
@@ -1239,46 +1293,63 @@ void hc_batch_destroy(hc_batch *b) {
     delete b;
 }
 
-int hc_batch_layout(const hc_batch *b, long long *offsets, long long *total_elems,
+int hc_batch_layout(const hc_batch *b, long long *offsets, int *pitches, long long *total_elems,
                     double *step_bytes) {
     g_msg.clear();
     if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
     if (offsets) std::copy(b->offset.begin(), b->offset.end(), offsets);
+    if (pitches) std::copy(b->pitch.begin(), b->pitch.end(), pitches);
     if (total_elems) *total_elems = b->total;
     if (step_bytes) *step_bytes = b->step_bytes;
     return HC_OK;
 }
 
-int hc_batch_set_tiling(hc_batch *b, int vec, int wx, int by, int zdepth, int pf, int xcd,
-                        int grid) {
+int hc_batch_set_tiling(hc_batch *b, int vec, int threads, int zdepth, int pf, int xcd,
+                        int width_class, int grid, int item_depth) {
     g_msg.clear();
     if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
-    const hc::HeatTiling t = {vec, wx, by, zdepth, pf, xcd};
+    const hc::BatchTiling t = {vec, threads, zdepth, pf, xcd, width_class};
     if (!hc::batch_tiling_supported(b->dtype, t))
-        return fail(HC_EINVAL, "batch tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built",
-                    vec, wx, by, zdepth, pf);
+        return fail(HC_EINVAL,
+                    "batch block shape (vec %d, threads %d, zdepth %d, pf %d) is not built", vec,
+                    threads, zdepth, pf);
+    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    if (width_class != -1 && !hc::batch_class_valid(threads, width_class))
+        return fail(HC_EINVAL, "width class %d does not exist for %d threads", width_class,
+                    threads);
     if (grid < 0) return fail(HC_EINVAL, "grid = %d < 0", grid);
-    for (int p = 0; p < b->count; ++p)
-        if (b->dims[3 * p] % vec)
-            return fail(HC_EINVAL, "problem %d: nx = %d is not a multiple of vec = %d", p,
-                        b->dims[3 * p], vec);
-    if (batch_shape_key(t) != batch_shape_key(b->tiling)) b->items_ok = false;
+    if (item_depth < 0) return fail(HC_EINVAL, "item_depth = %d < 0", item_depth);
+    if (batch_shape_key(t) != batch_shape_key(b->tiling) || item_depth != b->item_depth)
+        b->items_ok = false;
     b->tiling = t;
     b->grid = grid;
+    b->item_depth = item_depth;
     return HC_OK;
 }
 
-int hc_batch_get_tiling(const hc_batch *b, int *vec, int *wx, int *by, int *zdepth, int *pf,
-                        int *xcd, int *grid) {
+int hc_batch_get_tiling(const hc_batch *b, int *vec, int *threads, int *zdepth, int *pf,
+                        int *xcd, int *width_class, int *grid, int *item_depth) {
     g_msg.clear();
     if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
     if (vec) *vec = b->tiling.vec;
-    if (wx) *wx = b->tiling.wx;
-    if (by) *by = b->tiling.by;
+    if (threads) *threads = b->tiling.threads;
     if (zdepth) *zdepth = b->tiling.zdepth;
     if (pf) *pf = b->tiling.pf;
     if (xcd) *xcd = b->tiling.xcd;
+    if (width_class) *width_class = b->tiling.cls;
     if (grid) *grid = b->grid;
+    if (item_depth) *item_depth = b->item_depth;
+    return HC_OK;
+}
+
+int hc_batch_classes(hc_batch *b, int *classes) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
+    int rc = batch_check_device(b);
+    if (rc) return rc;
+    if ((rc = batch_items(b))) return rc;
+    if (classes)
+        for (int p = 0; p < b->count; ++p) classes[p] = b->probs[p].cls;
     return HC_OK;
 }
 
@@ -1290,12 +1361,6 @@ int hc_batch_step(hc_batch *b, void *u, void *u_new, int steps, int use_graph,
     int rc = batch_check_device(b);
     if (rc) return rc;
     if ((rc = batch_check_buffers(b, u, u_new))) return rc;
-    for (int p = 0; p < b->count; ++p)
-        if (b->dims[3 * p] % b->tiling.vec) {
-            b->tiling = {1, 1, 4, 16, 2, b->tiling.xcd};  // rows that are not whole lanes
-            b->items_ok = false;
-            break;
-        }
     if (steps == 0) return HC_OK;
     return batch_run(b, u, u_new, steps, use_graph, reinterpret_cast<hipStream_t>(stream));
 }
@@ -1310,28 +1375,34 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
     const size_t bytes = (size_t)b->total * hc::dtype_bytes(b->dtype);
     if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // candidates: every built shape whose lanes fit every problem's rows,
-    // each with one block per work-list entry and with persistent grids
+    // candidates: every built shape, with whole-column, 64-plane and
+    // zdepth-plane entries, one block per entry or a persistent grid
     int ncu = 256;
     {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
             ncu = prop.multiProcessorCount;
     }
-    std::vector<std::pair<hc::HeatTiling, int>> cand;
-    const int vecs[4] = {1, 2, 4, 8}, wxs[3] = {1, 2, 4}, bys[3] = {4, 8, 16}, zds[2] = {16, 32};
-    for (int v : vecs)
-        for (int w : wxs)
-            for (int by : bys)
-                for (int zd : zds) {
-                    const hc::HeatTiling t = {v, w, by, zd, 2, 8};
-                    if (!hc::batch_tiling_supported(b->dtype, t)) continue;
-                    bool fits = true;
-                    for (int p = 0; p < b->count && fits; ++p) fits = b->dims[3 * p] % v == 0;
-                    if (!fits) continue;
-                    for (int g : {0, 2 * ncu, 4 * ncu, 8 * ncu}) cand.push_back({t, g});
+    std::vector<hc::BatchTiling> shapes;
+    hc::batch_shapes(b->dtype, shapes);
+    std::vector<hc_batch::Cand> cand;
+    for (hc::BatchTiling t : shapes) {
+        // each problem's best-fitting width, with every order, run length
+        // and grid; then every width for all problems, in one setting
+        for (int x : {0, 8})
+            for (int dep : {0, 64})
+                for (int g : {0, 2 * ncu}) {
+                    t.xcd = x;
+                    t.cls = -1;
+                    cand.push_back({t, g, dep});
                 }
-    if (cand.empty()) return fail(HC_EINVAL, "no built batch shape fits these problems");
+        for (int c = 0; c <= 4; ++c)
+            if (hc::batch_class_valid(t.threads, c)) {
+                t.xcd = 8;
+                t.cls = c;
+                cand.push_back({t, 0, 64});
+            }
+    }
     void *sa = nullptr, *sb = nullptr;
     if (hipMalloc(&sa, bytes) != hipSuccess || hipMalloc(&sb, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -1339,8 +1410,8 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
         return fail(HC_ENOMEM, "autotuner scratch of 2 x %zu bytes", bytes);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const hc::HeatTiling keep_t = b->tiling;
-    const int keep_g = b->grid;
+    const hc::BatchTiling keep_t = b->tiling;
+    const int keep_g = b->grid, keep_d = b->item_depth;
     double best = INFINITY;
     size_t best_i = 0;
     b->tune_cand = cand;
@@ -1356,53 +1427,62 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
         cleanup();
         return fail(HC_EHIP, "hipEventCreate");
     }
+    const int tsteps = 2 * ((trial_steps + 1) / 2);
+    if (hipMemcpyAsync(sa, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(sb, sa, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        cleanup();
+        return fail(HC_EHIP, "hipMemcpyAsync");
+    }
     for (size_t i = 0; i < cand.size(); ++i) {
-        b->tiling = cand[i].first;
-        b->grid = cand[i].second;
+        b->tiling = cand[i].t;
+        b->grid = cand[i].grid;
+        b->item_depth = cand[i].depth;
         b->items_ok = false;
         rc = batch_items(b);
-        if (!rc && hipMemcpyAsync(sa, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            rc = fail(HC_EHIP, "hipMemcpyAsync");
-        if (!rc && hipMemcpyAsync(sb, sa, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            rc = fail(HC_EHIP, "hipMemcpyAsync");
-        if (!rc) rc = batch_enqueue(b, sa, sb, 1, s);  // warm-up
+        // every trial runs an even number of steps from the states in sa
+        // (sa and sb are each other's scratch): warm-up pair, timed steps
+        if (!rc) rc = batch_enqueue(b, sa, sb, 2, s);
         if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = fail(HC_EHIP, "hipEventRecord");
-        if (!rc) rc = batch_enqueue(b, sa, sb, 2 * ((trial_steps + 1) / 2), s);
+        if (!rc) rc = batch_enqueue(b, sa, sb, tsteps, s);
         if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(HC_EHIP, "hipEventRecord");
         float ms = 0.f;
-        if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        if (!rc && (hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
             rc = fail(HC_EHIP, "timing a candidate");
         if (rc) {
             b->tiling = keep_t;
             b->grid = keep_g;
+            b->item_depth = keep_d;
             b->items_ok = false;
             cleanup();
             return rc;
         }
-        b->tune_ms[i] = ms / (2 * ((trial_steps + 1) / 2));
+        b->tune_ms[i] = ms / tsteps;
         if (b->tune_ms[i] < best) {
             best = b->tune_ms[i];
             best_i = i;
         }
     }
     cleanup();
-    b->tiling = cand[best_i].first;
-    b->grid = cand[best_i].second;
+    b->tiling = cand[best_i].t;
+    b->grid = cand[best_i].grid;
+    b->item_depth = cand[best_i].depth;
     b->items_ok = false;
     batch_drop_graph(b);
     if (best_ms) *best_ms = best;
     return batch_items(b);
 }
 
-int hc_batch_tune_result(const hc_batch *b, int index, int *shape7, double *ms_per_step) {
+int hc_batch_tune_result(const hc_batch *b, int index, int *shape8, double *ms_per_step) {
     g_msg.clear();
     if (!b) return fail(HC_EINVAL, "batch must be non-NULL");
     if (index < 0) return (int)b->tune_cand.size();
     if (index >= (int)b->tune_cand.size()) return fail(HC_EINVAL, "index %d out of range", index);
-    const hc::HeatTiling &t = b->tune_cand[index].first;
-    if (shape7) {
-        const int v[7] = {t.vec, t.wx, t.by, t.zdepth, t.pf, t.xcd, b->tune_cand[index].second};
-        std::copy(v, v + 7, shape7);
+    const hc::BatchTiling &t = b->tune_cand[index].t;
+    if (shape8) {
+        const int v[8] = {t.vec, t.threads, t.zdepth, t.pf, t.xcd, t.cls,
+                          b->tune_cand[index].grid, b->tune_cand[index].depth};
+        std::copy(v, v + 8, shape8);
     }
     if (ms_per_step) *ms_per_step = b->tune_ms[index];
     return HC_OK;

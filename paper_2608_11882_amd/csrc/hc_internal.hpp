@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace hc {
 
@@ -79,10 +80,12 @@ hipError_t launch_copy_faces(int elem_bytes, const void *u, void *un, int nx, in
 
 // ---- batched heat (batch_kernels.hip) ------------------------------------------
 // One problem of a batch: its array starts `offset` elements into the packed
-// buffers.
+// buffers; rows are `pitch` >= nx elements apart (padded to 16 bytes); its
+// tiles have rows of 8 << cls lanes (width class cls).
 struct BatchProblem {
     long long offset;
-    int nx, ny, nz, pad;
+    int nx, ny, nz, pitch;
+    int cls, pad;
     double r;
 };
 // One work-list entry: tile (tx, ty) of `problem`, planes kb .. ke.
@@ -91,12 +94,25 @@ struct BatchItem {
     unsigned short tx, ty;
     int kb, ke;
 };
-bool batch_tiling_supported(int dtype, const HeatTiling &t);
+// Block shape of the batched sweep: vec nodes per lane (16 bytes),
+// `threads` per block, z-runs walked in unrolled sub-blocks of `zdepth`
+// planes, `pf` planes of loads in flight, runs of `xcd` consecutive
+// work-list entries per XCD (0 or 1: hardware order), and the width class
+// of every problem (-1: each problem's best fit).  Class c has rows of
+// 8 << c lanes, threads >> (3 + c) rows.
+struct BatchTiling {
+    int vec, threads, zdepth, pf, xcd, cls;
+};
+bool batch_tiling_supported(int dtype, const BatchTiling &t);
+// Whether width class cls exists for blocks of nt threads.
+bool batch_class_valid(int nt, int cls);
+// Every block shape built for `dtype` (xcd 0, class -1).
+void batch_shapes(int dtype, std::vector<BatchTiling> &out);
 // One time step of every problem; grid <= 0 or >= nitems: one block per
 // entry, else a persistent grid of `grid` blocks walking the list.
 hipError_t launch_heat_batch(int dtype, const void *u, void *un, const BatchProblem *probs,
                              const BatchItem *items, int nitems, int grid,
-                             const HeatTiling &t, hipStream_t s);
+                             const BatchTiling &t, hipStream_t s);
 
 // ---- CG (cg_kernels.hip) ------------------------------------------------------
 // Device-resident scalars of one CG solve.  Written by the last block of

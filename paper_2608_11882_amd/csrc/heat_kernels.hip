@@ -16,24 +16,27 @@ template <class P, int VEC, int WX, int BY, int PF, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void heat_interior(
     const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
     int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd, SRKey key) {
-    const auto g = block_tile<VEC, WX, BY>(nx, ny, zt, ntx, nty, xcd, ZB);
-    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, r, g, key);
+    __shared__ typename P::C tile[tile_lds_elems<VEC, 64 * WX, BY>()];
+    const auto g = block_tile<VEC, 64 * WX, BY>(nx, ny, zt, ntx, nty, xcd, ZB);
+    heat_tile_sweep<P, VEC, 64 * WX, BY, PF, ZB>(u, un, r, g, key, tile);
 }
 
 template <class P, int VEC, int WX, int BY, int PF, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void heat_boundary(
     const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
     int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd, SRKey key) {
-    const auto g = block_tile<VEC, WX, BY>(nx, ny, zt, ntx, nty, xcd, ZB);
-    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, r, g, key);
+    __shared__ typename P::C tile[tile_lds_elems<VEC, 64 * WX, BY>()];
+    const auto g = block_tile<VEC, 64 * WX, BY>(nx, ny, zt, ntx, nty, xcd, ZB);
+    heat_tile_sweep<P, VEC, 64 * WX, BY, PF, ZB>(u, un, r, g, key, tile);
 }
 
 template <class P, int VEC, int WX, int BY, int PF, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void heat_fused(
     const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,
     int ny, typename P::C r, ZTable zt, int ntx, int nty, int xcd, SRKey key) {
-    const auto g = block_tile<VEC, WX, BY>(nx, ny, zt, ntx, nty, xcd, ZB);
-    heat_tile_sweep<P, VEC, WX, BY, PF, ZB>(u, un, r, g, key);
+    __shared__ typename P::C tile[tile_lds_elems<VEC, 64 * WX, BY>()];
+    const auto g = block_tile<VEC, 64 * WX, BY>(nx, ny, zt, ntx, nty, xcd, ZB);
+    heat_tile_sweep<P, VEC, 64 * WX, BY, PF, ZB>(u, un, r, g, key, tile);
 }
 
 // One thread per interior node, all seven values loaded from memory: the
@@ -110,17 +113,18 @@ long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt
     X(1, 4, 4, 2, 16) X(1, 1, 4, 1, 16) X(1, 1, 8, 2, 16) X(1, 1, 16, 2, 16)     \
     X(1, 4, 4, 2, 32) X(2, 1, 8, 2, 16) X(2, 1, 16, 2, 32) X(2, 2, 8, 2, 16)     \
     X(2, 2, 8, 2, 32) X(2, 2, 8, 2, 64) X(2, 4, 4, 1, 16) X(2, 4, 4, 2, 16)      \
-    X(2, 4, 4, 2, 32) X(2, 4, 4, 2, 64)
+    X(2, 4, 4, 2, 32) X(2, 4, 4, 2, 64) X(2, 4, 4, 3, 32) X(2, 4, 4, 4, 32)
 #define HC_HEAT_SHAPES_F32(X)                                                     \
     X(1, 4, 4, 2, 16) X(1, 1, 8, 2, 16) X(2, 1, 8, 2, 32) X(2, 4, 4, 2, 32)      \
     X(4, 1, 8, 2, 32) X(4, 1, 16, 2, 32) X(4, 2, 4, 2, 32) X(4, 2, 8, 2, 16)     \
-    X(4, 2, 8, 2, 32) X(4, 4, 4, 2, 16) X(4, 4, 4, 2, 32) X(4, 2, 8, 1, 32)
+    X(4, 2, 8, 2, 32) X(4, 4, 4, 2, 16) X(4, 4, 4, 2, 32) X(4, 2, 8, 1, 32)       \
+    X(4, 4, 4, 3, 16) X(4, 4, 4, 4, 16)
 #define HC_HEAT_SHAPES_BF16(X)                                                    \
     X(1, 4, 4, 2, 16) X(1, 1, 8, 2, 16) X(2, 1, 8, 2, 16) X(4, 1, 8, 2, 16)      \
     X(4, 2, 8, 2, 32) X(4, 4, 4, 2, 32) X(8, 1, 4, 2, 32) X(8, 1, 8, 2, 16)      \
     X(8, 1, 8, 2, 32) X(8, 1, 16, 2, 32) X(8, 2, 4, 2, 32) X(8, 2, 8, 2, 32)
 
-#define HC_SHAPE_KEY(V, W, B, P, Z) ((((V * 8 + W) * 32 + B) * 4 + P) * 128 + Z)
+#define HC_SHAPE_KEY(V, W, B, P, Z) ((((V * 8 + W) * 32 + B) * 8 + P) * 128 + Z)
 
 bool heat_tiling_supported(int dtype, const HeatTiling &t) {
     const int key = HC_SHAPE_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);

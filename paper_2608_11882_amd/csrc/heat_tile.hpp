@@ -14,8 +14,9 @@
 // FP64 (the paper's precision), FP32, and bfloat16 storage with FP32
 // arithmetic (each new value rounded to the nearest bfloat16, ties to even).
 //
-// Kernel design (2.5-D z-march).  A block owns a tile of 64*VEC*WX (x) by
-// BY (y) nodes -- WX wavefronts per row, VEC consecutive nodes per lane, 16
+// Kernel design (2.5-D z-march).  A block owns a tile of VEC*TXL (x) by BY
+// (y) nodes -- TXL lanes per row (a multiple of 64, or 16 or 32 so that one
+// wavefront covers several short rows), VEC consecutive nodes per lane, 16
 // bytes per lane for the wide shapes -- and walks it through a run of planes
 // [kb, ke].  Each thread keeps its column's values at k-1, k, k+1 in
 // registers, so every stored node is loaded once per z-block.  The current
@@ -23,7 +24,7 @@
 // (two coalesced rows, two columns) for the y neighbours and for the x
 // neighbours across lanes; x neighbours inside a lane's VEC nodes come from
 // its registers.  An LDS row holds node v of every lane of the row as one
-// contiguous run of 64*WX values (v = 0..VEC-1), so every LDS access of a
+// contiguous run of TXL values (v = 0..VEC-1), so every LDS access of a
 // wavefront touches consecutive words (no bank conflicts) and each node
 // costs about two LDS reads.  PF planes of loads are in flight while a plane
 // is computed.  Results are stored non-temporally: u_new is not read again
@@ -234,8 +235,8 @@ __device__ __forceinline__ void store_vec_nt(typename P::S *__restrict__ p,
 // same accesses each plane, and the compiler waits only for the loads a
 // plane needs.
 //
-// A z-block of exactly ZB planes takes the fast path: the march is fully
-// unrolled, so the register queue along z is renamed rather than copied
+// A z-range of at least ZB planes takes the fast path, in sub-blocks of
+// exactly ZB planes: the march of a sub-block is fully unrolled, so the register queue along z is renamed rather than copied
 // (a copy would have to wait for the load in flight) and PF planes of loads
 // stay in flight behind the plane being computed.  The last z-block of a
 // range is shifted back to a full ZB planes; the planes it shares with the
@@ -243,15 +244,20 @@ __device__ __forceinline__ void store_vec_nt(typename P::S *__restrict__ p,
 // Ranges shorter than ZB (the Boundary planes) take the generic loop.
 
 // LDS row layout (LD values): [left ring column] [node 0 of lanes
-// 0..64*WX-1] [node 1 of every lane] ... [node VEC-1 of every lane] [right
-// ring column]; rows 0 and BY+1 are the ring rows.
-template <int VEC, int WX, int BY>
+// 0..TXL-1] [node 1 of every lane] ... [node VEC-1 of every lane] [right
+// ring column]; rows 0 and BY+1 are the ring rows.  Thread t works on lane
+// t % TXL of tile row t / TXL.
+//
+// Rows are `pitch` nodes apart in memory (pitch >= nx, a multiple of VEC;
+// the nodes past nx are padding that no update reads).  A lane whose VEC
+// nodes reach past nx is not updated there and writes back what it read.
+template <int VEC, int TXL, int BY>
 struct TileGeom {
-    static constexpr int TX = 64 * VEC * WX;   // tile width in nodes
-    static constexpr int TXL = 64 * WX;        // lanes per tile row
+    static constexpr int TX = VEC * TXL;       // tile width in nodes
     static constexpr int LD = TX + 2;          // LDS row stride
-    static constexpr int NT = 64 * WX * BY;    // threads per block
+    static constexpr int NT = TXL * BY;        // threads per block
     static constexpr int RROW = TXL;           // threads per ring row
+    static_assert(NT % 64 == 0, "whole wavefronts");
     static_assert(NT >= 2 * RROW + 2 * BY, "one thread per ring element");
     int kb, ke;
     long long plane, own, ring;  // ring: VEC-aligned offset of the ring load
@@ -263,26 +269,26 @@ struct TileGeom {
     bool rvec;  // ring element is a VEC-wide row piece (else one node)
     int rsel;   // the node's index within the aligned VEC-wide ring load
 
-    // Tile (tx, ty) of an nx x ny plane (x-tiles of TX nodes from x = 0,
-    // y-tiles of BY rows from y = 1), planes kb_ .. ke_.
-    __device__ __forceinline__ TileGeom(int nx, int ny, int tx, int ty, int kb_, int ke_) {
+    // Tile (tx, ty) of an nx x ny plane with rows `pitch` apart (x-tiles of
+    // TX nodes from x = 0, y-tiles of BY rows from y = 1), planes kb_..ke_.
+    __device__ __forceinline__ TileGeom(int nx, int pitch, int ny, int tx, int ty, int kb_,
+                                        int ke_) {
         kb = kb_;
         ke = ke_;
         const int t = threadIdx.x;
-        const int lane = t & 63, w = t >> 6;
-        const int wy = w / WX, wx = w % WX;
+        const int gl = t % TXL;      // lane index within the tile row
+        const int wy = t / TXL;      // tile row
         const int i0 = tx * TX;
         const int j0 = 1 + ty * BY;  // first updated row of the tile
-        const int ia = i0 + (wx * 64 + lane) * VEC;
+        const int ia = i0 + gl * VEC;
         const int j = j0 + wy;
-        plane = (long long)nx * ny;
+        plane = (long long)pitch * ny;
         if (ia >= nx)  // past the last column: Dirichlet row ny-1
-            own = (long long)(ny - 1) * nx + (nx - VEC);
+            own = (long long)(ny - 1) * pitch + (pitch - VEC);
         else
-            own = (long long)min(j, ny - 1) * nx + ia;
+            own = (long long)min(j, ny - 1) * pitch + ia;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) st[v] = (ia + v >= 1) && (ia + v <= nx - 2) && (j <= ny - 2);
-        const int gl = wx * 64 + lane;  // lane index within the tile row
         const int rowb = (wy + 1) * LD;
         own_slot = rowb + 1 + gl;
         xm_slot = gl == 0 ? rowb : own_slot - 1 + (VEC - 1) * TXL;
@@ -299,7 +305,7 @@ struct TileGeom {
         if (t < 2 * RROW) {
             const int row = t / RROW, q = t % RROW;
             const int rj = row == 0 ? j0 - 1 : min(j0 + BY, ny - 1);
-            ring = (long long)rj * nx + min(i0 + q * VEC, nx - VEC);
+            ring = (long long)rj * pitch + min(i0 + q * VEC, pitch - VEC);
             rslot = (row == 0 ? 0 : (BY + 1) * LD) + 1 + q;
             rvec = true;
         } else if (t < 2 * RROW + 2 * BY) {
@@ -307,7 +313,7 @@ struct TileGeom {
             const int row = q % BY, side = q / BY;
             const int ri = max(0, min(side == 0 ? i0 - 1 : i0 + TX, nx - 1));
             rsel = ri % VEC;
-            ring = (long long)min(j0 + row, ny - 1) * nx + (ri - rsel);
+            ring = (long long)min(j0 + row, ny - 1) * pitch + (ri - rsel);
             rslot = (row + 1) * LD + (side == 0 ? 0 : TX + 1);
         } else {
             ring = own;
@@ -318,8 +324,8 @@ struct TileGeom {
 // The tile and z-block of this block in a launch over table zt: tiles are
 // numbered y fastest (runs of tiles share halo rows), then x, then z-block;
 // the last z-block of a range is shifted back to a full zb_full planes.
-template <int VEC, int WX, int BY>
-__device__ __forceinline__ TileGeom<VEC, WX, BY> block_tile(int nx, int ny, const ZTable &zt,
+template <int VEC, int TXL, int BY>
+__device__ __forceinline__ TileGeom<VEC, TXL, BY> block_tile(int nx, int ny, const ZTable &zt,
                                                             int ntx, int nty, int xcd,
                                                             int zb_full) {
     const int L = block_order(blockIdx.x, gridDim.x, xcd);
@@ -332,21 +338,27 @@ __device__ __forceinline__ TileGeom<VEC, WX, BY> block_tile(int nx, int ny, cons
     int k0 = zt.kb[rg] + (z - zt.first[rg]) * zt.depth[rg];
     if (zt.depth[rg] == zb_full && zt.ke[rg] - zt.kb[rg] + 1 >= zb_full)
         k0 = min(k0, zt.ke[rg] - zb_full + 1);
-    return TileGeom<VEC, WX, BY>(nx, ny, tx, ty, k0, min(k0 + zt.depth[rg] - 1, zt.ke[rg]));
+    return TileGeom<VEC, TXL, BY>(nx, nx, ny, tx, ty, k0, min(k0 + zt.depth[rg] - 1, zt.ke[rg]));
 }
 
-// Sweep one tile (geometry g) of u into un: planes g.kb .. g.ke.
-template <class P, int VEC, int WX, int BY, int PF, int ZB>
+// LDS values a tile of this shape stages (the plane and its ring).
+template <int VEC, int TXL, int BY>
+constexpr int tile_lds_elems() {
+    return (BY + 2) * (VEC * TXL + 2);
+}
+
+// Sweep one tile (geometry g) of u into un: planes g.kb .. g.ke, staging
+// planes in `tile` (LDS, tile_lds_elems<VEC, TXL, BY>() values).
+template <class P, int VEC, int TXL, int BY, int PF, int ZB>
 __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict__ u,
                                                 typename P::S *__restrict__ un,
                                                 typename P::C r,
-                                                const TileGeom<VEC, WX, BY> &g,
-                                                const SRKey &key) {
+                                                const TileGeom<VEC, TXL, BY> &g,
+                                                const SRKey &key, typename P::C *tile) {
     using C = typename P::C;
     using S = typename P::S;
-    using G = TileGeom<VEC, WX, BY>;
-    static_assert(PF >= 1 && PF <= 2, "prefetch depth 1 or 2");
-    __shared__ C tile[(BY + 2) * G::LD];
+    using G = TileGeom<VEC, TXL, BY>;
+    static_assert(PF >= 1 && PF <= 4 && PF < ZB, "prefetch depth 1 to 4");
     const long long plane = g.plane;
     const S *__restrict__ uo = u + g.own;
     const S *__restrict__ ur = u + g.ring;
@@ -366,12 +378,12 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
     };
     auto put = [&](const C *c, const C *gv) {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) tile[g.own_slot + v * G::TXL] = c[v];
+        for (int v = 0; v < VEC; ++v) tile[g.own_slot + v * TXL] = c[v];
         if (g.rslot >= 0) {
             tile[g.rslot] = gv[0];
             if (g.rvec) {
 #pragma unroll
-                for (int v = 1; v < VEC; ++v) tile[g.rslot + v * G::TXL] = gv[v];
+                for (int v = 1; v < VEC; ++v) tile[g.rslot + v * TXL] = gv[v];
             }
         }
     };
@@ -380,7 +392,7 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
         const C xpl = tile[g.xp_slot];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-            const int sl = g.own_slot + v * G::TXL;
+            const int sl = g.own_slot + v * TXL;
             const C xm = v == 0 ? xm0 : c[v - 1];
             const C xp = v == VEC - 1 ? xpl : c[v + 1];
             const C ym = tile[sl - G::LD];
@@ -396,25 +408,35 @@ __device__ __forceinline__ void heat_tile_sweep(const typename P::S *__restrict_
         }
     };
 
-    if (ke - kb + 1 == ZB) {
-        // q[s] = column values of plane kb-1+s, gr[s] = ring of plane kb+s
-        C q[ZB + 2][VEC];
-        C gr[ZB][VEC];
+    if (ke - kb + 1 >= ZB) {
+        // sub-blocks of exactly ZB planes from kb on, the last one shifted
+        // back to end at ke (its planes shared with the one before are
+        // computed and written twice, with the same bits); a sub-block's
+        // first two planes were loaded by the one before and come from cache
+        for (int k0 = kb;; k0 += ZB) {
+            const int k1 = min(k0, ke - ZB + 1);
+            // q[s] = column values of plane k1-1+s, gr[s] = ring of plane k1+s
+            C q[ZB + 2][VEC];
+            C gr[ZB][VEC];
 #pragma unroll
-        for (int s = 0; s < PF + 2; ++s) load_vec<P, VEC>(uo + (long long)(kb - 1 + s) * plane, q[s]);
+            for (int s = 0; s < PF + 2; ++s)
+                load_vec<P, VEC>(uo + (long long)(k1 - 1 + s) * plane, q[s]);
 #pragma unroll
-        for (int s = 0; s < PF; ++s) ld_ring((long long)(kb + s) * plane, gr[s]);
+            for (int s = 0; s < PF; ++s) ld_ring((long long)(k1 + s) * plane, gr[s]);
 #pragma unroll
-        for (int s = 0; s < ZB; ++s) {
-            const long long kp = (long long)(kb + s) * plane;
-            __syncthreads();  // the previous plane's LDS reads are done
-            put(q[s + 1], gr[s]);
-            if (s + PF < ZB) ld_ring(kp + PF * plane, gr[s + PF]);
-            __syncthreads();
-            C out[VEC];
-            update(q[s], q[s + 1], q[s + 2], out);
-            store_vec_nt<P, VEC>(vo + kp, out, g.own + kp, key);
-            if (s + 2 + PF <= ZB + 1) load_vec<P, VEC>(uo + kp + (1 + PF) * plane, q[s + 2 + PF]);
+            for (int s = 0; s < ZB; ++s) {
+                const long long kp = (long long)(k1 + s) * plane;
+                __syncthreads();  // the previous plane's LDS reads are done
+                put(q[s + 1], gr[s]);
+                if (s + PF < ZB) ld_ring(kp + PF * plane, gr[s + PF]);
+                __syncthreads();
+                C out[VEC];
+                update(q[s], q[s + 1], q[s + 2], out);
+                store_vec_nt<P, VEC>(vo + kp, out, g.own + kp, key);
+                if (s + 2 + PF <= ZB + 1)
+                    load_vec<P, VEC>(uo + kp + (1 + PF) * plane, q[s + 2 + PF]);
+            }
+            if (k1 == ke - ZB + 1) break;
         }
         return;
     }

@@ -232,5 +232,5 @@ def test_batch_validation_happens_before_device_work(lib):
     assert create([[10, 10, 10]], [0.1], count=0) == HC_EINVAL
     assert lib.hc_batch_create(1, None, None, 1, ctypes.byref(h)) == HC_EINVAL
     assert lib.hc_batch_step(None, FAKE_U, FAKE_V, 1, 0, None) == HC_EINVAL
-    assert lib.hc_batch_layout(None, None, None, None) == HC_EINVAL
+    assert lib.hc_batch_layout(None, None, None, None, None) == HC_EINVAL
     lib.hc_batch_destroy(None)                                                   # no-op

@@ -44,6 +44,7 @@ def to_torch(a):
 
 
 def to_numpy(t):
+    t = t.contiguous()
     if t.dtype == torch.bfloat16:
         return t.view(torch.int16).cpu().numpy().view(np.uint16)
     return t.cpu().numpy()
@@ -88,38 +89,59 @@ def test_small_batch_bitwise(gpu, dtype, steps, graph):
 def test_layout_is_packed_and_aligned(gpu):
     batch = gpu.Batch(SMALL_DIMS, [0.1] * len(SMALL_DIMS), "f32")
     end = 0
-    for (nx, ny, nz), off in zip(batch.dims, batch.offsets):
-        assert off % 16 == 0 and off >= end
-        end = off + nx * ny * nz
+    for (nx, ny, nz), off, pitch in zip(batch.dims, batch.offsets, batch.pitches):
+        assert off % 16 == 0 and off >= end           # 64-byte aligned problems
+        assert pitch % 4 == 0 and nx <= pitch < nx + 4  # 16-byte rows
+        end = off + pitch * ny * nz
     assert batch.total >= end and batch.total - end < 16
     want = sum(4.0 * (nx * ny * nz + (nx - 2) * (ny - 2) * (nz - 2)) for nx, ny, nz in SMALL_DIMS)
     assert batch.step_bytes == want
     batch.close()
 
 
-def test_every_batch_shape_and_grid_bitwise(gpu):
-    dims = [(64, 30, 40), (128, 9, 35), (72, 40, 20), (32, 32, 32), (192, 10, 18)]   # nx % 8 == 0
-    rs = [0.1, 0.15, 0.12, 1.0 / 6.5, 0.05]
-    for dtype, vecs in (("f32", (1, 2, 4)), ("bf16", (1, 2, 4, 8)), ("f64", (1, 2))):
+def test_every_batch_shape_class_and_grid_bitwise(gpu):
+    dims = [(64, 30, 40), (127, 9, 35), (73, 40, 20), (33, 32, 32), (190, 10, 18), (3, 5, 7),
+            (500, 6, 9)]
+    rs = [0.1, 0.15, 0.12, 1.0 / 6.5, 0.05, 0.16, 0.11]
+    lib = gpu.load()
+    for dtype in ("f32", "bf16", "f64"):
         fields = make_fields(dims, 3, dtype)
         want = [oracle_run(f, r, 5) for f, r in zip(fields, rs)]
         batch = gpu.Batch(dims, rs, dtype)
-        lib = gpu.load()
-        shapes = [(v, w, b, z) for v in vecs for w in (1, 2) for b in (4, 8, 16) for z in (16, 32)
-                  if lib.hc_batch_set_tiling(batch._h, v, w, b, z, 2, 8, 0) == 0]
-        assert len(shapes) >= 4
+        shapes = [(v, nt, z, pf) for v in (2, 4, 8) for nt in (256, 512, 1024) for z in (16, 32)
+                  for pf in (1, 2, 3)
+                  if lib.hc_batch_set_tiling(batch._h, v, nt, z, pf, 0, -1, 0, 0) == 0]
+        assert len(shapes) >= 3
         for sh in shapes:
-            for grid in (0, 7, 1024):
-                note("batch %s shape %s grid %d" % (dtype, sh, grid))
-                batch.set_tiling(*sh, grid=grid)
+            settings = [(-1, 0, 0, 8), (-1, 7, 17, 3), (-1, 1024, 64, 0)]
+            settings += [(c, 0, 64, 8) for c in range(5)
+                         if lib.hc_batch_set_tiling(batch._h, *sh, 8, c, 0, 64) == 0]
+            for cls, grid, depth, xcd in settings:
+                note("batch %s shape %s class %d grid %d depth %d xcd %d"
+                     % (dtype, sh, cls, grid, depth, xcd))
+                batch.set_tiling(*sh, xcd=xcd, width_class=cls, grid=grid, item_depth=depth)
                 got = run_batch(gpu, batch, fields, 5, graph=(grid == 7))
                 for p in range(len(dims)):
-                    assert np.array_equal(got[p], want[p]), (dtype, sh, grid, p)
+                    assert np.array_equal(got[p], want[p]), (dtype, sh, cls, grid, depth, p)
         batch.close()
 
 
-def test_graph_replays_and_odd_width_fallback(gpu):
-    dims = [(31, 20, 20), (64, 16, 18), (45, 9, 30)]      # odd widths: one-node lanes
+def test_automatic_width_classes(gpu):
+    # 16-byte lanes of 4 nodes; with 512 threads class c covers 32 << c
+    # nodes by 64 >> c rows: among the classes whose tile covers a whole
+    # row, the one leaving the fewest idle threads, the wider one on a tie
+    dims = [(30, 66, 10), (60, 34, 10), (120, 18, 10), (250, 10, 10), (500, 6, 10), (3, 9, 9),
+            (30, 10, 10), (200, 66, 10), (900, 10, 10)]
+    batch = gpu.Batch(dims, [0.1] * len(dims), "f32")
+    batch.set_tiling(4, 512)
+    assert batch.classes() == [0, 1, 2, 3, 4, 3, 3, 3, 4]
+    batch.set_tiling(4, 256)                        # 256 threads have no 128-lane class
+    assert batch.classes() == [0, 1, 2, 3, 3, 2, 2, 3, 3]
+    batch.close()
+
+
+def test_graph_replays_and_odd_widths(gpu):
+    dims = [(31, 20, 20), (64, 16, 18), (45, 9, 30)]      # odd widths: padded rows
     rs = [0.1, 0.12, 0.14]
     fields = make_fields(dims, 5, "f32")
     batch = gpu.Batch(dims, rs, "f32")
@@ -134,7 +156,7 @@ def test_graph_replays_and_odd_width_fallback(gpu):
         assert x.item() == 1000.0
         for p, (v, f) in enumerate(zip(batch.views(u), fields)):
             assert np.array_equal(v.cpu().numpy(), oracle.heat_f32(f, rs[p], 4 * rep)), (rep, p)
-    assert batch.get_tiling()["vec"] == 1
+    assert batch.get_tiling()["vec"] == 4 and batch.get_tiling()["width_class"] == -1
     batch.close()
 
 
@@ -151,7 +173,7 @@ def test_autotune_keeps_results_bitwise(gpu):
     best = batch.autotune(u, trial_steps=2)
     assert torch.equal(u, keep)                     # the tuner does not write u
     res = batch.tune_results()
-    assert len(res) >= 8 and best == min(ms for _, ms in res) and best > 0
+    assert len(res) >= 40 and best == min(ms for _, ms in res) and best > 0
     t = batch.get_tiling()
     assert any(sh == t for sh, _ in res)
     got = run_batch(gpu, batch, fields, 6)

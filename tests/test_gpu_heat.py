@@ -89,7 +89,7 @@ def built_shapes(dtype="f64"):
         for wx in (1, 2, 4):
             for by in (4, 8, 16):
                 for zd in (16, 32, 64):
-                    for pf in (1, 2):
+                    for pf in (1, 2, 3, 4):
                         if lib.hc_heat_set_tiling(code, vec, wx, by, zd, pf, 0) == 0:
                             shapes.append((vec, wx, by, zd, pf))
     hc.set_tiling(dtype=dtype)
