@@ -34,7 +34,9 @@ sys.path.insert(0, ROOT)
 METRIC = "GLUP/s + achieved HBM GB/s (7-pt heat 512³ FP64 vs FP32); CG time-to-1e-10"
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_interior_f64_512_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2608_11882_amd", "csrc", "heat_kernels.hip")
+# the sources the Interior kernel is compiled from
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2608_11882_amd", "csrc", f)
+                  for f in ("heat_kernels.hip", "heat_tile.hpp")]
 
 
 def log(msg):
@@ -42,8 +44,11 @@ def log(msg):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(launch_bytes):
@@ -321,10 +326,13 @@ def batch_section(hc, dev):
     ms_graph = timed(lambda: batch.step(u, un, steps, graph=True))
     ms_direct = timed(lambda: batch.step(u, un, steps, graph=False))
     log("batch: sequential single-problem solves")
-    views_u, views_un = batch.views(u), batch.views(un)
+    # each problem on its own, in a contiguous array of its own (a packed
+    # problem's rows are padded, so its view in the batch is strided)
+    seq_u = [torch.from_numpy(f).to(dev) for f in fields]
+    seq_un = [torch.empty_like(a) for a in seq_u]
 
     def sequential(mode):
-        for p, (a, b) in enumerate(zip(views_u, views_un)):
+        for p, (a, b) in enumerate(zip(seq_u, seq_un)):
             hc.heat_step(a, b, float(rs[p]), steps, mode=mode)
     ms_plain = timed(lambda: sequential("plain"), reps=1)
     ms_fused = timed(lambda: sequential("fused"), reps=1)
