@@ -78,6 +78,12 @@ def _configure(lib):
                                  ctypes.c_double, L, LP, LP, dp, LP]
     lib.oracle_cg_ir.restype = ctypes.c_int
     lib.oracle_heat_bf16_sr.restype = ctypes.c_int
+    lib.oracle_heat_vk_sweep_f64.argtypes = [dp, dp, dp, dp, L, L, L, ctypes.c_double]
+    lib.oracle_heat_vk_sweep_f64.restype = None
+    lib.oracle_heat_vk_f64.argtypes = [dp, dp, dp, L, L, L, ctypes.c_double, L]
+    lib.oracle_heat_vk_f64.restype = ctypes.c_int
+    lib.oracle_heat_vk_f32.argtypes = [fp, fp, fp, L, L, L, ctypes.c_float, L]
+    lib.oracle_heat_vk_f32.restype = ctypes.c_int
     return lib
 
 
@@ -317,3 +323,53 @@ def cg_ir(b: np.ndarray, tol: float, maxit: int, inner_tol: float = 1e-5,
     if st == -4:
         raise MemoryError("oracle_cg_ir: out of memory")
     return IRResult(x, st, it.value, outer.value, rel.value, list(hist[:outer.value]))
+
+
+def _same_shape(u, *others):
+    for a in others:
+        if a.shape != u.shape:
+            raise ValueError("kappa and rhs must have u's shape %s, got %s" % (u.shape, a.shape))
+
+
+def heat_vk_sweep(u: np.ndarray, kappa: np.ndarray, rhs: np.ndarray, beta: float) -> np.ndarray:
+    """One variable-coefficient step with a source (Eq. 4, flux form,
+    rhs = dt f, beta = dt / (2 h^2)); boundary kept."""
+    u, kappa, rhs = _f64_c(u), _f64_c(kappa), _f64_c(rhs)
+    _same_shape(u, kappa, rhs)
+    out = u.copy()
+    nz, ny, nx = u.shape
+    _load().oracle_heat_vk_sweep_f64(_ptr(u), _ptr(kappa), _ptr(rhs), _ptr(out), nx, ny, nz,
+                                     float(beta))
+    return out
+
+
+def heat_vk(u0: np.ndarray, kappa: np.ndarray, rhs: np.ndarray, beta: float,
+            steps: int) -> np.ndarray:
+    """``steps`` variable-coefficient steps from ``u0`` (not modified)."""
+    u, kappa, rhs = _f64_c(u0).copy(), _f64_c(kappa), _f64_c(rhs)
+    _same_shape(u, kappa, rhs)
+    nz, ny, nx = u.shape
+    rc = _load().oracle_heat_vk_f64(_ptr(u), _ptr(kappa), _ptr(rhs), nx, ny, nz, float(beta),
+                                    int(steps))
+    if rc != 0:
+        raise MemoryError("oracle_heat_vk_f64 returned %d" % rc)
+    return u
+
+
+def heat_vk_f32(u0: np.ndarray, kappa: np.ndarray, rhs: np.ndarray, beta: float,
+                steps: int) -> np.ndarray:
+    """The variable-coefficient step in binary32 throughout (beta rounded to
+    binary32 once; kappa and rhs taken as binary32 arrays)."""
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float32)  # noqa: E731
+    u, kappa, rhs = f(u0).copy(), f(kappa), f(rhs)
+    if u.ndim != 3:
+        raise ValueError("expected a 3-D (nz, ny, nx) array")
+    _same_shape(u, kappa, rhs)
+    nz, ny, nx = u.shape
+    P = ctypes.POINTER(ctypes.c_float)
+    rc = _load().oracle_heat_vk_f32(u.ctypes.data_as(P), kappa.ctypes.data_as(P),
+                                    rhs.ctypes.data_as(P), nx, ny, nz, float(np.float32(beta)),
+                                    int(steps))
+    if rc != 0:
+        raise MemoryError("oracle_heat_vk_f32 returned %d" % rc)
+    return u

@@ -667,3 +667,125 @@ int oracle_cg_ir(const double *b, double *x, long nx, long ny, long nz, double t
     free(r); free(s); free(d); free(p); free(q);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Heat equation, variable coefficient with a source (the paper's equation)  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * One explicit step of Eq. (1), du/dt = div(kappa grad u) + f, by Eq. (4):
+ *
+ *   u_new = u + rhs + beta * (D_x + D_y + D_z),   rhs = dt f,  beta = dt/(2h^2)
+ *
+ * as the heat3d pseudocode stores it (its initialisation loop fills rhs with
+ * dt*f and kappa per node; the step adds rhs and beta times the operator).
+ * The paper does not spell out D_x.  It is read here as the conservative
+ * (flux) difference whose face coefficient is the sum of the coefficients of
+ * the face's two nodes, i.e. twice their arithmetic mean -- which is what the
+ * 1/2 in beta compensates:
+ *
+ *   D_x = (k[i] + k[i+1]) (u[i+1] - u[i]) - (k[i-1] + k[i]) (u[i] - u[i-1])
+ *
+ * and likewise along y and z.  With kappa constant it is 2 kappa times the
+ * second difference, i.e. the constant-coefficient step with r = 2 kappa beta.
+ * Evaluation order (fixed, no contraction): each D as written, then
+ * L = (D_x + D_y) + D_z, then u_new = (u + rhs) + beta * L.  Boundary nodes
+ * (the outermost layer) are Dirichlet nodes and are never written; kappa and
+ * rhs are read only where the formula reads them.
+ */
+void oracle_heat_vk_sweep_f64(const double *u, const double *kap,
+                              const double *rhs, double *un, long nx, long ny,
+                              long nz, double beta)
+{
+    const long sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 1; k < nz - 1; ++k)
+        for (long j = 1; j < ny - 1; ++j)
+            for (long i = 1; i < nx - 1; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const double c = u[p], kc = kap[p];
+                const double dx = (kc + kap[p + sx]) * (u[p + sx] - c) -
+                                  (kap[p - sx] + kc) * (c - u[p - sx]);
+                const double dy = (kc + kap[p + sy]) * (u[p + sy] - c) -
+                                  (kap[p - sy] + kc) * (c - u[p - sy]);
+                const double dz = (kc + kap[p + sz]) * (u[p + sz] - c) -
+                                  (kap[p - sz] + kc) * (c - u[p - sz]);
+                const double lop = (dx + dy) + dz;
+                un[p] = (c + rhs[p]) + beta * lop;
+            }
+}
+
+/*
+ * `steps` variable-coefficient steps with ping-pong buffers and a swap after
+ * each (the time loop of the heat3d pseudocode, with an integer step count).
+ * kappa and rhs do not change between steps.  Returns 0, or -4 when out of
+ * memory.
+ */
+int oracle_heat_vk_f64(double *u, const double *kap, const double *rhs,
+                       long nx, long ny, long nz, double beta, long steps)
+{
+    const long n = nx * ny * nz;
+    if (steps <= 0)
+        return 0;
+    double *w = (double *)malloc((size_t)n * sizeof(double));
+    if (!w)
+        return -4;
+    memcpy(w, u, (size_t)n * sizeof(double));
+    double *a = u, *b = w;
+    for (long s = 0; s < steps; ++s) {
+        oracle_heat_vk_sweep_f64(a, kap, rhs, b, nx, ny, nz, beta);
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != u)
+        memcpy(u, a, (size_t)n * sizeof(double));
+    free(w);
+    return 0;
+}
+
+/* The same step in binary32 throughout (beta rounded to binary32 once). */
+void oracle_heat_vk_sweep_f32(const float *u, const float *kap,
+                              const float *rhs, float *un, long nx, long ny,
+                              long nz, float beta)
+{
+    const long sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 1; k < nz - 1; ++k)
+        for (long j = 1; j < ny - 1; ++j)
+            for (long i = 1; i < nx - 1; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const float c = u[p], kc = kap[p];
+                const float dx = (kc + kap[p + sx]) * (u[p + sx] - c) -
+                                 (kap[p - sx] + kc) * (c - u[p - sx]);
+                const float dy = (kc + kap[p + sy]) * (u[p + sy] - c) -
+                                 (kap[p - sy] + kc) * (c - u[p - sy]);
+                const float dz = (kc + kap[p + sz]) * (u[p + sz] - c) -
+                                 (kap[p - sz] + kc) * (c - u[p - sz]);
+                const float lop = (dx + dy) + dz;
+                un[p] = (c + rhs[p]) + beta * lop;
+            }
+}
+
+int oracle_heat_vk_f32(float *u, const float *kap, const float *rhs, long nx,
+                       long ny, long nz, float beta, long steps)
+{
+    const long n = nx * ny * nz;
+    if (steps <= 0)
+        return 0;
+    float *w = (float *)malloc((size_t)n * sizeof(float));
+    if (!w)
+        return -4;
+    memcpy(w, u, (size_t)n * sizeof(float));
+    float *a = u, *b = w;
+    for (long s = 0; s < steps; ++s) {
+        oracle_heat_vk_sweep_f32(a, kap, rhs, b, nx, ny, nz, beta);
+        float *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != u)
+        memcpy(u, a, (size_t)n * sizeof(float));
+    free(w);
+    return 0;
+}

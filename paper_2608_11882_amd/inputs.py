@@ -151,6 +151,53 @@ def sine_field_lowp(nx: int, ny: int, nz: int, noise: float, seed: int, dtype: s
     return out
 
 
+# --- the paper's test case: variable coefficient and source ----------------
+
+KAPPA_MEAN, KAPPA_AMP, KAPPA_MAX = 0.5, 0.45, 0.95   # Eq. (2), alg:heat3d
+
+
+def paper_problem(n: int, dtype=np.float64) -> dict:
+    """The paper's test case on an n^3 grid (Eq. 2, 3, 5 and the set-up of
+    alg:heat3d): h = 1/(n-1), dt = h^2 / (12 kappa_max), beta = dt/(2 h^2);
+    kappa = 0.5 + 0.45 sin(pi x) sin(pi y) sin(pi z) and
+    rhs = dt (1 + cos(pi x) cos(pi y) cos(pi z)) at every node;
+    u0 = sin(pi x) sin(pi y) sin(pi z) inside, 0 on the boundary layer.
+
+    Returns dict(u0, kappa, rhs, beta, dt, h), arrays (n, n, n) of dtype
+    (each value computed in float64 and rounded once)."""
+    _check_dims(n, n, n)
+    h = 1.0 / (n - 1)
+    dt = h * h / (12.0 * KAPPA_MAX)
+    beta = dt / (2.0 * h * h)
+    x = node_coords(n)
+    s, c = np.sin(np.pi * x), np.cos(np.pi * x)
+    s2, c2 = s[:, None] * s[None, :], c[:, None] * c[None, :]
+    kappa = np.empty((n, n, n), dtype=dtype)
+    rhs = np.empty((n, n, n), dtype=dtype)
+    u0 = np.zeros((n, n, n), dtype=dtype)
+    for k in range(n):
+        kappa[k] = KAPPA_MEAN + KAPPA_AMP * (s[k] * s2)
+        rhs[k] = dt * (1.0 + c[k] * c2)
+        if 0 < k < n - 1:
+            u0[k, 1:-1, 1:-1] = (s[k] * s2)[1:-1, 1:-1]
+    return dict(u0=u0, kappa=kappa, rhs=rhs, beta=beta, dt=dt, h=h)
+
+
+def random_coefficients(nx: int, ny: int, nz: int, seed: int, k_lo: float = 0.05,
+                        k_hi: float = KAPPA_MAX, f_amp: float = 1e-3, dtype=np.float64):
+    """kappa ~ U[k_lo, k_hi] and rhs ~ U[-f_amp, f_amp] at every node (the
+    boundary layer included: the update reads kappa there), drawn plane by
+    plane, kappa's plane before rhs's.  Returns (kappa, rhs)."""
+    _check_dims(nx, ny, nz)
+    rng = np.random.default_rng(seed)
+    kappa = np.empty((nz, ny, nx), dtype=dtype)
+    rhs = np.empty((nz, ny, nx), dtype=dtype)
+    for k in range(nz):
+        kappa[k] = rng.uniform(k_lo, k_hi, size=(ny, nx))
+        rhs[k] = rng.uniform(-f_amp, f_amp, size=(ny, nx))
+    return kappa, rhs
+
+
 # --- the configurations the library is measured and tested on -------------
 
 def heat_small_f64(seed: int = 1, n: int = 66) -> np.ndarray:
@@ -168,3 +215,4 @@ HEAT_LARGE = dict(n=512, r=1.0 / 6.5, steps=1000, seed=2)
 HEAT_PRECISION = dict(n=1024, r=0.15, steps=500, seed=3)
 CG_LARGE = dict(n=256, tol=1e-10, maxit=10000, seed=4)
 BATCHED = dict(count=256, lo=32, hi=192, r_lo=0.05, r_hi=0.16, steps=200, seed=5)
+VARCOEF = dict(n=512, steps=500)     # the paper's test case (its runs: 500 steps)

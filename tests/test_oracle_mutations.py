@@ -14,6 +14,7 @@ import test_oracle_heat as heat_pins
 import test_oracle_ir as ir_pins
 import test_oracle_precision as prec_pins
 import test_oracle_sr as sr_pins
+import test_oracle_vk as vk_pins
 
 HEAT_PINS = [
     lambda: heat_pins.test_single_sine_mode_decays_by_exact_factor((13, 9, 7), (2, 3, 1), 0.16, 15),
@@ -53,7 +54,30 @@ IR_PINS = [
     ir_pins.test_refinement_converges_in_few_steps_near_the_f64_iteration_count,
 ]
 
+VK_PINS = [
+    lambda: vk_pins.test_step_matches_sparse_divergence_operator((9, 7, 6), 1),
+    lambda: vk_pins.test_exact_closed_form_on_linear_fields((2, -3, 5)),
+    vk_pins.test_operator_converges_to_the_continuous_divergence_at_second_order,
+    vk_pins.test_constant_coefficient_is_the_seven_point_step,
+    vk_pins.test_source_only_cases_are_exact,
+    vk_pins.test_operator_is_symmetric_on_fields_vanishing_on_the_boundary,
+    vk_pins.test_steps_compose_and_dirichlet_layer_is_never_written,
+    vk_pins.test_f32_step_against_f64_within_rounding_and_exact_on_integers,
+]
+
 MUTATIONS = {
+    "vk_face_single_node": ("const double dx = (kc + kap[p + sx]) * (u[p + sx] - c) -",
+                            "const double dx = (kc + kc) * (u[p + sx] - c) -", VK_PINS),
+    "vk_source_dropped": ("const double lop = (dx + dy) + dz;\n                un[p] = (c + rhs[p]) + beta * lop;",
+                          "const double lop = (dx + dy) + dz;\n                un[p] = c + beta * lop;", VK_PINS),
+    "vk_z_face_uses_y_stride": ("(kap[p - sz] + kc) * (c - u[p - sz]);\n                const double lop",
+                                "(kap[p - sy] + kc) * (c - u[p - sz]);\n                const double lop", VK_PINS),
+    "vk_dy_sign": ("const double lop = (dx + dy) + dz;", "const double lop = (dx - dy) + dz;", VK_PINS),
+    "vk_kappa_rhs_swapped": ("oracle_heat_vk_sweep_f64(a, kap, rhs, b, nx, ny, nz, beta);",
+                             "oracle_heat_vk_sweep_f64(a, rhs, kap, b, nx, ny, nz, beta);", VK_PINS),
+    "vk_f32_beta_sign": ("const float lop = (dx + dy) + dz;\n                un[p] = (c + rhs[p]) + beta * lop;",
+                         "const float lop = (dx + dy) + dz;\n                un[p] = (c + rhs[p]) - beta * lop;", VK_PINS),
+    "vk_f32_x_face_index": ("const float dx = (kc + kap[p + sx])", "const float dx = (kc + kap[p - sx])", VK_PINS),
     "ir_update_sign": ("x[t] = x[t] + (double)d[t];", "x[t] = x[t] - (double)d[t];", IR_PINS),
     "ir_alpha_inverted": ("const float alpha = (float)(rho / pq);", "const float alpha = (float)(pq / rho);", IR_PINS),
     "ir_f32_operator_y_for_z": ("const float zp = (k < nz - 1) ? x[p + sz] : 0.0f;",
