@@ -359,6 +359,78 @@ def batch_section(hc, dev):
     return res
 
 
+PAPER_KBAR_S = 6.4042e-11   # s per interior point and step, FP64 var-kappa, H100, 1 GPU
+
+
+def vk_section(hc, dev):
+    """The paper's own equation (variable kappa, source term; Eq. 1-4) on its
+    test case (Eq. 2, 3, 5) at 512^3, outside the timed region: 500 steps
+    (the paper's runs) in the split, fused and plain forms, FP64 and FP32,
+    the Interior kernel's own rate from sampled HIP events, and the FP32
+    result's error against FP64."""
+    import torch
+    from paper_2608_11882_amd import inputs
+    cfg = inputs.VARCOEF
+    n, steps = cfg["n"], cfg["steps"]
+    log("varcoef: paper problem %d^3" % n)
+    pb = inputs.paper_problem(n)
+    beta = pb["beta"]
+    lups = steps * (n - 2) ** 3
+    algo_step = 8.0 * 2 * (n ** 3 + (n - 2) ** 3)   # u, kappa over all nodes; rhs, u_new inside
+    res = {"grid": [n, n, n], "steps": steps, "beta": beta, "dt": pb["dt"],
+           "algo_bytes_per_lup_f64": 32, "paper_kbar_glups_h100": round(1e-9 / PAPER_KBAR_S, 2)}
+
+    def run(u0, kap, rhs, mode, u, un):
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hc.heat_vk_step(u, un, kap, rhs, beta, steps, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    out64 = None
+    for dt, npdt in (("f64", "float64"), ("f32", "float32")):
+        tdt = getattr(torch, npdt)
+        u0 = torch.from_numpy(pb["u0"]).to(dev, tdt)
+        kap = torch.from_numpy(pb["kappa"]).to(dev, tdt)
+        rhs = torch.from_numpy(pb["rhs"]).to(dev, tdt)
+        u, un = torch.empty_like(u0), torch.empty_like(u0)
+        eb = 8 if dt == "f64" else 4
+        forms = {}
+        for mode in ("split", "fused", "plain"):
+            ms = run(u0, kap, rhs, mode, u, un)
+            forms[mode] = {"ms": round(ms, 3), "glups": round(lups / (ms / 1e3) / 1e9, 2),
+                           "algo_hbm_gbs": round(steps * algo_step * eb / 8 / (ms / 1e3) / 1e9, 1)}
+        hc.prof_enable(True, every=8)
+        run(u0, kap, rhs, "split", u, un)
+        ims, inb, ibytes = hc.prof_read("vk_interior")
+        hc.prof_enable(False)
+        ok = bool(torch.isfinite(u).all().item()) and float(u.min()) >= 0.0
+        entry = {"tiling": hc.vk_tiling_for(u, un, kap, rhs), "forms_500_steps": forms,
+                 "result_ok_nonnegative_finite": ok}
+        if inb:
+            avg = ims / inb
+            entry["interior_kernel"] = {
+                "avg_launch_us": round(avg * 1e3, 2), "timed_launches": inb,
+                "algo_bytes_per_launch": ibytes / inb,
+                "achieved_gbs": round(ibytes / inb / (avg / 1e3) / 1e9, 1),
+                "frac_of_hbm_peak": round(ibytes / inb / (avg / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        if dt == "f64":
+            out64 = u.clone()
+            entry["vs_paper_kbar_h100"] = round(forms["split"]["glups"] * PAPER_KBAR_S * 1e9, 2)
+        else:
+            d = u.double() - out64
+            entry["max_err_vs_f64"] = float(d.abs().max())
+            entry["rel_l2_err_vs_f64"] = float(torch.linalg.norm(d) / torch.linalg.norm(out64))
+        res[dt] = entry
+        del u0, kap, rhs, u, un
+    del out64
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -475,7 +547,7 @@ def main():
         torch.cuda.synchronize()
         variants[mode] = round(100 * (n - 2) ** 3 / (e0.elapsed_time(e1) / 1e3) / 1e9, 2)
 
-    prec = None
+    prec = varcoef = None
     if args.precision:
         prec = precision_section(hc, dev, u_init, r, nsteps, args.cpu_seconds > 0)
         log("precision: CG with binary32 inner solves")
@@ -484,6 +556,7 @@ def main():
             torch.linalg.norm(x - xs) / torch.linalg.norm(xs)).item()
         log("batched configuration")
         prec["batch_256_f32"] = batch_section(hc, dev)
+        varcoef = vk_section(hc, dev)
 
     cpu = None
     if args.cpu_seconds > 0:
@@ -535,6 +608,7 @@ def main():
             "update_kernel_avg_us": round(1e3 * cgb_ms / max(cgb_n, 1), 2),
         },
         "precision": prec,
+        "varcoef_512": varcoef,
         "copy_probe_gbs": round(copy_gbs, 1),
         "roofline": {
             "kernel": "heat_interior_f64",

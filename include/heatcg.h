@@ -139,6 +139,58 @@ int heat_step_sr(void *u, void *u_new, int nx, int ny, int nz, double r,
                  int mode, int parts, hc_stream_t stream);
 
 /*
+ * heat_vk_step -- the paper's own equation: `steps` explicit steps of
+ * du/dt = div(kappa grad u) + f with kappa and f varying per node (Eq. 1-4
+ * of "Mathematical Details", the time loop of Pseudocode alg:heat3d).  For
+ * every interior node and each step, in this order and without contraction:
+ *     D_x   = (k + k_x+) (u_x+ - u) - (k_x- + k) (u - u_x-)   (D_y, D_z alike)
+ *     u_new = (u + rhs) + beta * ((D_x + D_y) + D_z)
+ * i.e. the flux form with the sum of the two nodes' coefficients on each
+ * face (twice their mean, which the 1/2 in beta = dt/(2 h^2) compensates),
+ * followed by a swap of u and u_new.  With kappa constant it is heat_step
+ * with r = 2 kappa beta (up to rounding).
+ *
+ *  u, u_new  as for heat_step_ex (u^0 in, u^steps out; u_new scratch whose
+ *            outermost layer is overwritten with u's).
+ *  kappa  [in] nx*ny*nz, device: the coefficient at every node, the
+ *         outermost layer included (faces next to the boundary read it).
+ *  rhs    [in] nx*ny*nz, device: dt * f at every node (read at interior
+ *         nodes only).  kappa and rhs are not written and must not overlap
+ *         u or u_new; they may be the same buffer.
+ *  beta   dt / (2 h^2); finite and >= 0, else HC_EUNSTABLE.  The step keeps
+ *         the discrete maximum principle (rhs = 0) while beta times the sum
+ *         of a node's six face coefficients is <= 1: with kappa <= kmax that
+ *         is beta <= 1 / (12 kmax), the paper's choice dt = h^2 / (12 kmax)
+ *         gives beta = 1 / (24 kmax).  The library does not read kappa to
+ *         check it.
+ *  dtype  HC_F64 (the paper's precision) or HC_F32 (every array and every
+ *         operation binary32, beta rounded to binary32 once).
+ *  mode, parts, stream  as for heat_step_ex (HC_HEAT_SPLIT: Interior kernel
+ *         on `stream`, Boundary planes on the internal stream).
+ * Moves 4 values per updated node and step (u, kappa, rhs in, u_new out).
+ * Enqueues and returns; HC_EINVAL, HC_EALIAS as for heat_step_ex.
+ */
+int heat_vk_step(void *u, void *u_new, const void *kappa, const void *rhs,
+                 int nx, int ny, int nz, double beta, int steps, int dtype,
+                 int mode, int parts, hc_stream_t stream);
+
+/*
+ * Tile shape of the variable-coefficient sweep, per dtype (HC_F64, HC_F32),
+ * same fields and rules as hc_heat_set_tiling; the shapes built are listed
+ * in varcoef_kernels.hip (HC_VK_SHAPES_*).  All zeros (the default) selects
+ * the automatic choice.  hc_heat_vk_tiling_for reports the shape a sweep of
+ * these four arrays would run with (the one-node shape when a wide lane does
+ * not fit nx or the alignment of any of them).
+ */
+int hc_heat_vk_set_tiling(int dtype, int vec, int wx, int by, int zdepth,
+                          int pf, int xcd);
+int hc_heat_vk_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth,
+                          int *pf, int *xcd);
+int hc_heat_vk_tiling_for(int dtype, int nx, const void *u, const void *u_new,
+                          const void *kappa, const void *rhs, int *vec,
+                          int *wx, int *by, int *zdepth, int *pf, int *xcd);
+
+/*
  * cg_solve -- solve A x = b with Conjugate Gradient (the CG case study),
  * A the 7-point Laplacian 6 I - (face neighbours) on an n x n x n box with
  * zero Dirichlet data outside the box (no ghost layer is stored).
@@ -427,7 +479,11 @@ enum hc_kernel_kind {
     HC_K_IR_RESIDUAL = 11,    /* r = b - A x, s = (float) r, sums */
     HC_K_IR_UPDATE = 12,      /* x += d                        */
     HC_K_BATCH = 13,          /* a batch step (graph: all steps) */
-    HC_K_COUNT = 14
+    HC_K_VK_INTERIOR = 14,    /* variable coefficient: Interior  */
+    HC_K_VK_BOUNDARY = 15,
+    HC_K_VK_FUSED = 16,
+    HC_K_VK_PLAIN = 17,
+    HC_K_COUNT = 18
 };
 int hc_prof_enable(int every);
 int hc_prof_read(int kind, double *total_ms, long long *launches,

@@ -18,7 +18,7 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "DEFAULT_CG_TILING", "DTYPES", "HC_F64", "HC_F32", "HC_BF16",
            "AUTO_TILING", "tiling_for", "cg_solve_ir", "cg_ir_workspace_bytes",
            "lap7_apply_f32", "set_cg_ir_tiling", "get_cg_ir_tiling", "DEFAULT_CG_IR_TILING",
-           "Batch"]
+           "Batch", "heat_vk_step", "set_vk_tiling", "get_vk_tiling", "vk_tiling_for"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -29,7 +29,7 @@ MODES = {"split": 0, "fused": 1, "plain": 2}
 KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain": 3,
            "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8,
            "cg32_direction": 9, "cg32_update": 10, "ir_residual": 11, "ir_update": 12,
-           "batch": 13}
+           "batch": 13, "vk_interior": 14, "vk_boundary": 15, "vk_fused": 16, "vk_plain": 17}
 
 _lib = None
 
@@ -90,6 +90,10 @@ def load():
         "hc_batch_autotune": (i, [vp, vp, i, vp, dp]),
         "hc_batch_tune_result": (i, [vp, i, ip, dp]),
         "hc_cg_get_tiling": (None, [ip, ip, ip, ip, ip]),
+        "heat_vk_step": (i, [vp, vp, vp, vp, i, i, i, d, i, i, i, i, vp]),
+        "hc_heat_vk_set_tiling": (i, [i, i, i, i, i, i, i]),
+        "hc_heat_vk_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
+        "hc_heat_vk_tiling_for": (i, [i, i, vp, vp, vp, vp, ip, ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -171,6 +175,24 @@ def heat_step_sr(u, u_new, r: float, steps: int, seed: int, step0: int = 0, mode
                             nx, ny, nz, float(r), int(steps), int(seed) & (2 ** 64 - 1),
                             int(step0) & (2 ** 64 - 1), MODES[mode], int(parts),
                             _stream_handle(u, stream)))
+
+
+def heat_vk_step(u, u_new, kappa, rhs, beta: float, steps: int, mode: str = "split",
+                 parts: int = 1, stream=None) -> None:
+    """Advance ``u`` by ``steps`` explicit steps of the variable-coefficient
+    equation with a source: u_new = (u + rhs) + beta * (D_x + D_y + D_z),
+    flux form, rhs = dt f, beta = dt / (2 h^2).  float64 or float32 tensors,
+    all four of one shape; ``kappa`` and ``rhs`` are read only.  Enqueued on
+    ``stream`` (default: torch's current stream); does not synchronize."""
+    import torch
+    _require_cuda_3d(u, u_new, kappa, rhs)
+    if u.dtype not in (torch.float64, torch.float32):
+        raise TypeError("heat_vk_step needs float64 or float32 tensors")
+    nz, ny, nx = u.shape
+    _check(load().heat_vk_step(ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(u_new.data_ptr()),
+                               ctypes.c_void_p(kappa.data_ptr()), ctypes.c_void_p(rhs.data_ptr()),
+                               nx, ny, nz, float(beta), int(steps), _dtype_code(u), MODES[mode],
+                               int(parts), _stream_handle(u, stream)))
 
 
 def cg_workspace_bytes(nx: int, ny: int, nz: int) -> int:
@@ -307,6 +329,35 @@ def tiling_for(u, u_new=None, sr: bool = False) -> dict:
                                      ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(un.data_ptr()),
                                      *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def set_vk_tiling(vec: int | None = None, wx: int | None = None, by: int | None = None,
+                  zdepth: int | None = None, pf: int = 2, xcd: int = 8,
+                  dtype: str = "f64") -> None:
+    """Tile shape of the variable-coefficient kernels ("f64" or "f32");
+    with no shape given, the automatic choice."""
+    if vec is None and wx is None and by is None and zdepth is None:
+        t = AUTO_TILING
+    else:
+        if None in (vec, wx, by, zdepth):
+            raise ValueError("give vec, wx, by and zdepth, or none of them")
+        t = dict(vec=vec, wx=wx, by=by, zdepth=zdepth, pf=pf, xcd=xcd)
+    _check(load().hc_heat_vk_set_tiling(DTYPES[dtype], *(int(t[k]) for k in _TILE_KEYS)))
+
+
+def get_vk_tiling(dtype: str = "f64") -> dict:
+    v = [ctypes.c_int(0) for _ in range(6)]
+    _check(load().hc_heat_vk_get_tiling(DTYPES[dtype], *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def vk_tiling_for(u, u_new, kappa, rhs) -> dict:
+    """The tile shape heat_vk_step would sweep these tensors with."""
+    v = [ctypes.c_int(0) for _ in range(6)]
+    ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (u, u_new, kappa, rhs)]
+    _check(load().hc_heat_vk_tiling_for(_dtype_code(u), int(u.shape[-1]), *ptrs,
+                                        *[ctypes.byref(x) for x in v]))
     return dict(zip(_TILE_KEYS, (x.value for x in v)))
 
 

@@ -102,6 +102,50 @@ hc::HeatTiling heat_tiling_for(int dtype, int nx, const void *u, const void *un)
     return til;
 }
 
+// Tile shape of the variable-coefficient sweep, per precision (FP64, FP32):
+// set by the caller, or all zeros for the automatic choice.  Its candidates
+// are built in a list of their own (two LDS planes and two register queues
+// per tile, so narrower tiles than for the constant coefficient).
+hc::HeatTiling g_vk_tiling[2] = {};
+// The candidates are the fastest shapes of a sweep over the built ones at
+// 512^3 on MI355X (binary32 runs fastest with one-node lanes here).
+const hc::HeatTiling kVkAuto[2][4] = {
+    {{2, 4, 4, 32, 2, 8}, {2, 2, 8, 16, 2, 8}, {2, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}},
+    {{1, 4, 4, 16, 2, 8}, {4, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}, {}},
+};
+
+hc::HeatTiling vk_tiling_for(int dtype, int nx, const void *const *arrays, int narrays) {
+    hc::HeatTiling til;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        til = g_vk_tiling[dtype];
+    }
+    if (til.vec == 0) {
+        long long best = -1;
+        for (const hc::HeatTiling &c : kVkAuto[dtype]) {
+            if (c.vec == 0) break;
+            const long long w = hc::tile_width(c);
+            const long long padded = (nx + w - 1) / w * w;
+            if (best < 0 || padded < best) best = padded;
+        }
+        til = kVkAuto[dtype][0];
+        for (const hc::HeatTiling &c : kVkAuto[dtype]) {
+            if (c.vec == 0) break;
+            const long long w = hc::tile_width(c);
+            if ((nx + w - 1) / w * w * 8 <= best * 9) {
+                til = c;
+                break;
+            }
+        }
+    }
+    const uintptr_t lane_bytes = (uintptr_t)til.vec * (uintptr_t)hc::dtype_bytes(dtype);
+    bool fits = til.vec == 1 || nx % til.vec == 0;
+    for (int q = 0; q < narrays && fits; ++q)
+        fits = reinterpret_cast<uintptr_t>(arrays[q]) % lane_bytes == 0;
+    if (!fits) til = {1, 4, 4, 16, 2, til.xcd};
+    return til;
+}
+
 hc::CGTiling g_cg_tiling = {2, 2, 8, 32, 8};
 
 // Tile shape of the refinement's binary32 inner solve: 256 x 8 tiles of
@@ -319,15 +363,29 @@ double tile_algo_bytes(const hc::ZTable &t, int nx, int ny, int nz, size_t elem)
     return (double)elem * ((double)planes * nx * ny + (double)written * (nx - 2) * (ny - 2));
 }
 
+// The explicit sweep in any of its forms.  With kap == nullptr it is the
+// constant-coefficient step with r; otherwise the variable-coefficient step
+// with source rhs and beta = r (FP64 or FP32).
 int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int steps, int mode,
-             int parts, unsigned long long seed, unsigned long long step0, hipStream_t s) {
+             int parts, unsigned long long seed, unsigned long long step0, hipStream_t s,
+             const void *kap = nullptr, const void *rhs = nullptr) {
     DevState *d = nullptr;
     int rc = device_state(&d);
     if (rc) return rc;
+    const bool vk = kap != nullptr;
     const size_t eb = (size_t)hc::dtype_bytes(dtype);
-    const hc::HeatTiling til = heat_tiling_for(dtype, nx, u, un);
+    const void *arrays[4] = {u, un, kap, rhs};
+    const hc::HeatTiling til = vk ? vk_tiling_for(dtype, nx, arrays, 4)
+                                  : heat_tiling_for(dtype, nx, u, un);
+    // algorithmic bytes: u (and kappa) over every node read, rhs and u_new
+    // over the updated nodes
+    const double fields = vk ? 2.0 : 1.0;
     const double plain_bytes =
-        (double)eb * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
+        (double)eb * fields * ((double)nx * ny * nz + (double)(nx - 2) * (ny - 2) * (nz - 2));
+    const hc::KernelKind k_plain = vk ? hc::K_VK_PLAIN : hc::K_HEAT_PLAIN;
+    const hc::KernelKind k_fused = vk ? hc::K_VK_FUSED : hc::K_HEAT_FUSED;
+    const hc::KernelKind k_int = vk ? hc::K_VK_INTERIOR : hc::K_HEAT_INTERIOR;
+    const hc::KernelKind k_bd = vk ? hc::K_VK_BOUNDARY : hc::K_HEAT_BOUNDARY;
 
     hc::ZTable tin = empty_table(), tbd = empty_table();
     if (mode == HC_HEAT_SPLIT) {
@@ -349,8 +407,13 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     const long long nb_bd = hc::heat_tile_blocks(nx, ny, til, tbd);
     if (nb_in > 2147483647LL || nb_bd > 2147483647LL)
         return fail(HC_EINVAL, "grid too large for this tile shape");
-    const double bytes_in = tile_algo_bytes(tin, nx, ny, nz, eb);
-    const double bytes_bd = tile_algo_bytes(tbd, nx, ny, nz, eb);
+    const double bytes_in = fields * tile_algo_bytes(tin, nx, ny, nz, eb);
+    const double bytes_bd = fields * tile_algo_bytes(tbd, nx, ny, nz, eb);
+    auto tile_launch = [&](hc::KernelKind kind, const hc::ZTable &zt, const void *a, void *b,
+                           unsigned long long step, hipStream_t st) {
+        return vk ? hc::launch_heat_vk_tile(dtype, kind, a, kap, rhs, b, nx, ny, r, zt, til, st)
+                  : hc::launch_heat_tile(dtype, kind, a, b, nx, ny, r, zt, til, seed, step, st);
+    };
 
     HC_TRY(hc::launch_copy_faces((int)eb, u, un, nx, ny, nz, s), "copy_faces launch");
     const bool split = (mode == HC_HEAT_SPLIT) && tbd.n > 0;
@@ -361,30 +424,26 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     void *a = u, *b = un;
     for (int st = 0; st < steps; ++st) {
         if (mode == HC_HEAT_PLAIN) {
-            Timed tm(hc::K_HEAT_PLAIN, s, plain_bytes);
-            HC_TRY(hc::launch_heat_plain(dtype, a, b, nx, ny, nz, r, seed, step0 + st, s), "heat_plain launch");
+            Timed tm(k_plain, s, plain_bytes);
+            HC_TRY(vk ? hc::launch_heat_vk_plain(dtype, a, kap, rhs, b, nx, ny, nz, r, s)
+                      : hc::launch_heat_plain(dtype, a, b, nx, ny, nz, r, seed, step0 + st, s),
+                   "heat_plain launch");
             tm.done();
         } else if (mode == HC_HEAT_FUSED) {
-            Timed tm(hc::K_HEAT_FUSED, s, bytes_in);
-            HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_FUSED, a, b, nx, ny, r, tin, til, seed,
-                                        step0 + st, s),
-                   "heat_fused launch");
+            Timed tm(k_fused, s, bytes_in);
+            HC_TRY(tile_launch(k_fused, tin, a, b, step0 + st, s), "heat_fused launch");
             tm.done();
         } else {
             // the short Boundary kernel goes first, so it is long done when
             // the next step's Interior kernel waits for it
             {
-                Timed tm(hc::K_HEAT_BOUNDARY, d->aux, bytes_bd);
-                HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_BOUNDARY, a, b, nx, ny, r, tbd, til,
-                                            seed, step0 + st, d->aux),
-                       "heat_boundary launch");
+                Timed tm(k_bd, d->aux, bytes_bd);
+                HC_TRY(tile_launch(k_bd, tbd, a, b, step0 + st, d->aux), "heat_boundary launch");
                 tm.done();
             }
             if (tin.n > 0) {
-                Timed tm(hc::K_HEAT_INTERIOR, s, bytes_in);
-                HC_TRY(hc::launch_heat_tile(dtype, hc::K_HEAT_INTERIOR, a, b, nx, ny, r, tin, til, seed,
-                                            step0 + st, s),
-                       "heat_interior launch");
+                Timed tm(k_int, s, bytes_in);
+                HC_TRY(tile_launch(k_int, tin, a, b, step0 + st, s), "heat_interior launch");
                 tm.done();
             }
             // join: the next step needs both halves of this one, in both streams
@@ -892,6 +951,31 @@ int heat_step_sr(void *u, void *u_new, int nx, int ny, int nz, double r, int ste
                     reinterpret_cast<hipStream_t>(stream));
 }
 
+int heat_vk_step(void *u, void *u_new, const void *kappa, const void *rhs, int nx, int ny,
+                 int nz, double beta, int steps, int dtype, int mode, int parts,
+                 hc_stream_t stream) {
+    g_msg.clear();
+    if (!kappa || !rhs) return fail(HC_EINVAL, "kappa and rhs must be non-NULL");
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d: the variable-coefficient step takes HC_F64 or HC_F32",
+                    dtype);
+    if (!std::isfinite(beta) || beta < 0.0)
+        return fail(HC_EUNSTABLE, "beta = %g must be finite and >= 0", beta);
+    size_t bytes = 0;
+    int rc = validate_heat(u, u_new, nx, ny, nz, 0.0, steps, dtype, mode, parts, &bytes);
+    if (rc) return rc;
+    if (overlaps(kappa, bytes, u, bytes) || overlaps(kappa, bytes, u_new, bytes) ||
+        overlaps(rhs, bytes, u, bytes) || overlaps(rhs, bytes, u_new, bytes))
+        return fail(HC_EALIAS, "kappa and rhs must not overlap u or u_new");
+    if (steps == 0) return HC_OK;
+    if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
+    if ((rc = check_device_buffer(u_new, bytes, "u_new"))) return rc;
+    if ((rc = check_device_buffer(kappa, bytes, "kappa"))) return rc;
+    if ((rc = check_device_buffer(rhs, bytes, "rhs"))) return rc;
+    return heat_run(dtype, u, u_new, nx, ny, nz, beta, steps, mode, parts, 0, 0,
+                    reinterpret_cast<hipStream_t>(stream), kappa, rhs);
+}
+
 int heat_step(double *u, double *u_new, int nx, int ny, int nz, double r, int steps) {
     int rc = heat_step_ex(u, u_new, nx, ny, nz, r, steps, HC_F64, HC_HEAT_SPLIT, 1, nullptr);
     if (rc != HC_OK || steps == 0) return rc;
@@ -1116,6 +1200,63 @@ int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new, int 
         return fail(HC_EINVAL, "dtype %d is not supported", dtype);
     if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
     const hc::HeatTiling t = heat_tiling_for(dtype, nx, u, u_new);
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
+    return HC_OK;
+}
+
+int hc_heat_vk_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int pf, int xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    const hc::HeatTiling t = {vec, wx, by, zdepth, pf, xcd};
+    if (vec == 0 && wx == 0 && by == 0 && zdepth == 0 && pf == 0 && xcd == 0) {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        g_vk_tiling[dtype] = t;
+        return HC_OK;
+    }
+    if (!hc::heat_vk_tiling_supported(dtype, t))
+        return fail(HC_EINVAL,
+                    "variable-coefficient tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is "
+                    "not built for dtype %d",
+                    vec, wx, by, zdepth, pf, dtype);
+    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_vk_tiling[dtype] = t;
+    return HC_OK;
+}
+
+int hc_heat_vk_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth, int *pf, int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    hc::HeatTiling t;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        t = g_vk_tiling[dtype];
+    }
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
+    return HC_OK;
+}
+
+int hc_heat_vk_tiling_for(int dtype, int nx, const void *u, const void *u_new, const void *kappa,
+                          const void *rhs, int *vec, int *wx, int *by, int *zdepth, int *pf,
+                          int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
+    const void *arrays[4] = {u, u_new, kappa, rhs};
+    const hc::HeatTiling t = vk_tiling_for(dtype, nx, arrays, 4);
     if (vec) *vec = t.vec;
     if (wx) *wx = t.wx;
     if (by) *by = t.by;

@@ -53,7 +53,11 @@ enum KernelKind {
     K_IR_RESIDUAL = 11,
     K_IR_UPDATE = 12,
     K_BATCH = 13,
-    K_COUNT = 14
+    K_VK_INTERIOR = 14,
+    K_VK_BOUNDARY = 15,
+    K_VK_FUSED = 16,
+    K_VK_PLAIN = 17,
+    K_COUNT = 18
 };
 
 // ---- heat (heat_kernels.hip) ------------------------------------------------
@@ -77,6 +81,16 @@ hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny,
                              hipStream_t s);
 hipError_t launch_copy_faces(int elem_bytes, const void *u, void *un, int nx, int ny, int nz,
                              hipStream_t s);
+
+// ---- variable coefficient and source (varcoef_kernels.hip) ----------------------
+// u, kap, rhs and un hold FP64 (dtype 0) or FP32 (dtype 1) nodes; the tile
+// shapes are those of HeatTiling, from a list of their own.
+bool heat_vk_tiling_supported(int dtype, const HeatTiling &t);
+hipError_t launch_heat_vk_tile(int dtype, KernelKind kind, const void *u, const void *kap,
+                               const void *rhs, void *un, int nx, int ny, double beta,
+                               const ZTable &zt, const HeatTiling &t, hipStream_t s);
+hipError_t launch_heat_vk_plain(int dtype, const void *u, const void *kap, const void *rhs,
+                                void *un, int nx, int ny, int nz, double beta, hipStream_t s);
 
 // ---- batched heat (batch_kernels.hip) ------------------------------------------
 // One problem of a batch: its array starts `offset` elements into the packed

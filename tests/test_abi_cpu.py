@@ -234,3 +234,61 @@ def test_batch_validation_happens_before_device_work(lib):
     assert lib.hc_batch_step(None, FAKE_U, FAKE_V, 1, 0, None) == HC_EINVAL
     assert lib.hc_batch_layout(None, None, None, None, None) == HC_EINVAL
     lib.hc_batch_destroy(None)                                                   # no-op
+
+
+FAKE_K = ctypes.c_void_p(0x10000 + 16 * 10 ** 6)
+FAKE_R = ctypes.c_void_p(0x10000 + 24 * 10 ** 6)
+
+
+def test_heat_vk_step_validation_happens_before_device_work(lib):
+    f = lib.heat_vk_step
+    u, v, k, r = FAKE_U, FAKE_V, FAKE_K, FAKE_R
+    ok = (10, 10, 10, 0.04, 1, 0, 0, 1, None)
+    assert f(u, v, None, r, *ok) == HC_EINVAL
+    assert f(u, v, k, None, *ok) == HC_EINVAL
+    assert f(None, v, k, r, *ok) == HC_EINVAL
+    assert f(u, v, k, r, 10, 10, 10, 0.04, 1, 2, 0, 1, None) == HC_EINVAL       # bfloat16
+    assert f(u, v, k, r, 10, 10, 10, 0.04, 1, 3, 0, 1, None) == HC_EINVAL       # bfloat16 SR
+    assert f(u, v, k, r, 10, 10, 10, -0.01, 1, 0, 0, 1, None) == HC_EUNSTABLE
+    assert f(u, v, k, r, 10, 10, 10, float("nan"), 1, 0, 0, 1, None) == HC_EUNSTABLE
+    assert f(u, v, k, r, 10, 10, 10, float("inf"), 1, 0, 0, 1, None) == HC_EUNSTABLE
+    assert f(u, v, k, r, 2, 10, 10, 0.04, 1, 0, 0, 1, None) == HC_EINVAL        # edge < 3
+    assert f(u, v, k, r, 10, 10, 10, 0.04, -1, 0, 0, 1, None) == HC_EINVAL      # steps
+    assert f(u, v, k, r, 10, 10, 10, 0.04, 1, 0, 9, 1, None) == HC_EINVAL       # mode
+    assert f(u, v, k, r, 10, 10, 10, 0.04, 1, 0, 1, 2, None) == HC_EINVAL       # parts w/o split
+    assert f(u, u, k, r, *ok) == HC_EALIAS
+    assert f(u, v, u, r, *ok) == HC_EALIAS                                       # kappa = u
+    assert f(u, v, k, v, *ok) == HC_EALIAS                                       # rhs = u_new
+    assert f(u, v, ctypes.c_void_p(0x10000 + 8 * 999), r, *ok) == HC_EALIAS      # kappa overlaps u
+    assert f(u, v, k, k, 10, 10, 10, 0.04, 0, 0, 0, 1, None) == HC_OK            # steps 0; kappa = rhs
+    assert f(u, v, k, r, 10, 10, 10, 0.04, 0, 1, 2, 1, None) == HC_OK            # f32, plain
+    assert lib.hc_last_error_message().decode() == ""
+
+
+def test_vk_tiling_settings_and_automatic_choice(lib):
+    assert lib.hc_heat_vk_set_tiling(2, 1, 4, 4, 16, 2, 8) == HC_EINVAL     # bfloat16
+    assert lib.hc_heat_vk_set_tiling(0, 8, 1, 8, 16, 2, 8) == HC_EINVAL     # not built
+    assert lib.hc_heat_vk_set_tiling(0, 2, 2, 8, 16, 2, 65) == HC_EINVAL    # xcd
+    assert lib.hc_heat_vk_set_tiling(0, 2, 1, 8, 16, 2, 3) == HC_OK
+    assert hc.get_vk_tiling("f64") == dict(vec=2, wx=1, by=8, zdepth=16, pf=2, xcd=3)
+    assert hc.get_vk_tiling("f32") == hc.AUTO_TILING
+    hc.set_vk_tiling(dtype="f64")
+    assert hc.get_vk_tiling("f64") == hc.AUTO_TILING
+
+    def tiling_for(dtype, nx, ptrs):
+        v = [ctypes.c_int(0) for _ in range(6)]
+        assert lib.hc_heat_vk_tiling_for(dtype, nx, *ptrs, *[ctypes.byref(x) for x in v]) == HC_OK
+        return tuple(x.value for x in v)
+
+    aligned = [ctypes.c_void_p(0x100000 * (q + 1)) for q in range(4)]
+    t = tiling_for(0, 512, aligned)
+    assert t[0] == 2 and lib.hc_heat_vk_set_tiling(0, *t) == HC_OK      # a built shape
+    hc.set_vk_tiling(dtype="f64")
+    t = tiling_for(1, 512, aligned)
+    assert t[0] == 1 and lib.hc_heat_vk_set_tiling(1, *t) == HC_OK      # one-node lanes
+    hc.set_vk_tiling(dtype="f32")
+    assert tiling_for(0, 513, aligned)[0] == 1                 # odd rows: one-node lanes
+    odd = list(aligned)
+    odd[3] = ctypes.c_void_p(0x100000 * 4 + 8)                 # rhs not 16-byte aligned
+    assert tiling_for(0, 512, odd)[0] == 1
+    assert lib.hc_heat_vk_tiling_for(2, 512, *aligned, *([None] * 6)) == HC_EINVAL
