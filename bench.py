@@ -4,7 +4,9 @@
 One step = one full pass of the hot path over the benchmark inputs:
   * heat: the 512^3 FP64 field (U[0,1] + central Gaussian hot spot, zero
     Dirichlet data), r = 1/6.5, 1000 explicit 7-point steps, Interior
-    kernel on the caller's stream and Boundary planes on a second stream;
+    kernel on the caller's stream and Boundary planes on a second stream,
+    two steps per pass over memory (the library's default; bit-identical to
+    single steps);
   * CG: the 7-point Laplacian on 256^3 unknowns, b = A x* for a seeded
     x* ~ U[-1,1], x0 = 0, relative residual 1e-10, FP64.
 Inputs are resident in HBM before the timed region; each step restarts both
@@ -33,31 +35,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GLUP/s + achieved HBM GB/s (7-pt heat 512³ FP64 vs FP32); CG time-to-1e-10"
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat_interior_f64_512_traffic.json")
-# the sources the Interior kernel is compiled from
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2608_11882_amd", "csrc", f)
-                  for f in ("heat_kernels.hip", "heat_tile.hpp")]
+# The Interior kernel of each pass form: its committed rocprofv3 HBM-traffic
+# record and the sources it is compiled from.
+CSRC = os.path.join(ROOT, "paper_2608_11882_amd", "csrc")
+INTERIOR = {
+    1: ("heat_interior", os.path.join(ROOT, "profiles", "heat_interior_f64_512_traffic.json"),
+        ("heat_kernels.hip", "heat_tile.hpp")),
+    2: ("heat2_interior", os.path.join(ROOT, "profiles", "heat2_interior_f64_512_traffic.json"),
+        ("heat2_kernels.hip", "heat_tile2.hpp", "heat_tile.hpp")),
+}
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(files):
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
-            h.update(f.read())
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(launch_bytes):
-    """Per-launch HBM bytes from the committed rocprofv3 counter summary,
-    or None when the counters were taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(time_block):
+    """Per-launch HBM bytes of the Interior kernel from the committed
+    rocprofv3 counter summary, or None when the counters were taken on a
+    different kernel source."""
+    _, path, files = INTERIOR[time_block]
+    if not os.path.exists(path):
         return None
-    rec = json.load(open(TRAFFIC_FILE))
-    if rec.get("kernel_source_sha256") != kernel_source_hash():
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_hash(files):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -179,10 +188,11 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
         timed_sweep(hc, u, un, u0, r_large, 10, sr)
         ms = timed_sweep(hc, u, un, u0, r_large, nsteps_large, sr)
         eb = u0.element_size()
-        rate[name] = {"tiling": hc.tiling_for(u, un, sr),
+        til = pass_tiling(hc, u, un, sr)
+        rate[name] = {"tiling": til,
                       "glups": round(lups / (ms / 1e3) / 1e9, 2),
-                      "algo_hbm_gbs": round(nsteps_large * eb * (n ** 3 + (n - 2) ** 3)
-                                            / (ms / 1e3) / 1e9, 1)}
+                      "algo_hbm_gbs": round(n_passes(nsteps_large, til) * eb
+                                            * (n ** 3 + (n - 2) ** 3) / (ms / 1e3) / 1e9, 1)}
         del u, un, u0
     out["heat_512_rates"] = rate
     log("precision: 512^3 rates %s" % rate)
@@ -206,9 +216,11 @@ def precision_section(hc, dev, u_init64, r_large, nsteps_large, with_oracle):
         timed_sweep(hc, u, un, u0, r, 5, sr)
         ms = timed_sweep(hc, u, un, u0, r, steps, sr)
         eb = u0.element_size()
-        rec = {"tiling": hc.tiling_for(u, un, sr),
+        til = pass_tiling(hc, u, un, sr)
+        rec = {"tiling": til,
                "glups": round(lups / (ms / 1e3) / 1e9, 2),
-               "algo_hbm_gbs": round(steps * eb * (N ** 3 + (N - 2) ** 3) / (ms / 1e3) / 1e9, 1),
+               "algo_hbm_gbs": round(n_passes(steps, til) * eb * (N ** 3 + (N - 2) ** 3)
+                                     / (ms / 1e3) / 1e9, 1),
                "ms": round(ms, 2)}
         del un, u0
         if name == "f64":
@@ -362,6 +374,19 @@ def batch_section(hc, dev):
 PAPER_KBAR_S = 6.4042e-11   # s per interior point and step, FP64 var-kappa, H100, 1 GPU
 
 
+def n_passes(steps, tiling):
+    """Passes over memory a run of `steps` makes (a last odd step is one)."""
+    k = tiling["steps_per_pass"]
+    return steps // k + steps % k
+
+
+def pass_tiling(hc, u, un, sr=False):
+    """The tile shape (and steps per pass) a sweep of these tensors runs with."""
+    if hc.get_time_block() == 2 and not sr:
+        return dict(hc.tiling2_for(u, un), steps_per_pass=2)
+    return dict(hc.tiling_for(u, un, sr), steps_per_pass=1)
+
+
 def vk_section(hc, dev):
     """The paper's own equation (variable kappa, source term; Eq. 1-4) on its
     test case (Eq. 2, 3, 5) at 512^3, outside the timed region: 500 steps
@@ -501,8 +526,10 @@ def main():
         log("step %d/%d enqueued" % (k + 1, args.steps))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    int_ms, int_n, int_bytes = hc.prof_read("heat_interior")
-    bnd_ms, bnd_n, _ = hc.prof_read("heat_boundary")
+    tb = hc.get_time_block()
+    kname = INTERIOR[tb][0]
+    int_ms, int_n, int_bytes = hc.prof_read(kname)
+    bnd_ms, bnd_n, _ = hc.prof_read(kname.replace("interior", "boundary"))
     cga_ms, cga_n, cga_b = hc.prof_read("cg_direction")
     cgb_ms, cgb_n, cgb_b = hc.prof_read("cg_update")
     hc.prof_enable(False)
@@ -515,15 +542,20 @@ def main():
     lups = nsteps * (n - 2) ** 3
     heat_s_total = sum(heat_ms) / 1e3
     glups = args.steps * lups / heat_s_total / 1e9
+    # the bytes a pass must move: every stored node read once, every updated
+    # node written once; with two steps per pass a run of nsteps makes
+    # nsteps // 2 + nsteps % 2 passes
     algo_step = 8.0 * (n ** 3 + (n - 2) ** 3)
-    heat_gbs = args.steps * nsteps * algo_step / heat_s_total / 1e9
+    passes = nsteps // tb + nsteps % tb
+    heat_gbs = args.steps * passes * algo_step / heat_s_total / 1e9
+    single_step_gbs = args.steps * nsteps * algo_step / heat_s_total / 1e9
     ok_heat = bool(torch.isfinite(u).all().item()) and float(u.min()) >= 0.0
 
     # dominant kernel: the Interior sweep
     launch_bytes = int_bytes / max(int_n, 1)
     launch_ms = int_ms / max(int_n, 1)
     achieved = launch_bytes / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic(launch_bytes)
+    traffic = measured_traffic(tb)
 
     # copy-probe ceiling and the other kernel forms (outside the timed region)
     log("copy probe and kernel-form comparison")
@@ -536,16 +568,23 @@ def main():
         torch.cuda.synchronize()
         probe.append(2 * u_init.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9)
     copy_gbs = statistics.median(probe)
+    # every form at one and at two steps per pass (plain: always one)
     variants = {}
-    for mode in ("split", "fused", "plain"):
-        u.copy_(u_init)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        hc.heat_step(u, un, r, 100, mode=mode)
-        e1.record()
-        torch.cuda.synchronize()
-        variants[mode] = round(100 * (n - 2) ** 3 / (e0.elapsed_time(e1) / 1e3) / 1e9, 2)
+    for passes in (tb, 3 - tb):
+        hc.set_time_block(passes)
+        for mode in ("split", "fused", "plain"):
+            if mode == "plain" and passes == 2:
+                continue
+            u.copy_(u_init)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            hc.heat_step(u, un, r, 100, mode=mode)
+            e1.record()
+            torch.cuda.synchronize()
+            key = mode if mode == "plain" else "%s_%d_step%s" % (mode, passes, "s" if passes > 1 else "")
+            variants[key] = round(100 * (n - 2) ** 3 / (e0.elapsed_time(e1) / 1e3) / 1e9, 2)
+    hc.set_time_block(tb)
 
     prec = varcoef = None
     if args.precision:
@@ -563,7 +602,7 @@ def main():
         b_host = b.cpu().numpy()
         cpu = cpu_baseline(u0_host, r, b_host, cg_iters, args.cpu_seconds)
 
-    tiling = hc.tiling_for(u, un)
+    tiling = hc.tiling_for(u, un) if tb == 1 else hc.tiling2_for(u, un)
     out = {
         "metric": METRIC,
         "value": round(glups, 3),
@@ -580,15 +619,18 @@ def main():
         "config": {
             "workload": "heat 7-point FP64 512^3 r=1/6.5 x1000 steps (Interior/Boundary split) "
                         "+ CG 7-point Laplacian FP64 256^3 to relres 1e-10",
+            "steps_per_pass": tb,
             "heat_grid": [n, n, n], "heat_steps": nsteps, "heat_r": r,
             "cg_grid": [m, m, m], "cg_tol": tol, "parallelism": "single-gpu",
             "tiling": tiling,
         },
         "heat": {
             "glups": round(glups, 3),
+            "steps_per_pass": tb,
             "algo_hbm_gbs": round(heat_gbs, 1),
             "pct_of_hbm_peak": round(100 * heat_gbs / PEAK_HBM_GBS, 2),
             "pct_of_copy_probe": round(100 * heat_gbs / copy_gbs, 2),
+            "single_step_equivalent_gbs": round(single_step_gbs, 1),
             "ms_per_time_step": round(sum(heat_ms) / len(heat_ms) / nsteps, 5),
             "run_ms": [round(t, 3) for t in heat_ms],
             "variability": round((max(heat_ms) - min(heat_ms)) / statistics.median(heat_ms), 4),
@@ -611,7 +653,8 @@ def main():
         "varcoef_512": varcoef,
         "copy_probe_gbs": round(copy_gbs, 1),
         "roofline": {
-            "kernel": "heat_interior_f64",
+            "kernel": kname + "_f64",
+            "steps_per_launch": tb,
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBS,
@@ -622,6 +665,9 @@ def main():
             "avg_launch_us": round(launch_ms * 1e3, 3),
             "timed_launches": int_n,
             "launch_sampling": "every 16th launch of each kernel, HIP events on its stream",
+            "algo_bytes_rule": "every stored node of the planes the launch reads (its output "
+                               "planes and %d on each side) once, every node it writes once"
+                               % tb,
         },
         "cpu_baseline": cpu,
     }

@@ -70,9 +70,12 @@ enum hc_heat_mode {
  *          return.  Its outermost layer holds the Dirichlet data and is
  *          never written (the paper uses zero data, Eq. 5).
  *  u_new   [scratch] nx*ny*nz FP64, device, must not overlap u.  On entry
- *          its outermost layer is overwritten with u's.  On return it holds
- *          u^(steps-1) when steps is even and >= 2, and u^steps when steps
- *          is odd (the last sweep lands in u_new and is copied to u).
+ *          its outermost layer is overwritten with u's, and it keeps u's
+ *          outermost layer on return.  With one step per pass
+ *          (hc_heat_set_time_block(1)) it holds u^(steps-1) when steps is
+ *          even and >= 2 and u^steps when steps is odd; with two steps per
+ *          pass (the default) its interior holds the state before the last
+ *          pass or u^steps, and should be taken as unspecified.
  *  nx,ny,nz  stored edge lengths including the Dirichlet layer, each >= 3;
  *          (nx-2)(ny-2)(nz-2) nodes are updated.
  *  r       finite, 0 <= r <= 1/6 (stability and the discrete maximum
@@ -137,6 +140,37 @@ int heat_step_ex(void *u, void *u_new, int nx, int ny, int nz, double r,
 int heat_step_sr(void *u, void *u_new, int nx, int ny, int nz, double r,
                  int steps, unsigned long long seed, unsigned long long step0,
                  int mode, int parts, hc_stream_t stream);
+
+/*
+ * Steps per pass of the constant-coefficient z-marching sweeps (process
+ * wide): 1, or 2 (temporal blocking: a pass reads u^t once and writes
+ * u^(t+2); u^(t+1) is computed on each tile and its one-node ring in
+ * registers and LDS and never stored).  Results do not depend on it: every
+ * value of u^(t+1) is evaluated with the same expression and rounding as a
+ * single step.  It applies to HC_F64, HC_F32 and HC_BF16 in HC_HEAT_SPLIT
+ * and HC_HEAT_FUSED (a last odd step takes a single pass); heat_step_sr,
+ * HC_HEAT_PLAIN and heat_vk_step always take single steps.  In the split
+ * form with two steps per pass, the Boundary kernel owns the first and last
+ * two planes of each slab (the depth of halo two steps need), the Interior
+ * kernel the rest.  Default: 2.  HC_EINVAL for other values.
+ */
+int hc_heat_set_time_block(int steps_per_pass);
+int hc_heat_get_time_block(void);
+
+/*
+ * Tile shape of the two-step sweep, per dtype (HC_F64, HC_F32, HC_BF16),
+ * same fields and rules as hc_heat_set_tiling (all zeros: automatic); the
+ * shapes built are listed in heat2_kernels.hip (HC_HEAT2_SHAPES_*).
+ * hc_heat2_tiling_for reports the shape a two-step sweep of these arrays
+ * would run with.
+ */
+int hc_heat2_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int pf,
+                        int xcd);
+int hc_heat2_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth,
+                        int *pf, int *xcd);
+int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new,
+                        int *vec, int *wx, int *by, int *zdepth, int *pf,
+                        int *xcd);
 
 /*
  * heat_vk_step -- the paper's own equation: `steps` explicit steps of
@@ -483,7 +517,10 @@ enum hc_kernel_kind {
     HC_K_VK_BOUNDARY = 15,
     HC_K_VK_FUSED = 16,
     HC_K_VK_PLAIN = 17,
-    HC_K_COUNT = 18
+    HC_K_HEAT2_INTERIOR = 18, /* two steps per pass            */
+    HC_K_HEAT2_BOUNDARY = 19,
+    HC_K_HEAT2_FUSED = 20,
+    HC_K_COUNT = 21
 };
 int hc_prof_enable(int every);
 int hc_prof_read(int kind, double *total_ms, long long *launches,

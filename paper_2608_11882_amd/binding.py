@@ -18,7 +18,8 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "DEFAULT_CG_TILING", "DTYPES", "HC_F64", "HC_F32", "HC_BF16",
            "AUTO_TILING", "tiling_for", "cg_solve_ir", "cg_ir_workspace_bytes",
            "lap7_apply_f32", "set_cg_ir_tiling", "get_cg_ir_tiling", "DEFAULT_CG_IR_TILING",
-           "Batch", "heat_vk_step", "set_vk_tiling", "get_vk_tiling", "vk_tiling_for"]
+           "Batch", "heat_vk_step", "set_vk_tiling", "get_vk_tiling", "vk_tiling_for",
+           "set_time_block", "get_time_block", "set_tiling2", "get_tiling2", "tiling2_for"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -29,7 +30,8 @@ MODES = {"split": 0, "fused": 1, "plain": 2}
 KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain": 3,
            "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8,
            "cg32_direction": 9, "cg32_update": 10, "ir_residual": 11, "ir_update": 12,
-           "batch": 13, "vk_interior": 14, "vk_boundary": 15, "vk_fused": 16, "vk_plain": 17}
+           "batch": 13, "vk_interior": 14, "vk_boundary": 15, "vk_fused": 16, "vk_plain": 17,
+           "heat2_interior": 18, "heat2_boundary": 19, "heat2_fused": 20}
 
 _lib = None
 
@@ -94,6 +96,11 @@ def load():
         "hc_heat_vk_set_tiling": (i, [i, i, i, i, i, i, i]),
         "hc_heat_vk_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
         "hc_heat_vk_tiling_for": (i, [i, i, vp, vp, vp, vp, ip, ip, ip, ip, ip, ip]),
+        "hc_heat_set_time_block": (i, [i]),
+        "hc_heat_get_time_block": (i, []),
+        "hc_heat2_set_tiling": (i, [i, i, i, i, i, i, i]),
+        "hc_heat2_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
+        "hc_heat2_tiling_for": (i, [i, i, vp, vp, ip, ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -329,6 +336,47 @@ def tiling_for(u, u_new=None, sr: bool = False) -> dict:
                                      ctypes.c_void_p(u.data_ptr()),
                                      ctypes.c_void_p(un.data_ptr()),
                                      *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def set_time_block(steps_per_pass: int) -> None:
+    """Steps per pass of the constant-coefficient z-marching sweeps (1 or
+    2); results do not depend on it."""
+    _check(load().hc_heat_set_time_block(int(steps_per_pass)))
+
+
+def get_time_block() -> int:
+    return int(load().hc_heat_get_time_block())
+
+
+def set_tiling2(vec: int | None = None, wx: int | None = None, by: int | None = None,
+                zdepth: int | None = None, pf: int = 2, xcd: int = 8,
+                dtype: str = "f64") -> None:
+    """Tile shape of the two-step sweep for one element type; with no shape
+    given, the automatic choice."""
+    if vec is None and wx is None and by is None and zdepth is None:
+        t = AUTO_TILING
+    else:
+        if None in (vec, wx, by, zdepth):
+            raise ValueError("give vec, wx, by and zdepth, or none of them")
+        t = dict(vec=vec, wx=wx, by=by, zdepth=zdepth, pf=pf, xcd=xcd)
+    _check(load().hc_heat2_set_tiling(DTYPES[dtype], *(int(t[k]) for k in _TILE_KEYS)))
+
+
+def get_tiling2(dtype: str = "f64") -> dict:
+    v = [ctypes.c_int(0) for _ in range(6)]
+    _check(load().hc_heat2_get_tiling(DTYPES[dtype], *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def tiling2_for(u, u_new=None) -> dict:
+    """The tile shape a two-step sweep of these tensors would run with."""
+    v = [ctypes.c_int(0) for _ in range(6)]
+    un = u if u_new is None else u_new
+    _check(load().hc_heat2_tiling_for(_dtype_code(u), int(u.shape[-1]),
+                                      ctypes.c_void_p(u.data_ptr()),
+                                      ctypes.c_void_p(un.data_ptr()),
+                                      *[ctypes.byref(x) for x in v]))
     return dict(zip(_TILE_KEYS, (x.value for x in v)))
 
 

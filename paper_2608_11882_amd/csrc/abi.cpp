@@ -146,6 +146,55 @@ hc::HeatTiling vk_tiling_for(int dtype, int nx, const void *const *arrays, int n
     return til;
 }
 
+// Steps per pass of the z-marching constant-coefficient sweeps (1 or 2;
+// two by default: a pass then moves half the bytes per step).  The
+// two-step sweep has tile shapes of its own, per storage precision; the
+// automatic candidates are the fastest of a sweep over the built ones at
+// 512^3 on MI355X (tiles 256 nodes wide, 4-8 rows, z-blocks of 32 planes).
+int g_time_block = 2;
+hc::HeatTiling g_tiling2[3] = {};
+const hc::HeatTiling kAuto2[3][4] = {
+    {{2, 2, 4, 32, 2, 8}, {2, 1, 8, 32, 2, 8}, {1, 4, 4, 16, 2, 8}, {}},
+    {{4, 1, 8, 32, 2, 8}, {4, 1, 4, 32, 2, 8}, {1, 4, 4, 16, 2, 8}, {}},
+    {{4, 1, 4, 32, 2, 8}, {4, 1, 8, 32, 2, 8}, {1, 4, 4, 16, 2, 8}, {}},
+};
+
+hc::HeatTiling heat2_tiling_for(int dtype, int nx, const void *u, const void *un) {
+    hc::HeatTiling til;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        til = g_tiling2[dtype];
+    }
+    if (til.vec == 0) {
+        long long best = -1;
+        for (const hc::HeatTiling &c : kAuto2[dtype]) {
+            if (c.vec == 0) break;
+            const long long w = hc::tile_width(c);
+            const long long padded = (nx + w - 1) / w * w;
+            if (best < 0 || padded < best) best = padded;
+        }
+        til = kAuto2[dtype][0];
+        for (const hc::HeatTiling &c : kAuto2[dtype]) {
+            if (c.vec == 0) break;
+            const long long w = hc::tile_width(c);
+            if ((nx + w - 1) / w * w * 8 <= best * 9) {
+                til = c;
+                break;
+            }
+        }
+    }
+    const uintptr_t lane_bytes = (uintptr_t)til.vec * (uintptr_t)hc::dtype_bytes(dtype);
+    if (til.vec > 1 && ((nx % til.vec) || (reinterpret_cast<uintptr_t>(u) % lane_bytes) ||
+                        (reinterpret_cast<uintptr_t>(un) % lane_bytes)))
+        til = {1, 4, 4, 16, 2, til.xcd};
+    return til;
+}
+
+int current_time_block() {
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    return g_time_block;
+}
+
 hc::CGTiling g_cg_tiling = {2, 2, 8, 32, 8};
 
 // Tile shape of the refinement's binary32 inner solve: 256 x 8 tiles of
@@ -351,11 +400,12 @@ void slab(int nz, int parts, int s, int *a, int *b) {
 // Bytes a z-marching launch over `t` must move: every stored node of the
 // planes it reads (kb-1 .. ke+1 of each range, counted once) plus every
 // node it writes.
-double tile_algo_bytes(const hc::ZTable &t, int nx, int ny, int nz, size_t elem) {
+double tile_algo_bytes(const hc::ZTable &t, int nx, int ny, int nz, size_t elem, int halo = 1) {
     std::vector<char> rd(nz, 0);
     long long written = 0;
     for (int q = 0; q < t.n; ++q) {
-        for (int k = t.kb[q] - 1; k <= t.ke[q] + 1; ++k) rd[k] = 1;
+        for (int k = std::max(0, t.kb[q] - halo); k <= std::min(nz - 1, t.ke[q] + halo); ++k)
+            rd[k] = 1;
         written += t.ke[q] - t.kb[q] + 1;
     }
     long long planes = 0;
@@ -415,14 +465,81 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                   : hc::launch_heat_tile(dtype, kind, a, b, nx, ny, r, zt, til, seed, step, st);
     };
 
+    // two steps per pass where the sweep allows it (constant coefficient,
+    // nearest rounding, z-marching forms); a last odd step takes one pass
+    const bool two = !vk && dtype != hc::kDtypeBF16SR && mode != HC_HEAT_PLAIN &&
+                     steps >= 2 && current_time_block() == 2;
+    hc::HeatTiling til2 = {};
+    hc::ZTable tin2 = empty_table(), tbd2 = empty_table();
+    double bytes_in2 = 0.0, bytes_bd2 = 0.0;
+    if (two) {
+        til2 = heat2_tiling_for(dtype, nx, u, un);
+        if (mode == HC_HEAT_SPLIT) {
+            // the first and last two planes of a slab are its Boundary planes
+            for (int q = 0; q < parts; ++q) {
+                int a, b;
+                slab(nz, parts, q, &a, &b);
+                if (b - a + 1 >= 5) push_range(tin2, a + 2, b - 2, til2.zdepth);
+            }
+            for (int q = 0; q < parts; ++q) {
+                int a, b;
+                slab(nz, parts, q, &a, &b);
+                if (b - a + 1 >= 5) {
+                    push_range(tbd2, a, a + 1, 2);
+                    push_range(tbd2, b - 1, b, 2);
+                } else {
+                    push_range(tbd2, a, b, b - a + 1);
+                }
+            }
+        } else {
+            push_range(tin2, 1, nz - 2, til2.zdepth);
+        }
+        if (hc::heat_tile_blocks(nx, ny, til2, tin2) > 2147483647LL ||
+            hc::heat_tile_blocks(nx, ny, til2, tbd2) > 2147483647LL)
+            return fail(HC_EINVAL, "grid too large for this tile shape");
+        bytes_in2 = tile_algo_bytes(tin2, nx, ny, nz, eb, 2);
+        bytes_bd2 = tile_algo_bytes(tbd2, nx, ny, nz, eb, 2);
+    }
+
     HC_TRY(hc::launch_copy_faces((int)eb, u, un, nx, ny, nz, s), "copy_faces launch");
-    const bool split = (mode == HC_HEAT_SPLIT) && tbd.n > 0;
+    const bool split = (mode == HC_HEAT_SPLIT) && (tbd.n > 0 || tbd2.n > 0);
     if (split) {
         HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
         HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
     }
     void *a = u, *b = un;
-    for (int st = 0; st < steps; ++st) {
+    for (int st = 0; st < steps;) {
+        if (two && steps - st >= 2) {
+            if (mode == HC_HEAT_FUSED) {
+                Timed tm(hc::K_HEAT2_FUSED, s, bytes_in2);
+                HC_TRY(hc::launch_heat2_tile(dtype, hc::K_HEAT2_FUSED, a, b, nx, ny, nz, r, tin2,
+                                             til2, s),
+                       "heat2_fused launch");
+                tm.done();
+            } else {
+                {
+                    Timed tm(hc::K_HEAT2_BOUNDARY, d->aux, bytes_bd2);
+                    HC_TRY(hc::launch_heat2_tile(dtype, hc::K_HEAT2_BOUNDARY, a, b, nx, ny, nz,
+                                                 r, tbd2, til2, d->aux),
+                           "heat2_boundary launch");
+                    tm.done();
+                }
+                if (tin2.n > 0) {
+                    Timed tm(hc::K_HEAT2_INTERIOR, s, bytes_in2);
+                    HC_TRY(hc::launch_heat2_tile(dtype, hc::K_HEAT2_INTERIOR, a, b, nx, ny, nz,
+                                                 r, tin2, til2, s),
+                           "heat2_interior launch");
+                    tm.done();
+                }
+                HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
+                HC_TRY(hipEventRecord(d->ev_aux, d->aux), "hipEventRecord");
+                HC_TRY(hipStreamWaitEvent(s, d->ev_aux, 0), "hipStreamWaitEvent");
+                HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
+            }
+            std::swap(a, b);
+            st += 2;
+            continue;
+        }
         if (mode == HC_HEAT_PLAIN) {
             Timed tm(k_plain, s, plain_bytes);
             HC_TRY(vk ? hc::launch_heat_vk_plain(dtype, a, kap, rhs, b, nx, ny, nz, r, s)
@@ -453,6 +570,7 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
             HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
         }
         std::swap(a, b);
+        ++st;
     }
     if (a != u)
         HC_TRY(hipMemcpyAsync(u, a, (size_t)nx * ny * nz * eb, hipMemcpyDeviceToDevice, s),
@@ -1200,6 +1318,72 @@ int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new, int 
         return fail(HC_EINVAL, "dtype %d is not supported", dtype);
     if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
     const hc::HeatTiling t = heat_tiling_for(dtype, nx, u, u_new);
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
+    return HC_OK;
+}
+
+int hc_heat_set_time_block(int steps_per_pass) {
+    g_msg.clear();
+    if (steps_per_pass != 1 && steps_per_pass != 2)
+        return fail(HC_EINVAL, "steps per pass %d: 1 or 2", steps_per_pass);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_time_block = steps_per_pass;
+    return HC_OK;
+}
+
+int hc_heat_get_time_block(void) { return current_time_block(); }
+
+int hc_heat2_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int pf, int xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    const hc::HeatTiling t = {vec, wx, by, zdepth, pf, xcd};
+    if (vec == 0 && wx == 0 && by == 0 && zdepth == 0 && pf == 0 && xcd == 0) {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        g_tiling2[dtype] = t;
+        return HC_OK;
+    }
+    if (!hc::heat2_tiling_supported(dtype, t))
+        return fail(HC_EINVAL,
+                    "two-step tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built "
+                    "for dtype %d",
+                    vec, wx, by, zdepth, pf, dtype);
+    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_tiling2[dtype] = t;
+    return HC_OK;
+}
+
+int hc_heat2_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth, int *pf, int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    hc::HeatTiling t;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        t = g_tiling2[dtype];
+    }
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
+    return HC_OK;
+}
+
+int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new, int *vec, int *wx,
+                        int *by, int *zdepth, int *pf, int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
+    const hc::HeatTiling t = heat2_tiling_for(dtype, nx, u, u_new);
     if (vec) *vec = t.vec;
     if (wx) *wx = t.wx;
     if (by) *by = t.by;

@@ -57,7 +57,10 @@ enum KernelKind {
     K_VK_BOUNDARY = 15,
     K_VK_FUSED = 16,
     K_VK_PLAIN = 17,
-    K_COUNT = 18
+    K_HEAT2_INTERIOR = 18,
+    K_HEAT2_BOUNDARY = 19,
+    K_HEAT2_FUSED = 20,
+    K_COUNT = 21
 };
 
 // ---- heat (heat_kernels.hip) ------------------------------------------------
@@ -80,6 +83,15 @@ hipError_t launch_heat_plain(int dtype, const void *u, void *un, int nx, int ny,
                              double r, unsigned long long seed, unsigned long long step,
                              hipStream_t s);
 hipError_t launch_copy_faces(int elem_bytes, const void *u, void *un, int nx, int ny, int nz,
+                             hipStream_t s);
+
+// ---- two steps per pass (heat2_kernels.hip) ------------------------------------
+// FP64, FP32 or bfloat16 (nearest) storage; the tile shapes are those of
+// HeatTiling, from a list of their own.  A launch over zt writes u^(t+2) of
+// the planes in zt from u^t.
+bool heat2_tiling_supported(int dtype, const HeatTiling &t);
+hipError_t launch_heat2_tile(int dtype, KernelKind kind, const void *u, void *un, int nx, int ny,
+                             int nz, double r, const ZTable &zt, const HeatTiling &t,
                              hipStream_t s);
 
 // ---- variable coefficient and source (varcoef_kernels.hip) ----------------------

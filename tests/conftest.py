@@ -27,3 +27,22 @@ def gpu():
     import paper_2608_11882_amd as hc
     hc.load()  # raises if the HIP library is not built
     return hc
+
+
+@pytest.fixture
+def one_step(gpu):
+    """One step per pass for the duration of a test: the single-step
+    kernels (the library takes two steps per pass by default)."""
+    saved = gpu.get_time_block()
+    gpu.set_time_block(1)
+    yield gpu
+    gpu.set_time_block(saved)
+
+
+@pytest.fixture(params=[1, 2], ids=["one_step", "two_steps"])
+def time_block(request, gpu):
+    """Run a test with one, then two steps per pass (restored afterwards)."""
+    saved = gpu.get_time_block()
+    gpu.set_time_block(request.param)
+    yield request.param
+    gpu.set_time_block(saved)

@@ -292,3 +292,33 @@ def test_vk_tiling_settings_and_automatic_choice(lib):
     odd[3] = ctypes.c_void_p(0x100000 * 4 + 8)                 # rhs not 16-byte aligned
     assert tiling_for(0, 512, odd)[0] == 1
     assert lib.hc_heat_vk_tiling_for(2, 512, *aligned, *([None] * 6)) == HC_EINVAL
+
+
+def test_time_block_and_two_step_tiling_settings(lib):
+    assert lib.hc_heat_get_time_block() in (1, 2)
+    saved = lib.hc_heat_get_time_block()
+    assert lib.hc_heat_set_time_block(0) == HC_EINVAL
+    assert lib.hc_heat_set_time_block(3) == HC_EINVAL
+    assert lib.hc_heat_get_time_block() == saved
+    assert lib.hc_heat_set_time_block(2) == HC_OK and hc.get_time_block() == 2
+    assert lib.hc_heat_set_time_block(saved) == HC_OK
+    assert lib.hc_heat2_set_tiling(3, 8, 1, 8, 16, 2, 8) == HC_EINVAL     # SR: single steps
+    assert lib.hc_heat2_set_tiling(0, 8, 1, 8, 16, 2, 8) == HC_EINVAL     # not built
+    assert lib.hc_heat2_set_tiling(0, 2, 2, 8, 16, 2, 65) == HC_EINVAL    # xcd
+    assert lib.hc_heat2_set_tiling(0, 2, 1, 16, 16, 2, 4) == HC_OK
+    assert hc.get_tiling2("f64") == dict(vec=2, wx=1, by=16, zdepth=16, pf=2, xcd=4)
+    hc.set_tiling2(dtype="f64")
+    assert hc.get_tiling2("f64") == hc.AUTO_TILING
+
+    def tiling_for(dtype, nx, a, b):
+        v = [ctypes.c_int(0) for _ in range(6)]
+        assert lib.hc_heat2_tiling_for(dtype, nx, a, b, *[ctypes.byref(x) for x in v]) == HC_OK
+        return tuple(x.value for x in v)
+
+    a, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000)
+    for dtype, vec in ((0, 2), (1, 4), (2, 4)):
+        t = tiling_for(dtype, 512, a, b)
+        assert t[0] == vec and lib.hc_heat2_set_tiling(dtype, *t) == HC_OK   # a built shape
+        lib.hc_heat2_set_tiling(dtype, 0, 0, 0, 0, 0, 0)
+    assert tiling_for(0, 511, a, b)[0] == 1
+    assert tiling_for(0, 512, ctypes.c_void_p(0x100008), b)[0] == 1

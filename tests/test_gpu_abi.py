@@ -59,8 +59,9 @@ def test_copy_probe_copies_bitwise_and_is_timed(gpu):
     assert n == 1 and ms > 0 and nbytes == 2 * src.numel() * 8
 
 
-def test_heat_kernels_are_timed_per_role(gpu):
-    note("prof counters on a split run")
+def test_heat_kernels_are_timed_per_role(one_step):
+    gpu = one_step
+    note("prof counters on a split run, one step per pass")
     u = torch.rand(40, 36, 70, dtype=torch.float64, device="cuda")
     un = torch.empty_like(u)
     gpu.prof_enable(True)
@@ -72,3 +73,27 @@ def test_heat_kernels_are_timed_per_role(gpu):
     assert n_i == 4 and n_b == 4 and ms_i > 0 and ms_b > 0
     # interior: reads planes 1..38, writes planes 2..37
     assert b_i == 4 * 8 * (38 * 36 * 70 + 36 * 34 * 68)
+
+
+def test_two_step_kernels_are_timed_per_role(gpu):
+    note("prof counters on a split run, two steps per pass")
+    saved = gpu.get_time_block()
+    gpu.set_time_block(2)
+    try:
+        u = torch.rand(40, 36, 70, dtype=torch.float64, device="cuda")
+        un = torch.empty_like(u)
+        gpu.prof_enable(True)
+        gpu.heat_step(u, un, 0.1, 5)
+        torch.cuda.synchronize()
+        ms_i, n_i, b_i = gpu.prof_read("heat2_interior")
+        ms_b, n_b, b_b = gpu.prof_read("heat2_boundary")
+        n_1 = gpu.prof_read("heat_interior")[1]
+        gpu.prof_enable(False)
+    finally:
+        gpu.set_time_block(saved)
+    # 5 steps: two two-step passes and a last single step
+    assert n_i == 2 and n_b == 2 and n_1 == 1 and ms_i > 0 and ms_b > 0
+    # interior: output planes 3..36 read planes 1..38
+    assert b_i == 2 * 8 * (38 * 36 * 70 + 34 * 34 * 68)
+    # boundary: output planes {1, 2, 37, 38} read planes 0..4 and 35..39
+    assert b_b == 2 * 8 * (10 * 36 * 70 + 4 * 34 * 68)

@@ -61,7 +61,7 @@ def field(dims, seed, dtype, noise=None):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("mode", ["split", "fused", "plain"])
-def test_small_config_bitwise(gpu, dtype, mode):
+def test_small_config_bitwise(gpu, dtype, mode, time_block):
     cfg = inputs.HEAT_SMALL
     note("heat %s 66^3 r=0.1 100 steps mode=%s" % (dtype, mode))
     u0 = inputs.sine_field_lowp(66, 66, 66, 1e-3, cfg["seed"], dtype)
@@ -110,7 +110,8 @@ def built_shapes(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_every_tile_shape_is_bitwise_identical(gpu, dtype):
+def test_every_tile_shape_is_bitwise_identical(one_step, dtype):
+    gpu = one_step
     dims = (2056, 37, 75)   # ragged against every width (2056 = 8 * 257) and depth
     u0 = field(dims, 31, dtype)
     want = oracle_heat(u0, 1.0 / 6.5, 5)
