@@ -318,7 +318,6 @@ def batch_section(hc, dev):
     for v, f in zip(batch.views(u0), fields):
         v.copy_(torch.from_numpy(f))
     lups = steps * sum((int(d[0]) - 2) * (int(d[1]) - 2) * (int(d[2]) - 2) for d in dims)
-    algo = steps * batch.step_bytes
 
     def timed(fn, reps=3):
         out = []
@@ -335,6 +334,9 @@ def batch_section(hc, dev):
 
     log("batch: autotune")
     tuned_ms = batch.autotune(u0, trial_steps=4)
+    # a pass moves one step's bytes; two steps per pass make steps / 2 passes
+    spp = batch.steps_per_pass()
+    algo = (steps // spp + steps % spp) * batch.step_bytes
     ms_graph = timed(lambda: batch.step(u, un, steps, graph=True))
     ms_direct = timed(lambda: batch.step(u, un, steps, graph=False))
     log("batch: sequential single-problem solves")
@@ -354,11 +356,14 @@ def batch_section(hc, dev):
         "lups": lups,
         "algo_bytes_per_step": batch.step_bytes,
         "tiling": batch.get_tiling(),
+        "steps_per_pass": spp,
         "autotune_ms_per_step": round(tuned_ms, 4),
         "autotune_candidates": len(batch.tune_results()),
         "graph": {"ms": round(ms_graph, 3), "glups": round(lups / (ms_graph / 1e3) / 1e9, 2),
                   "algo_hbm_gbs": round(algo / (ms_graph / 1e3) / 1e9, 1),
-                  "pct_of_hbm_peak": round(100 * algo / (ms_graph / 1e3) / 1e9 / PEAK_HBM_GBS, 2)},
+                  "pct_of_hbm_peak": round(100 * algo / (ms_graph / 1e3) / 1e9 / PEAK_HBM_GBS, 2),
+                  "single_step_equivalent_gbs":
+                      round(steps * batch.step_bytes / (ms_graph / 1e3) / 1e9, 1)},
         "direct_launches": {"ms": round(ms_direct, 3),
                             "glups": round(lups / (ms_direct / 1e3) / 1e9, 2)},
         "sequential_plain": {"ms": round(ms_plain, 3),

@@ -439,8 +439,9 @@ int hc_batch_layout(const hc_batch *b, long long *offsets, int *pitches,
  *            buffers, this step count and tile shape) and launched as one
  *            graph, joined to `stream` through events.
  * Each launch runs a persistent kernel whose blocks walk the work list of
- * (problem, x-tile, y-tile, run of planes) entries.  Enqueued; does not
- * wait.
+ * (problem, x-tile, y-tile, run of planes) entries; with two steps per pass
+ * (hc_batch_steps_per_pass) there is one launch per width class and pass.
+ * Enqueued; does not wait.
  */
 int hc_batch_step(hc_batch *b, void *u, void *u_new, int steps, int use_graph,
                   hc_stream_t stream);
@@ -459,7 +460,9 @@ int hc_batch_step(hc_batch *b, void *u, void *u_new, int steps, int use_graph,
  * per work-list entry); `item_depth`: the planes per work-list entry (0: a
  * problem's whole column; else near-equal runs of at least
  * max(item_depth, zdepth) planes).  hc_batch_classes writes the width
- * class each problem gets (classes[count]).
+ * class each problem gets (classes[count]).  A new batch starts with vec
+ * 16 / element size, 256 threads for HC_F32 and 512 otherwise, zdepth 16,
+ * pf 2, xcd 8, width class -1, grid 0, item_depth 64.
  */
 int hc_batch_set_tiling(hc_batch *b, int vec, int threads, int zdepth, int pf,
                         int xcd, int width_class, int grid, int item_depth);
@@ -484,6 +487,15 @@ int hc_batch_classes(hc_batch *b, int *classes);
 int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t stream,
                       double *best_ms);
 int hc_batch_tune_result(const hc_batch *b, int index, int *shape8, double *ms_per_step);
+
+/*
+ * Steps per pass hc_batch_step takes with the batch's current shape: 2 when
+ * hc_heat_set_time_block(2) is in effect (the default) and the shape is
+ * built for two steps (HC_BATCH2_SHAPES_* in batch2_kernels.hip; a last odd
+ * step then takes one pass), else 1; HC_EINVAL for a NULL batch.  The result
+ * of a step does not depend on it.
+ */
+int hc_batch_steps_per_pass(const hc_batch *b);
 
 /* Detail of the last failure on the calling thread ("" if none). */
 const char *hc_last_error_message(void);

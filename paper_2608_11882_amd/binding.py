@@ -91,6 +91,7 @@ def load():
         "hc_batch_classes": (i, [vp, ip]),
         "hc_batch_autotune": (i, [vp, vp, i, vp, dp]),
         "hc_batch_tune_result": (i, [vp, i, ip, dp]),
+        "hc_batch_steps_per_pass": (i, [vp]),
         "hc_cg_get_tiling": (None, [ip, ip, ip, ip, ip]),
         "heat_vk_step": (i, [vp, vp, vp, vp, i, i, i, d, i, i, i, i, vp]),
         "hc_heat_vk_set_tiling": (i, [i, i, i, i, i, i, i]),
@@ -535,6 +536,10 @@ class Batch:
         v = [ctypes.c_int(0) for _ in range(8)]
         _check(load().hc_batch_get_tiling(self._h, *[ctypes.byref(x) for x in v]))
         return dict(zip(self._KEYS, (x.value for x in v)))
+
+    def steps_per_pass(self) -> int:
+        """Steps one launch of this batch's shape advances (1 or 2)."""
+        return _check(load().hc_batch_steps_per_pass(self._h))
 
     def autotune(self, u, trial_steps: int = 4, stream=None) -> float:
         """Time every candidate shape on copies of u; keep the fastest.

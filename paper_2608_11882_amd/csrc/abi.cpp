@@ -801,11 +801,14 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
 
 
 // ---- batched heat ------------------------------------------------------------
-// Default batch shapes per precision: 16-byte lanes, blocks of 512 threads,
-// each problem with the width class that fits its rows; the autotuner
+// Default batch shapes per precision: 16-byte lanes, each problem with the
+// width class that fits its rows, work-list entries of 64 planes; blocks of
+// 256 threads for binary32 (the fastest shape for the uneven FP32
+// configuration at two steps per pass), 512 otherwise.  The autotuner
 // measures all the built ones.
-const hc::BatchTiling kBatchDefault[3] = {{2, 512, 16, 2, 8, -1}, {4, 512, 16, 2, 8, -1},
+const hc::BatchTiling kBatchDefault[3] = {{2, 512, 16, 2, 8, -1}, {4, 256, 16, 2, 8, -1},
                                           {8, 512, 16, 2, 8, -1}};
+constexpr int kBatchDefaultDepth = 64;
 
 }  // namespace
 
@@ -821,14 +824,19 @@ struct hc_batch {
     double step_bytes = 0.0;        // algorithmic bytes of one step of all problems
     hc::BatchTiling tiling{};
     int grid = 0;                   // persistent blocks (0: one per entry)
-    int item_depth = 0;             // planes per work-list entry (0: whole column)
+    int item_depth = kBatchDefaultDepth;  // planes per work-list entry (0: whole column)
     std::vector<hc::BatchProblem> probs;  // host copy of the problem table
     hc::BatchProblem *d_probs = nullptr;
     hc::BatchItem *d_items = nullptr;
     int nitems = 0, items_cap = 0;
+    int cls_first[5] = {}, cls_count[5] = {};  // each width class's slice of the list
     bool items_ok = false;
     hipStream_t gstream = nullptr;  // capture and launch stream of the graph
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // the width classes of a two-step pass run side by side on these
+    // streams (forked from and joined to the step's stream by events)
+    hipStream_t cstream[4] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[4] = {};
     hipGraphExec_t gexec = nullptr;
     const void *g_u = nullptr;
     const void *g_un = nullptr;
@@ -904,7 +912,11 @@ int batch_items(hc_batch *b) {
         }
     }
     std::vector<hc::BatchItem> items;
-    for (int c = 4; c >= 0; --c) items.insert(items.end(), per_class[c].begin(), per_class[c].end());
+    for (int c = 4; c >= 0; --c) {
+        b->cls_first[c] = (int)items.size();
+        b->cls_count[c] = (int)per_class[c].size();
+        items.insert(items.end(), per_class[c].begin(), per_class[c].end());
+    }
     if (items.size() > (size_t)INT32_MAX) return fail(HC_EINVAL, "work list too long");
     if ((int)items.size() > b->items_cap) {
         if (b->d_items) HC_TRY(hipFree(b->d_items), "hipFree");
@@ -936,13 +948,47 @@ void batch_drop_graph(hc_batch *b) {
 
 // The step loop on stream s: `steps` launches alternating the buffers, then
 // the copy that leaves the result in u when steps is odd.
+// Steps per pass the batch takes with its current shape: two when the
+// library's setting asks for two and the shape is built for them.
+int batch_time_block(const hc_batch *b) {
+    return current_time_block() == 2 && hc::batch2_tiling_supported(b->dtype, b->tiling) ? 2 : 1;
+}
+
 int batch_enqueue(hc_batch *b, void *u, void *un, int steps, hipStream_t s) {
     const int eb = hc::dtype_bytes(b->dtype);
+    const int tb = batch_time_block(b);
     void *a = u, *c = un;
-    for (int st = 0; st < steps; ++st) {
-        HC_TRY(hc::launch_heat_batch(b->dtype, a, c, b->d_probs, b->d_items, b->nitems, b->grid,
-                                     b->tiling, s),
-               "heat_batch launch");
+    for (int st = 0; st < steps;) {
+        if (tb == 2 && steps - st >= 2) {
+            // one launch per width class present; the classes run side by
+            // side, so their tails overlap
+            int used[5], nc = 0;
+            for (int k = 4; k >= 0; --k)
+                if (b->cls_count[k] > 0) used[nc++] = k;
+            if (nc > 1) {
+                HC_TRY(hipEventRecord(b->ev_fork, s), "hipEventRecord");
+                for (int i = 1; i < nc; ++i)
+                    HC_TRY(hipStreamWaitEvent(b->cstream[i - 1], b->ev_fork, 0), "hipStreamWaitEvent");
+            }
+            for (int i = 0; i < nc; ++i) {
+                const int k = used[i];
+                hipStream_t ks = i == 0 ? s : b->cstream[i - 1];
+                HC_TRY(hc::launch_heat_batch2(b->dtype, k, a, c, b->d_probs,
+                                              b->d_items + b->cls_first[k], b->cls_count[k],
+                                              b->grid, b->tiling, ks),
+                       "heat_batch2 launch");
+            }
+            for (int i = 1; i < nc; ++i) {
+                HC_TRY(hipEventRecord(b->ev_join[i - 1], b->cstream[i - 1]), "hipEventRecord");
+                HC_TRY(hipStreamWaitEvent(s, b->ev_join[i - 1], 0), "hipStreamWaitEvent");
+            }
+            st += 2;
+        } else {
+            HC_TRY(hc::launch_heat_batch(b->dtype, a, c, b->d_probs, b->d_items, b->nitems,
+                                         b->grid, b->tiling, s),
+                   "heat_batch launch");
+            ++st;
+        }
         std::swap(a, c);
     }
     if (a != u)
@@ -966,13 +1012,16 @@ int batch_run(hc_batch *b, void *u, void *un, int steps, int use_graph, hipStrea
     // u_new takes u's Dirichlet layer (a copy of the whole buffer)
     HC_TRY(hipMemcpyAsync(un, u, (size_t)b->total * eb, hipMemcpyDeviceToDevice, s),
            "hipMemcpyAsync");
+    // algorithmic bytes: a pass moves one step's bytes
+    const int tb = batch_time_block(b);
+    const double run_bytes = b->step_bytes * (steps / tb + steps % tb);
     if (!use_graph) {
-        Timed tm(hc::K_BATCH, s, b->step_bytes * steps, steps);
+        Timed tm(hc::K_BATCH, s, run_bytes, steps);
         if ((rc = batch_enqueue(b, u, un, steps, s))) return rc;
         tm.done();
         return HC_OK;
     }
-    const long long key = batch_shape_key(b->tiling);
+    const long long key = batch_shape_key(b->tiling) * 2 + (tb - 1);
     if (!b->gexec || b->g_u != u || b->g_un != un || b->g_steps != steps || b->g_key != key ||
         b->g_grid != b->grid || b->g_depth != b->item_depth) {
         batch_drop_graph(b);
@@ -999,7 +1048,7 @@ int batch_run(hc_batch *b, void *u, void *un, int steps, int use_graph, hipStrea
     HC_TRY(hipEventRecord(b->ev_in, s), "hipEventRecord");
     HC_TRY(hipStreamWaitEvent(b->gstream, b->ev_in, 0), "hipStreamWaitEvent");
     {
-        Timed tm(hc::K_BATCH, b->gstream, b->step_bytes * steps, steps);
+        Timed tm(hc::K_BATCH, b->gstream, run_bytes, steps);
         HC_TRY(hipGraphLaunch(b->gexec, b->gstream), "hipGraphLaunch");
         tm.done();
     }
@@ -1594,9 +1643,17 @@ int hc_batch_create(int count, const int *dims, const double *r, int dtype, hc_b
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
         const hipError_t e = hipGetLastError();
         rc = fail(HC_EHIP, "batch set-up: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < 4 && !rc; ++i) {
+        if (hipStreamCreateWithFlags(&b->cstream[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming) != hipSuccess) {
+            const hipError_t e = hipGetLastError();
+            rc = fail(HC_EHIP, "batch set-up: %s", hipGetErrorString(e));
+        }
     }
     if (rc) {
         hc_batch_destroy(b);
@@ -1614,6 +1671,11 @@ void hc_batch_destroy(hc_batch *b) {
     if (b->d_probs) (void)hipFree(b->d_probs);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (int i = 0; i < 4; ++i) {
+        if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
+        if (b->cstream[i]) (void)hipStreamDestroy(b->cstream[i]);
+    }
     if (b->gstream) (void)hipStreamDestroy(b->gstream);
     delete b;
 }
@@ -1796,6 +1858,12 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
     batch_drop_graph(b);
     if (best_ms) *best_ms = best;
     return batch_items(b);
+}
+
+int hc_batch_steps_per_pass(const hc_batch *b) {
+    g_msg.clear();
+    if (!b) return fail(HC_EINVAL, "batch is NULL");
+    return batch_time_block(b);
 }
 
 int hc_batch_tune_result(const hc_batch *b, int index, int *shape8, double *ms_per_step) {

@@ -24,22 +24,13 @@
 // one XCD (block_order), so that their shared halo rows meet in one L2.  The
 // Dirichlet layer is never written.
 
+#include "batch_class.hpp"
 #include "heat_tile.hpp"
 
 #include <climits>
 
 namespace hc {
 namespace {
-
-// Width class c: 8 << c lanes per row, NT >> (3 + c) rows.  A class exists
-// for a block size when it has at least 4 rows and one thread per ring
-// element.
-template <int NT, int CLS>
-struct WidthClass {
-    static constexpr int lanes = 8 << CLS;
-    static constexpr int rows = NT / lanes;
-    static constexpr bool valid = rows >= 4 && NT >= 2 * lanes + 2 * rows;
-};
 
 template <int VEC, int NT, int CLS>
 constexpr int class_lds() {
@@ -96,7 +87,7 @@ __global__ __launch_bounds__(NT) void heat_batch_step(
 bool batch_class_valid(int nt, int cls) {
     if (cls < 0 || cls > 4) return false;
     const int lanes = 8 << cls, rows = nt / lanes;
-    return rows >= 4 && nt >= 2 * lanes + 2 * rows;
+    return rows >= 4 && nt >= 2 * lanes + 2 * rows + 4;
 }
 
 // The block shapes built for the batched sweep, per precision:

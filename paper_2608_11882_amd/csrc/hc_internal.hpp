@@ -134,6 +134,14 @@ bool batch_tiling_supported(int dtype, const BatchTiling &t);
 bool batch_class_valid(int nt, int cls);
 // Every block shape built for `dtype` (xcd 0, class -1).
 void batch_shapes(int dtype, std::vector<BatchTiling> &out);
+// The two-step batched sweep (batch2_kernels.hip): its shapes are a subset
+// of the single-step ones.
+bool batch2_tiling_supported(int dtype, const BatchTiling &t);
+// One pass over the n work-list entries `items` of width class cls (all
+// of one class).
+hipError_t launch_heat_batch2(int dtype, int cls, const void *u, void *un,
+                              const BatchProblem *probs, const BatchItem *items, int n, int grid,
+                              const BatchTiling &t, hipStream_t s);
 // One time step of every problem; grid <= 0 or >= nitems: one block per
 // entry, else a persistent grid of `grid` blocks walking the list.
 hipError_t launch_heat_batch(int dtype, const void *u, void *un, const BatchProblem *probs,

@@ -75,7 +75,7 @@ SMALL_DIMS = [(3, 3, 3), (40, 12, 9), (64, 6, 70), (33, 20, 17), (128, 3, 5), (2
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("steps", [6, 7])
 @pytest.mark.parametrize("graph", [False, True])
-def test_small_batch_bitwise(gpu, dtype, steps, graph):
+def test_small_batch_bitwise(gpu, dtype, steps, graph, time_block):
     note("batch %s %d problems, %d steps, graph=%s" % (dtype, len(SMALL_DIMS), steps, graph))
     rs = np.linspace(0.05, 1.0 / 6.0, len(SMALL_DIMS))
     fields = make_fields(SMALL_DIMS, 11, dtype)
@@ -99,7 +99,7 @@ def test_layout_is_packed_and_aligned(gpu):
     batch.close()
 
 
-def test_every_batch_shape_class_and_grid_bitwise(gpu):
+def test_every_batch_shape_class_and_grid_bitwise(gpu, time_block):
     dims = [(64, 30, 40), (127, 9, 35), (73, 40, 20), (33, 32, 32), (190, 10, 18), (3, 5, 7),
             (500, 6, 9)]
     rs = [0.1, 0.15, 0.12, 1.0 / 6.5, 0.05, 0.16, 0.11]
@@ -140,7 +140,7 @@ def test_automatic_width_classes(gpu):
     batch.close()
 
 
-def test_graph_replays_and_odd_widths(gpu):
+def test_graph_replays_and_odd_widths(gpu, time_block):
     dims = [(31, 20, 20), (64, 16, 18), (45, 9, 30)]      # odd widths: padded rows
     rs = [0.1, 0.12, 0.14]
     fields = make_fields(dims, 5, "f32")
