@@ -37,7 +37,8 @@
 namespace hc {
 namespace {
 
-constexpr int kPF = 2;  // planes of field loads in flight
+constexpr int kPF = 2;   // planes of field loads in flight
+constexpr int kPFE = 1;  // planes ahead the epilogue's own loads are issued
 
 // Block order: the hardware deals workgroups to the 8 XCDs round-robin; with
 // g > 1, runs of g consecutive tiles (y-neighbours) are dealt to one XCD
@@ -100,7 +101,7 @@ struct BoxGeom {
     static constexpr int TX = 64 * VEC * WX;
     static constexpr int LD = TX + 2;
     static constexpr int NT = 64 * WX * BY;
-    static constexpr int RROW = TX / VEC;
+    static constexpr int RROW = TX / VEC;  // lanes per tile row
     static_assert(NT >= 2 * RROW + 2 * BY, "one thread per ring element");
     int kb, ke;
     long long plane, own, ring;  // ring: VEC-aligned offset of the ring load
@@ -108,7 +109,11 @@ struct BoxGeom {
     bool in[VEC];     // own nodes inside the box
     bool lane_in;     // all own nodes inside the box
     bool rin[VEC];    // ring nodes inside the box
+    // LDS slots (rows of [left ring][node 0 of every lane] ... [node VEC-1
+    // of every lane][right ring]: a wavefront's LDS accesses touch
+    // consecutive words); node e of a lane or row piece at slot + e * RROW
     int own_slot, rslot;
+    int xm_slot, xp_slot;  // left neighbour of node 0, right one of node VEC-1
     bool rvec;
     int rsel;         // a column node's index within its aligned ring load
 
@@ -133,7 +138,11 @@ struct BoxGeom {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) in[v] = (ia + v < nx) && (j < ny);
         lane_in = in[VEC - 1];
-        own_slot = (wy + 1) * LD + (wx * 64 + lane) * VEC + 1;
+        const int gl = wx * 64 + lane;  // lane within the tile row
+        const int rowb = (wy + 1) * LD;
+        own_slot = rowb + 1 + gl;
+        xm_slot = gl == 0 ? rowb : own_slot - 1 + (VEC - 1) * RROW;
+        xp_slot = gl == RROW - 1 ? rowb + TX + 1 : own_slot + 1;
 
         rvec = false;
         rslot = -1;
@@ -143,7 +152,7 @@ struct BoxGeom {
             const int row = t / RROW, q = t % RROW;
             rj = row == 0 ? j0 - 1 : j0 + BY;
             ri = i0 + q * VEC;
-            rslot = (row == 0 ? 0 : (BY + 1) * LD) + q * VEC + 1;
+            rslot = (row == 0 ? 0 : (BY + 1) * LD) + 1 + q;
             rvec = true;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) rin[v] = (rj >= 0) && (rj < ny) && (ri + v < nx);
@@ -227,21 +236,25 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
     };
     auto put = [&](const T *c, const T *rv) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) tile[g.own_slot + e] = c[e];
+        for (int e = 0; e < VEC; ++e) tile[g.own_slot + e * G::RROW] = c[e];
         if (g.rslot >= 0) {
             tile[g.rslot] = rv[0];
             if (g.rvec) {
 #pragma unroll
-                for (int e = 1; e < VEC; ++e) tile[g.rslot + e] = rv[e];
+                for (int e = 1; e < VEC; ++e) tile[g.rslot + e * G::RROW] = rv[e];
             }
         }
     };
-    auto nsums = [&](const T *zm, const T *zp, T *ns) {
+    // x neighbours inside the lane come from its registers (the same values
+    // the tile holds), the ones across lanes from the tile
+    auto nsums = [&](const T *zm, const T *c, const T *zp, T *ns) {
+        const T xm0 = tile[g.xm_slot];
+        const T xpl = tile[g.xp_slot];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            const int sl = g.own_slot + e;
-            const T xm = tile[sl - 1];
-            const T xp = tile[sl + 1];
+            const int sl = g.own_slot + e * G::RROW;
+            const T xm = e == 0 ? xm0 : c[e - 1];
+            const T xp = e == VEC - 1 ? xpl : c[e + 1];
             const T ym = tile[sl - G::LD];
             const T yp = tile[sl + G::LD];
             ns[e] = ((xm + xp) + (ym + yp)) + (zm[e] + zp[e]);
@@ -257,16 +270,17 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
         for (int s = 0; s < kPF + 2; ++s) col(kb - 1 + s, q[s]);
 #pragma unroll
         for (int s = 0; s < kPF; ++s) ringv(kb + s, rg[s]);
-        pre[0] = epi.prefetch(kb, g.own_b);
+#pragma unroll
+        for (int s = 0; s < kPFE && s < ZB; ++s) pre[s] = epi.prefetch(kb + s, g.own_b);
 #pragma unroll
         for (int s = 0; s < ZB; ++s) {
             __syncthreads();
             put(q[s + 1], rg[s]);
             if (s + kPF < ZB) ringv(kb + s + kPF, rg[s + kPF]);
-            if (s + 1 < ZB) pre[s + 1] = epi.prefetch(kb + s + 1, g.own_b);
+            if (s + kPFE < ZB) pre[s + kPFE] = epi.prefetch(kb + s + kPFE, g.own_b);
             __syncthreads();
             T ns[VEC];
-            nsums(q[s], q[s + 2], ns);
+            nsums(q[s], q[s + 1], q[s + 2], ns);
             epi.finish(g.in, g.lane_in, kb + s, g.own_b, lane_sink, q[s + 1], ns, pre[s]);
             if (s + 2 + kPF <= ZB + 1) col(kb + s + 1 + kPF, q[s + 2 + kPF]);
         }
@@ -287,7 +301,7 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
         put(c, rc);
         __syncthreads();
         T ns[VEC];
-        nsums(zm, zp, ns);
+        nsums(zm, c, zp, ns);
         epi.finish(g.in, g.lane_in, k, g.own_b, lane_sink, c, ns, pr);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
