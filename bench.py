@@ -407,8 +407,12 @@ def vk_section(hc, dev):
     beta = pb["beta"]
     lups = steps * (n - 2) ** 3
     algo_step = 8.0 * 2 * (n ** 3 + (n - 2) ** 3)   # u, kappa over all nodes; rhs, u_new inside
+    tb = hc.get_time_block()
+    passes = steps // tb + steps % tb              # a pass moves one step's bytes
+    kname = "vk2_interior" if tb == 2 else "vk_interior"
     res = {"grid": [n, n, n], "steps": steps, "beta": beta, "dt": pb["dt"],
-           "algo_bytes_per_lup_f64": 32, "paper_kbar_glups_h100": round(1e-9 / PAPER_KBAR_S, 2)}
+           "steps_per_pass": tb, "algo_bytes_per_lup_f64_per_pass": 32,
+           "paper_kbar_glups_h100": round(1e-9 / PAPER_KBAR_S, 2)}
 
     def run(u0, kap, rhs, mode, u, un):
         u.copy_(u0)
@@ -431,18 +435,27 @@ def vk_section(hc, dev):
         forms = {}
         for mode in ("split", "fused", "plain"):
             ms = run(u0, kap, rhs, mode, u, un)
+            npass = steps if mode == "plain" else passes
             forms[mode] = {"ms": round(ms, 3), "glups": round(lups / (ms / 1e3) / 1e9, 2),
-                           "algo_hbm_gbs": round(steps * algo_step * eb / 8 / (ms / 1e3) / 1e9, 1)}
+                           "algo_hbm_gbs": round(npass * algo_step * eb / 8 / (ms / 1e3) / 1e9, 1)}
+        if tb == 2:
+            hc.set_time_block(1)
+            for mode in ("split", "fused"):
+                ms = run(u0, kap, rhs, mode, u, un)
+                forms[mode + "_1_step"] = {"ms": round(ms, 3),
+                                           "glups": round(lups / (ms / 1e3) / 1e9, 2)}
+            hc.set_time_block(tb)
         hc.prof_enable(True, every=8)
         run(u0, kap, rhs, "split", u, un)
-        ims, inb, ibytes = hc.prof_read("vk_interior")
+        ims, inb, ibytes = hc.prof_read(kname)
         hc.prof_enable(False)
         ok = bool(torch.isfinite(u).all().item()) and float(u.min()) >= 0.0
-        entry = {"tiling": hc.vk_tiling_for(u, un, kap, rhs), "forms_500_steps": forms,
-                 "result_ok_nonnegative_finite": ok}
+        til = (hc.vk2_tiling_for(u, un, kap, rhs) if tb == 2 else hc.vk_tiling_for(u, un, kap, rhs))
+        entry = {"tiling": til, "forms_500_steps": forms, "result_ok_nonnegative_finite": ok}
         if inb:
             avg = ims / inb
             entry["interior_kernel"] = {
+                "kernel": kname, "steps_per_launch": tb,
                 "avg_launch_us": round(avg * 1e3, 2), "timed_launches": inb,
                 "algo_bytes_per_launch": ibytes / inb,
                 "achieved_gbs": round(ibytes / inb / (avg / 1e3) / 1e9, 1),

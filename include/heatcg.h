@@ -148,8 +148,9 @@ int heat_step_sr(void *u, void *u_new, int nx, int ny, int nz, double r,
  * registers and LDS and never stored).  Results do not depend on it: every
  * value of u^(t+1) is evaluated with the same expression and rounding as a
  * single step.  It applies to HC_F64, HC_F32 and HC_BF16 in HC_HEAT_SPLIT
- * and HC_HEAT_FUSED (a last odd step takes a single pass); heat_step_sr,
- * HC_HEAT_PLAIN and heat_vk_step always take single steps.  In the split
+ * and HC_HEAT_FUSED (a last odd step takes a single pass), to heat_vk_step
+ * (HC_F64, HC_F32) and to the batch (hc_batch_steps_per_pass); heat_step_sr
+ * and HC_HEAT_PLAIN always take single steps.  In the split
  * form with two steps per pass, the Boundary kernel owns the first and last
  * two planes of each slab (the depth of halo two steps need), the Interior
  * kernel the rest.  Default: 2.  HC_EINVAL for other values.
@@ -201,7 +202,9 @@ int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new,
  *         operation binary32, beta rounded to binary32 once).
  *  mode, parts, stream  as for heat_step_ex (HC_HEAT_SPLIT: Interior kernel
  *         on `stream`, Boundary planes on the internal stream).
- * Moves 4 values per updated node and step (u, kappa, rhs in, u_new out).
+ * Moves 4 values per updated node and pass (u, kappa, rhs in, u_new out);
+ * with two steps per pass (hc_heat_set_time_block(2), the default) a pass
+ * takes two steps, with the same bits as single steps.
  * Enqueues and returns; HC_EINVAL, HC_EALIAS as for heat_step_ex.
  */
 int heat_vk_step(void *u, void *u_new, const void *kappa, const void *rhs,
@@ -223,6 +226,16 @@ int hc_heat_vk_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth,
 int hc_heat_vk_tiling_for(int dtype, int nx, const void *u, const void *u_new,
                           const void *kappa, const void *rhs, int *vec,
                           int *wx, int *by, int *zdepth, int *pf, int *xcd);
+
+/* The same for the two-steps-per-pass variable-coefficient sweep (shapes
+ * in varcoef2_kernels.hip, HC_VK2_SHAPES_*). */
+int hc_heat_vk2_set_tiling(int dtype, int vec, int wx, int by, int zdepth,
+                           int pf, int xcd);
+int hc_heat_vk2_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth,
+                           int *pf, int *xcd);
+int hc_heat_vk2_tiling_for(int dtype, int nx, const void *u, const void *u_new,
+                           const void *kappa, const void *rhs, int *vec,
+                           int *wx, int *by, int *zdepth, int *pf, int *xcd);
 
 /*
  * cg_solve -- solve A x = b with Conjugate Gradient (the CG case study),
@@ -532,7 +545,10 @@ enum hc_kernel_kind {
     HC_K_HEAT2_INTERIOR = 18, /* two steps per pass            */
     HC_K_HEAT2_BOUNDARY = 19,
     HC_K_HEAT2_FUSED = 20,
-    HC_K_COUNT = 21
+    HC_K_VK2_INTERIOR = 21,   /* variable coefficient, two steps */
+    HC_K_VK2_BOUNDARY = 22,
+    HC_K_VK2_FUSED = 23,
+    HC_K_COUNT = 24
 };
 int hc_prof_enable(int every);
 int hc_prof_read(int kind, double *total_ms, long long *launches,

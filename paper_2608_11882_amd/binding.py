@@ -19,7 +19,8 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "AUTO_TILING", "tiling_for", "cg_solve_ir", "cg_ir_workspace_bytes",
            "lap7_apply_f32", "set_cg_ir_tiling", "get_cg_ir_tiling", "DEFAULT_CG_IR_TILING",
            "Batch", "heat_vk_step", "set_vk_tiling", "get_vk_tiling", "vk_tiling_for",
-           "set_time_block", "get_time_block", "set_tiling2", "get_tiling2", "tiling2_for"]
+           "set_time_block", "get_time_block", "set_tiling2", "get_tiling2", "tiling2_for",
+           "set_vk2_tiling", "get_vk2_tiling", "vk2_tiling_for"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
@@ -31,7 +32,8 @@ KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain"
            "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8,
            "cg32_direction": 9, "cg32_update": 10, "ir_residual": 11, "ir_update": 12,
            "batch": 13, "vk_interior": 14, "vk_boundary": 15, "vk_fused": 16, "vk_plain": 17,
-           "heat2_interior": 18, "heat2_boundary": 19, "heat2_fused": 20}
+           "heat2_interior": 18, "heat2_boundary": 19, "heat2_fused": 20,
+           "vk2_interior": 21, "vk2_boundary": 22, "vk2_fused": 23}
 
 _lib = None
 
@@ -102,6 +104,9 @@ def load():
         "hc_heat2_set_tiling": (i, [i, i, i, i, i, i, i]),
         "hc_heat2_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
         "hc_heat2_tiling_for": (i, [i, i, vp, vp, ip, ip, ip, ip, ip, ip]),
+        "hc_heat_vk2_set_tiling": (i, [i, i, i, i, i, i, i]),
+        "hc_heat_vk2_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
+        "hc_heat_vk2_tiling_for": (i, [i, i, vp, vp, vp, vp, ip, ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -407,6 +412,36 @@ def vk_tiling_for(u, u_new, kappa, rhs) -> dict:
     ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (u, u_new, kappa, rhs)]
     _check(load().hc_heat_vk_tiling_for(_dtype_code(u), int(u.shape[-1]), *ptrs,
                                         *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def set_vk2_tiling(vec: int | None = None, wx: int | None = None, by: int | None = None,
+                   zdepth: int | None = None, pf: int = 2, xcd: int = 8,
+                   dtype: str = "f64") -> None:
+    """Tile shape of the two-step variable-coefficient kernels; with no
+    shape given, the automatic choice."""
+    if vec is None and wx is None and by is None and zdepth is None:
+        t = AUTO_TILING
+    else:
+        if None in (vec, wx, by, zdepth):
+            raise ValueError("give vec, wx, by and zdepth, or none of them")
+        t = dict(vec=vec, wx=wx, by=by, zdepth=zdepth, pf=pf, xcd=xcd)
+    _check(load().hc_heat_vk2_set_tiling(DTYPES[dtype], *(int(t[k]) for k in _TILE_KEYS)))
+
+
+def get_vk2_tiling(dtype: str = "f64") -> dict:
+    v = [ctypes.c_int(0) for _ in range(6)]
+    _check(load().hc_heat_vk2_get_tiling(DTYPES[dtype], *[ctypes.byref(x) for x in v]))
+    return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def vk2_tiling_for(u, u_new, kappa, rhs) -> dict:
+    """The tile shape a two-step variable-coefficient sweep of these tensors
+    would run with."""
+    v = [ctypes.c_int(0) for _ in range(6)]
+    ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (u, u_new, kappa, rhs)]
+    _check(load().hc_heat_vk2_tiling_for(_dtype_code(u), int(u.shape[-1]), *ptrs,
+                                         *[ctypes.byref(x) for x in v]))
     return dict(zip(_TILE_KEYS, (x.value for x in v)))
 
 

@@ -16,6 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libheatcg.so")
 SOURCES = ["abi.cpp", "heat_kernels.hip", "heat2_kernels.hip", "varcoef_kernels.hip",
+           "varcoef2_kernels.hip",
            "batch_kernels.hip", "batch2_kernels.hip", "cg_kernels.hip", "probe.hip"]
 
 ARCH = "gfx950"

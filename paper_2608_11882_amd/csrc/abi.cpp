@@ -114,6 +114,31 @@ const hc::HeatTiling kVkAuto[2][4] = {
     {{1, 4, 4, 16, 2, 8}, {4, 1, 8, 16, 2, 8}, {1, 1, 8, 16, 2, 8}, {}},
 };
 
+// Two-step variable-coefficient sweep: shapes of its own, per precision;
+// the automatic one is the fastest of a sweep over the built ones at 512^3
+// on MI355X (16-byte lanes, tiles 128 nodes wide and 4 rows tall, one plane
+// of loads ahead: the register queues of u and kappa are long).
+hc::HeatTiling g_vk2_tiling[2] = {};
+const hc::HeatTiling kVk2Auto[2][2] = {
+    {{2, 1, 4, 32, 1, 8}, {}},
+    {{4, 1, 4, 32, 1, 8}, {}},
+};
+
+hc::HeatTiling vk2_tiling_for(int dtype, int nx, const void *const *arrays, int narrays) {
+    hc::HeatTiling til;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        til = g_vk2_tiling[dtype];
+    }
+    if (til.vec == 0) til = kVk2Auto[dtype][0];
+    const uintptr_t lane_bytes = (uintptr_t)til.vec * (uintptr_t)hc::dtype_bytes(dtype);
+    bool fits = til.vec == 1 || nx % til.vec == 0;
+    for (int q = 0; q < narrays && fits; ++q)
+        fits = reinterpret_cast<uintptr_t>(arrays[q]) % lane_bytes == 0;
+    if (!fits) til = {1, 4, 4, 16, 2, til.xcd};
+    return til;
+}
+
 hc::HeatTiling vk_tiling_for(int dtype, int nx, const void *const *arrays, int narrays) {
     hc::HeatTiling til;
     {
@@ -467,13 +492,13 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
 
     // two steps per pass where the sweep allows it (constant coefficient,
     // nearest rounding, z-marching forms); a last odd step takes one pass
-    const bool two = !vk && dtype != hc::kDtypeBF16SR && mode != HC_HEAT_PLAIN &&
-                     steps >= 2 && current_time_block() == 2;
+    const bool two = dtype != hc::kDtypeBF16SR && mode != HC_HEAT_PLAIN && steps >= 2 &&
+                     current_time_block() == 2;
     hc::HeatTiling til2 = {};
     hc::ZTable tin2 = empty_table(), tbd2 = empty_table();
     double bytes_in2 = 0.0, bytes_bd2 = 0.0;
     if (two) {
-        til2 = heat2_tiling_for(dtype, nx, u, un);
+        til2 = vk ? vk2_tiling_for(dtype, nx, arrays, 4) : heat2_tiling_for(dtype, nx, u, un);
         if (mode == HC_HEAT_SPLIT) {
             // the first and last two planes of a slab are its Boundary planes
             for (int q = 0; q < parts; ++q) {
@@ -497,9 +522,18 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
         if (hc::heat_tile_blocks(nx, ny, til2, tin2) > 2147483647LL ||
             hc::heat_tile_blocks(nx, ny, til2, tbd2) > 2147483647LL)
             return fail(HC_EINVAL, "grid too large for this tile shape");
-        bytes_in2 = tile_algo_bytes(tin2, nx, ny, nz, eb, 2);
-        bytes_bd2 = tile_algo_bytes(tbd2, nx, ny, nz, eb, 2);
+        bytes_in2 = fields * tile_algo_bytes(tin2, nx, ny, nz, eb, 2);
+        bytes_bd2 = fields * tile_algo_bytes(tbd2, nx, ny, nz, eb, 2);
     }
+    const hc::KernelKind k2_fused = vk ? hc::K_VK2_FUSED : hc::K_HEAT2_FUSED;
+    const hc::KernelKind k2_int = vk ? hc::K_VK2_INTERIOR : hc::K_HEAT2_INTERIOR;
+    const hc::KernelKind k2_bd = vk ? hc::K_VK2_BOUNDARY : hc::K_HEAT2_BOUNDARY;
+    auto tile2_launch = [&](hc::KernelKind kind, const hc::ZTable &zt, const void *a, void *b,
+                            hipStream_t st) {
+        return vk ? hc::launch_heat_vk2_tile(dtype, kind, a, kap, rhs, b, nx, ny, nz, r, zt, til2,
+                                             st)
+                  : hc::launch_heat2_tile(dtype, kind, a, b, nx, ny, nz, r, zt, til2, st);
+    };
 
     HC_TRY(hc::launch_copy_faces((int)eb, u, un, nx, ny, nz, s), "copy_faces launch");
     const bool split = (mode == HC_HEAT_SPLIT) && (tbd.n > 0 || tbd2.n > 0);
@@ -511,24 +545,18 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     for (int st = 0; st < steps;) {
         if (two && steps - st >= 2) {
             if (mode == HC_HEAT_FUSED) {
-                Timed tm(hc::K_HEAT2_FUSED, s, bytes_in2);
-                HC_TRY(hc::launch_heat2_tile(dtype, hc::K_HEAT2_FUSED, a, b, nx, ny, nz, r, tin2,
-                                             til2, s),
-                       "heat2_fused launch");
+                Timed tm(k2_fused, s, bytes_in2);
+                HC_TRY(tile2_launch(k2_fused, tin2, a, b, s), "heat2_fused launch");
                 tm.done();
             } else {
                 {
-                    Timed tm(hc::K_HEAT2_BOUNDARY, d->aux, bytes_bd2);
-                    HC_TRY(hc::launch_heat2_tile(dtype, hc::K_HEAT2_BOUNDARY, a, b, nx, ny, nz,
-                                                 r, tbd2, til2, d->aux),
-                           "heat2_boundary launch");
+                    Timed tm(k2_bd, d->aux, bytes_bd2);
+                    HC_TRY(tile2_launch(k2_bd, tbd2, a, b, d->aux), "heat2_boundary launch");
                     tm.done();
                 }
                 if (tin2.n > 0) {
-                    Timed tm(hc::K_HEAT2_INTERIOR, s, bytes_in2);
-                    HC_TRY(hc::launch_heat2_tile(dtype, hc::K_HEAT2_INTERIOR, a, b, nx, ny, nz,
-                                                 r, tin2, til2, s),
-                           "heat2_interior launch");
+                    Timed tm(k2_int, s, bytes_in2);
+                    HC_TRY(tile2_launch(k2_int, tin2, a, b, s), "heat2_interior launch");
                     tm.done();
                 }
                 HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
@@ -1433,6 +1461,64 @@ int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new, int
         return fail(HC_EINVAL, "dtype %d is not supported", dtype);
     if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
     const hc::HeatTiling t = heat2_tiling_for(dtype, nx, u, u_new);
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
+    return HC_OK;
+}
+
+int hc_heat_vk2_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int pf, int xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    const hc::HeatTiling t = {vec, wx, by, zdepth, pf, xcd};
+    if (vec == 0 && wx == 0 && by == 0 && zdepth == 0 && pf == 0 && xcd == 0) {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        g_vk2_tiling[dtype] = t;
+        return HC_OK;
+    }
+    if (!hc::heat_vk2_tiling_supported(dtype, t))
+        return fail(HC_EINVAL,
+                    "two-step variable-coefficient tile shape (vec %d, wx %d, by %d, zdepth %d, "
+                    "pf %d) is not built for dtype %d",
+                    vec, wx, by, zdepth, pf, dtype);
+    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_vk2_tiling[dtype] = t;
+    return HC_OK;
+}
+
+int hc_heat_vk2_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth, int *pf,
+                           int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    hc::HeatTiling t;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        t = g_vk2_tiling[dtype];
+    }
+    if (vec) *vec = t.vec;
+    if (wx) *wx = t.wx;
+    if (by) *by = t.by;
+    if (zdepth) *zdepth = t.zdepth;
+    if (pf) *pf = t.pf;
+    if (xcd) *xcd = t.xcd;
+    return HC_OK;
+}
+
+int hc_heat_vk2_tiling_for(int dtype, int nx, const void *u, const void *u_new,
+                           const void *kappa, const void *rhs, int *vec, int *wx, int *by,
+                           int *zdepth, int *pf, int *xcd) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d is not supported", dtype);
+    if (nx < 3) return fail(HC_EINVAL, "nx = %d < 3", nx);
+    const void *arrays[4] = {u, u_new, kappa, rhs};
+    const hc::HeatTiling t = vk2_tiling_for(dtype, nx, arrays, 4);
     if (vec) *vec = t.vec;
     if (wx) *wx = t.wx;
     if (by) *by = t.by;

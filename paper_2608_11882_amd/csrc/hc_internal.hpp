@@ -60,7 +60,10 @@ enum KernelKind {
     K_HEAT2_INTERIOR = 18,
     K_HEAT2_BOUNDARY = 19,
     K_HEAT2_FUSED = 20,
-    K_COUNT = 21
+    K_VK2_INTERIOR = 21,
+    K_VK2_BOUNDARY = 22,
+    K_VK2_FUSED = 23,
+    K_COUNT = 24
 };
 
 // ---- heat (heat_kernels.hip) ------------------------------------------------
@@ -103,6 +106,12 @@ hipError_t launch_heat_vk_tile(int dtype, KernelKind kind, const void *u, const 
                                const ZTable &zt, const HeatTiling &t, hipStream_t s);
 hipError_t launch_heat_vk_plain(int dtype, const void *u, const void *kap, const void *rhs,
                                 void *un, int nx, int ny, int nz, double beta, hipStream_t s);
+
+// Two steps per pass of the same (varcoef2_kernels.hip).
+bool heat_vk2_tiling_supported(int dtype, const HeatTiling &t);
+hipError_t launch_heat_vk2_tile(int dtype, KernelKind kind, const void *u, const void *kap,
+                                const void *rhs, void *un, int nx, int ny, int nz, double beta,
+                                const ZTable &zt, const HeatTiling &t, hipStream_t s);
 
 // ---- batched heat (batch_kernels.hip) ------------------------------------------
 // One problem of a batch: its array starts `offset` elements into the packed

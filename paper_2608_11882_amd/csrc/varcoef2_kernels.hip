@@ -1,0 +1,109 @@
+// varcoef2_kernels.hip -- Interior / Boundary / fused sweeps of the
+// variable-coefficient step with a source taking two steps per pass (tile
+// body in varcoef_tile2.hpp), FP64 and FP32.
+
+#include "varcoef_tile2.hpp"
+
+#include <climits>
+#include <type_traits>
+
+namespace hc {
+namespace {
+
+#define HC_VK2_KERNEL(NAME)                                                                   \
+    template <class P, int VEC, int WX, int BY, int PF, int ZB>                               \
+    __global__ __launch_bounds__(64 * WX * BY) void NAME(                                     \
+        const typename P::S *__restrict__ u, const typename P::S *__restrict__ kap,           \
+        const typename P::S *__restrict__ rhs, typename P::S *__restrict__ un, int nx,        \
+        int ny, int nz, typename P::C beta, ZTable zt, int ntx, int nty, int xcd) {           \
+        using G = TileGeom2<VEC, 64 * WX, BY>;                                                \
+        __shared__ typename P::C tu[G::U_ELEMS];                                              \
+        __shared__ typename P::C tk[2 * G::U_ELEMS];                                          \
+        __shared__ typename P::C ta[2 * G::A_ELEMS];                                          \
+        const auto g = block_tile2<VEC, 64 * WX, BY>(nx, ny, nz, zt, ntx, nty, xcd, ZB);      \
+        vk_tile_sweep2<P, VEC, 64 * WX, BY, PF, ZB>(u, kap, rhs, un, beta, g, tu, tk, ta);    \
+    }
+
+// Three entry points with one body, so that profiles name the role.
+HC_VK2_KERNEL(heat_vk2_interior)
+HC_VK2_KERNEL(heat_vk2_boundary)
+HC_VK2_KERNEL(heat_vk2_fused)
+#undef HC_VK2_KERNEL
+
+}  // namespace
+
+// Tile shapes built for the two-step variable-coefficient sweep, per
+// precision: X(vec, wx, by, pf, zdepth).  (1, 4, 4, 2, 16) is the fallback
+// for arrays that do not allow wide lanes.
+#define HC_VK2_SHAPES_F64(X)                                                     \
+    X(1, 4, 4, 2, 16) X(1, 2, 4, 2, 32) X(2, 1, 4, 2, 32) X(2, 2, 4, 2, 32)     \
+    X(2, 1, 4, 1, 32) X(2, 1, 4, 2, 16) X(2, 1, 8, 1, 32)
+#define HC_VK2_SHAPES_F32(X)                                                     \
+    X(1, 4, 4, 2, 16) X(1, 2, 4, 2, 32) X(2, 2, 4, 2, 32) X(4, 1, 4, 2, 32)     \
+    X(4, 1, 4, 1, 32) X(4, 1, 4, 2, 16) X(4, 1, 8, 1, 32)
+
+#define HC_VK2_KEY(V, W, B, P, Z) ((((V * 8 + W) * 32 + B) * 8 + P) * 128 + Z)
+
+bool heat_vk2_tiling_supported(int dtype, const HeatTiling &t) {
+    const int key = HC_VK2_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
+#define HC_X(V, W, B, P, Z) if (key == HC_VK2_KEY(V, W, B, P, Z)) return true;
+    if (dtype == kDtypeF64) { HC_VK2_SHAPES_F64(HC_X) }
+    if (dtype == kDtypeF32) { HC_VK2_SHAPES_F32(HC_X) }
+#undef HC_X
+    return false;
+}
+
+template <class P>
+static hipError_t launch_vk2(KernelKind kind, const void *u, const void *kap, const void *rhs,
+                             void *un, int nx, int ny, int nz, double beta, const ZTable &zt,
+                             const HeatTiling &t, hipStream_t s) {
+    using S = typename P::S;
+    using C = typename P::C;
+    const long long nb = heat_tile_blocks(nx, ny, t, zt);
+    if (nb <= 0) return hipSuccess;
+    if (nb > INT_MAX) return hipErrorInvalidConfiguration;
+    const int txw = tile_width(t);
+    const int ntx = (nx + txw - 1) / txw;
+    const int nty = (ny - 2 + t.by - 1) / t.by;
+    const dim3 grid((unsigned)nb), block(64 * t.wx * t.by);
+    const S *us = static_cast<const S *>(u);
+    const S *ks = static_cast<const S *>(kap);
+    const S *rs = static_cast<const S *>(rhs);
+    S *uns = static_cast<S *>(un);
+    const C b = (C)beta;
+    const int shape = HC_VK2_KEY(t.vec, t.wx, t.by, t.pf, t.zdepth);
+#define HC_X(V, W, B, PF, Z)                                                         \
+    if (shape == HC_VK2_KEY(V, W, B, PF, Z)) {                                       \
+        if (kind == K_VK2_INTERIOR)                                                  \
+            heat_vk2_interior<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(             \
+                us, ks, rs, uns, nx, ny, nz, b, zt, ntx, nty, t.xcd);                \
+        else if (kind == K_VK2_BOUNDARY)                                             \
+            heat_vk2_boundary<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(             \
+                us, ks, rs, uns, nx, ny, nz, b, zt, ntx, nty, t.xcd);                \
+        else                                                                         \
+            heat_vk2_fused<P, V, W, B, PF, Z><<<grid, block, 0, s>>>(                \
+                us, ks, rs, uns, nx, ny, nz, b, zt, ntx, nty, t.xcd);                \
+        return hipGetLastError();                                                    \
+    }
+    if constexpr (std::is_same<P, PrecF64>::value) {
+        HC_VK2_SHAPES_F64(HC_X)
+    } else {
+        HC_VK2_SHAPES_F32(HC_X)
+    }
+#undef HC_X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_heat_vk2_tile(int dtype, KernelKind kind, const void *u, const void *kap,
+                                const void *rhs, void *un, int nx, int ny, int nz, double beta,
+                                const ZTable &zt, const HeatTiling &t, hipStream_t s) {
+    switch (dtype) {
+        case kDtypeF64:
+            return launch_vk2<PrecF64>(kind, u, kap, rhs, un, nx, ny, nz, beta, zt, t, s);
+        case kDtypeF32:
+            return launch_vk2<PrecF32>(kind, u, kap, rhs, un, nx, ny, nz, beta, zt, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hc

@@ -322,3 +322,29 @@ def test_time_block_and_two_step_tiling_settings(lib):
         lib.hc_heat2_set_tiling(dtype, 0, 0, 0, 0, 0, 0)
     assert tiling_for(0, 511, a, b)[0] == 1
     assert tiling_for(0, 512, ctypes.c_void_p(0x100008), b)[0] == 1
+
+
+def test_every_automatic_shape_is_a_built_shape(lib):
+    """The automatic tile shape of every sweep, for widths that allow each
+    lane width, is one the library is built with (a launch would refuse any
+    other)."""
+    a, b, c, d = (ctypes.c_void_p(0x100000 * (q + 1)) for q in range(4))
+    v = [ctypes.c_int(0) for _ in range(6)]
+    refs = [ctypes.byref(x) for x in v]
+    for nx in (3, 7, 64, 130, 512, 1000, 1024):
+        for dtype in (0, 1, 2):
+            assert lib.hc_heat_tiling_for(dtype, nx, a, b, *refs) == HC_OK
+            assert lib.hc_heat_set_tiling(dtype, *(x.value for x in v)) == HC_OK
+            assert lib.hc_heat2_tiling_for(dtype, nx, a, b, *refs) == HC_OK
+            assert lib.hc_heat2_set_tiling(dtype, *(x.value for x in v)) == HC_OK
+        for dtype in (0, 1):
+            assert lib.hc_heat_vk_tiling_for(dtype, nx, a, b, c, d, *refs) == HC_OK
+            assert lib.hc_heat_vk_set_tiling(dtype, *(x.value for x in v)) == HC_OK
+            assert lib.hc_heat_vk2_tiling_for(dtype, nx, a, b, c, d, *refs) == HC_OK
+            assert lib.hc_heat_vk2_set_tiling(dtype, *(x.value for x in v)) == HC_OK
+    for dtype in (0, 1, 2):
+        for f in (lib.hc_heat_set_tiling, lib.hc_heat2_set_tiling):
+            assert f(dtype, 0, 0, 0, 0, 0, 0) == HC_OK
+    for dtype in (0, 1):
+        for f in (lib.hc_heat_vk_set_tiling, lib.hc_heat_vk2_set_tiling):
+            assert f(dtype, 0, 0, 0, 0, 0, 0) == HC_OK

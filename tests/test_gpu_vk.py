@@ -39,7 +39,7 @@ def random_case(dims, seed, dtype=np.float64):
 
 
 @pytest.mark.parametrize("mode", ["split", "fused", "plain"])
-def test_papers_test_case_66_bitwise(gpu, mode):
+def test_papers_test_case_66_bitwise(gpu, mode, time_block):
     note("vk paper problem 66^3, 60 steps, mode=%s" % mode)
     pb = inputs.paper_problem(66)
     want = oracle.heat_vk(pb["u0"], pb["kappa"], pb["rhs"], pb["beta"], 60)
@@ -50,7 +50,7 @@ def test_papers_test_case_66_bitwise(gpu, mode):
 @pytest.mark.parametrize("dims", [(3, 3, 3), (5, 4, 3), (130, 9, 7), (67, 33, 41),
                                   (260, 12, 70), (1029, 6, 5), (64, 131, 36)])
 @pytest.mark.parametrize("mode", ["split", "fused", "plain"])
-def test_random_coefficients_bitwise(gpu, dims, mode):
+def test_random_coefficients_bitwise(gpu, dims, mode, time_block):
     note("vk random %s mode=%s" % (dims, mode))
     u0, kappa, rhs = random_case(dims, seed=sum(dims))
     for steps in (1, 4):
@@ -59,8 +59,8 @@ def test_random_coefficients_bitwise(gpu, dims, mode):
         assert np.array_equal(got, want), (dims, mode, steps)
 
 
-@pytest.mark.parametrize("parts", [2, 3, 7])
-def test_split_into_slabs_bitwise(gpu, parts):
+@pytest.mark.parametrize("parts", [2, 3, 7, 16])
+def test_split_into_slabs_bitwise(gpu, parts, time_block):
     dims = (70, 20, 40)
     note("vk split parts=%d %s" % (parts, dims))
     u0, kappa, rhs = random_case(dims, seed=3)
@@ -69,7 +69,7 @@ def test_split_into_slabs_bitwise(gpu, parts):
 
 
 @pytest.mark.parametrize("mode", ["split", "fused", "plain"])
-def test_f32_bitwise(gpu, mode):
+def test_f32_bitwise(gpu, mode, time_block):
     dims = (132, 37, 45)
     note("vk f32 %s mode=%s" % (dims, mode))
     u0, kappa, rhs = random_case(dims, seed=8, dtype=np.float32)
@@ -94,7 +94,8 @@ def built_shapes(hc, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_every_built_shape_bitwise(gpu, dtype):
+def test_every_built_shape_bitwise(one_step, dtype):
+    gpu = one_step
     shapes = built_shapes(gpu, dtype)
     assert len(shapes) >= 8
     npdt = np.float64 if dtype == "f64" else np.float32
@@ -112,6 +113,45 @@ def test_every_built_shape_bitwise(gpu, dtype):
                     assert np.array_equal(got, want), (shape, xcd, mode)
     finally:
         gpu.set_vk_tiling(dtype=dtype)
+
+
+def built_shapes2(hc, dtype):
+    lib = hc.load()
+    code = hc.DTYPES[dtype]
+    out = []
+    for vec in (1, 2, 4):
+        for wx in (1, 2, 4):
+            for by in (4, 8, 16):
+                for zd in (16, 32):
+                    for pf in (1, 2, 3):
+                        if lib.hc_heat_vk2_set_tiling(code, vec, wx, by, zd, pf, 0) == 0:
+                            out.append((vec, wx, by, zd, pf))
+    hc.set_vk2_tiling(dtype=dtype)
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_every_built_two_step_shape_bitwise(gpu, dtype):
+    saved = gpu.get_time_block()
+    gpu.set_time_block(2)
+    shapes = built_shapes2(gpu, dtype)
+    assert len(shapes) >= 5
+    npdt = np.float64 if dtype == "f64" else np.float32
+    dims = (264, 19, 75)
+    u0, kappa, rhs = random_case(dims, seed=23, dtype=npdt)
+    ref = oracle.heat_vk if dtype == "f64" else oracle.heat_vk_f32
+    want = ref(u0, kappa, rhs, 0.04, 5)
+    try:
+        for shape in shapes:
+            for xcd in (0, 8):
+                for mode in ("split", "fused"):
+                    note("vk2 %s shape %s xcd=%d %s" % (dtype, shape, xcd, mode))
+                    gpu.set_vk2_tiling(*shape, xcd=xcd, dtype=dtype)
+                    got = gpu_vk(gpu, u0, kappa, rhs, 0.04, 5, mode=mode)
+                    assert np.array_equal(got, want), (shape, xcd, mode)
+    finally:
+        gpu.set_vk2_tiling(dtype=dtype)
+        gpu.set_time_block(saved)
 
 
 def test_tiling_for_reports_a_built_shape_and_odd_rows_fall_back(gpu):
@@ -156,11 +196,12 @@ def test_degenerate_steps_and_buffers(gpu):
 
 
 @pytest.mark.parametrize("mode", ["split", "fused"])
-def test_papers_test_case_512_full_size(gpu, mode):
+def test_papers_test_case_512_full_size(gpu, mode, time_block):
     """The configuration the variable-coefficient rate is measured on, in
     the launch shape the benchmark times; compared in full after 3 steps."""
     n, steps = inputs.VARCOEF["n"], 3
-    note("vk paper problem %d^3 %d steps mode=%s (full size)" % (n, steps, mode))
+    note("vk paper problem %d^3 %d steps mode=%s, %d per pass (full size)"
+         % (n, steps, mode, time_block))
     pb = inputs.paper_problem(n)
     want = oracle.heat_vk(pb["u0"], pb["kappa"], pb["rhs"], pb["beta"], steps)
     got = gpu_vk(gpu, pb["u0"], pb["kappa"], pb["rhs"], pb["beta"], steps, mode=mode)
