@@ -45,7 +45,7 @@ struct TileGeom2 {
     static constexpr int R1N = 2 * TXL + 2 * BY;      // inner ring: rows, columns
     static constexpr int R2N = 2 * TXL + 2 * BY + 4;  // outer ring + inner corners
     static constexpr int U_ELEMS = (BY + 4) * LDU;
-    static constexpr int A_ELEMS = (BY + 2) * LDA + 1;  // + one write-only sink slot
+    static constexpr int A_ELEMS = (BY + 2) * LDA + 1;  // + one slot no thread reads
     static_assert(NT % 64 == 0, "whole wavefronts");
     static_assert(NT <= 1024, "at most 1024 threads per block");
     static_assert(NT >= R2N, "one thread per ring element");
@@ -311,18 +311,20 @@ __device__ __forceinline__ void heat_tile_sweep2(const typename P::S *__restrict
             step(tu, G::LDU, g.own_u, g.xm_u, g.xp_u, true, qc[s], qc[s + 1], qc[s + 2], upd,
                  qa[s]);
             to_storage<P, VEC>(qa[s]);
-            C a1[VEC];
-            step(tu, G::LDU, g.r1_u, g.r1xm_u, g.r1xp_u, g.r1vec, q1[s], q1[s + 1], q1[s + 2],
-                 upd1, a1);
-            to_storage<P, VEC>(a1);
 #pragma unroll
             for (int v = 0; v < VEC; ++v) tcur[g.own_a + v * TXL] = qa[s][v];
-            // a column element writes its one node; a thread without an
-            // element writes the sink slot
-            tcur[g.r1_a] = a1[0];
-            if (g.r1vec) {
+            // the inner-ring element, in the threads that hold one (all the
+            // lanes of a wavefront agree, but for one wavefront of the block)
+            if (g.r1on) {
+                C a1[VEC];
+                step(tu, G::LDU, g.r1_u, g.r1xm_u, g.r1xp_u, g.r1vec, q1[s], q1[s + 1],
+                     q1[s + 2], upd1, a1);
+                to_storage<P, VEC>(a1);
+                tcur[g.r1_a] = a1[0];  // a column element writes its one node
+                if (g.r1vec) {
 #pragma unroll
-                for (int v = 1; v < VEC; ++v) tcur[g.r1_a + v * TXL] = a1[v];
+                    for (int v = 1; v < VEC; ++v) tcur[g.r1_a + v * TXL] = a1[v];
+                }
             }
             // u^(t+2)(ka-1): its plane of u^(t+1) was staged last iteration
             if (s >= 2) {

@@ -157,16 +157,18 @@ __device__ __forceinline__ void vk_tile_sweep2(const typename P::S *__restrict__
             // u^(t+1)(ka) at the own nodes and the inner-ring element
             step(tu, G::LDU, g.own_u, g.xm_u, g.xp_u, kcur, g.own_u, g.xm_u, g.xp_u, true, qc[s],
                  qc[s + 1], qc[s + 2], qk[s], qk[s + 1], qk[s + 2], qf[s], upd, qa[s]);
-            C a1[VEC];
-            step(tu, G::LDU, g.r1_u, g.r1xm_u, g.r1xp_u, kcur, g.r1_u, g.r1xm_u, g.r1xp_u,
-                 g.r1vec, q1[s], q1[s + 1], q1[s + 2], q1k[s], q1k[s + 1], q1k[s + 2], q1f[s],
-                 upd1, a1);
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acur[g.own_a + v * TXL] = qa[s][v];
-            acur[g.r1_a] = a1[0];
-            if (g.r1vec) {
+            if (g.r1on) {  // the inner-ring element, in the threads that hold one
+                C a1[VEC];
+                step(tu, G::LDU, g.r1_u, g.r1xm_u, g.r1xp_u, kcur, g.r1_u, g.r1xm_u, g.r1xp_u,
+                     g.r1vec, q1[s], q1[s + 1], q1[s + 2], q1k[s], q1k[s + 1], q1k[s + 2],
+                     q1f[s], upd1, a1);
+                acur[g.r1_a] = a1[0];
+                if (g.r1vec) {
 #pragma unroll
-                for (int v = 1; v < VEC; ++v) acur[g.r1_a + v * TXL] = a1[v];
+                    for (int v = 1; v < VEC; ++v) acur[g.r1_a + v * TXL] = a1[v];
+                }
             }
             // u^(t+2)(ka-1): u^(t+1) and kappa of that plane were staged in
             // the last iteration
