@@ -23,7 +23,7 @@
 //
 // Output planes come in sub-blocks of exactly ZB planes, fully unrolled (ZB
 // + 2 planes of u^(t+1), ZB + 4 of u^t), the last one shifted back to end at
-// ke; runs shorter than ZB take sub-blocks of one plane.  Loads are never
+// ke; runs shorter than ZB take sub-blocks of two planes (and one).  Loads are never
 // predicated and are clamped into the array (rows, columns and planes); a
 // value read at a clamped address only reaches nodes that are not updated.
 // Nodes that are not updated (the Dirichlet layer, lanes past the last
@@ -343,7 +343,10 @@ __device__ __forceinline__ void heat_tile_sweep2(const typename P::S *__restrict
             if (k1 == g.ke - ZB + 1) break;
         }
     } else {
-        for (int k = g.kb; k <= g.ke; ++k) block(k, std::integral_constant<int, 1>{});
+        // short runs (the Boundary planes): two planes at a time, then one
+        int k = g.kb;
+        for (; k + 1 <= g.ke; k += 2) block(k, std::integral_constant<int, 2>{});
+        if (k == g.ke) block(k, std::integral_constant<int, 1>{});
     }
 }
 

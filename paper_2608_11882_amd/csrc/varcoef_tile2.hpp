@@ -189,7 +189,10 @@ __device__ __forceinline__ void vk_tile_sweep2(const typename P::S *__restrict__
             if (k1 == g.ke - ZB + 1) break;
         }
     } else {
-        for (int k = g.kb; k <= g.ke; ++k) block(k, std::integral_constant<int, 1>{});
+        // short runs (the Boundary planes): two planes at a time, then one
+        int k = g.kb;
+        for (; k + 1 <= g.ke; k += 2) block(k, std::integral_constant<int, 2>{});
+        if (k == g.ke) block(k, std::integral_constant<int, 1>{});
     }
 }
 
