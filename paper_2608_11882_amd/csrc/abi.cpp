@@ -673,22 +673,26 @@ int cg_run_ir(const double *b, double *x, int nx, int ny, int nz, double tol, in
         int cur = 0, first = 1;
         while (h->state == 0 && h->iter < maxit) {
             const int batch = std::min(16, maxit - h->iter);
+            const int k0 = h->iter;
             for (int q = 0; q < batch; ++q) {
                 {
                     Timed tm(hc::K_CG32_DIRECTION, s, (first ? 8.0 : 12.0) * n);
-                    HC_TRY(hc::launch_cg_direction_f32(w, cur, first, nx, ny, nz, t32, d->sink, s),
+                    HC_TRY(hc::launch_cg_direction_f32(w, cur, first, k0 + q, nx, ny, nz, t32,
+                                                       d->sink, s),
                            "cg_direction (binary32) launch");
                     tm.done();
                 }
                 {
                     Timed tm(hc::K_CG32_UPDATE, s, 20.0 * n);
-                    HC_TRY(hc::launch_cg_update_f32(w, cur, nx, ny, nz, t32, d->sink, s),
+                    HC_TRY(hc::launch_cg_update_f32(w, cur, k0 + q, nx, ny, nz, t32, d->sink, s),
                            "cg_update (binary32) launch");
                     tm.done();
                 }
                 cur ^= 1;
                 first = 0;
             }
+            HC_TRY(hc::launch_cg_settle_f32(w, k0 + batch, nx, ny, nz, t32, s),
+                   "cg_settle (binary32) launch");
             if ((rc = read_scalars())) return rc;
         }
         ++outer;
@@ -797,22 +801,25 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         }
         if (h->iter >= maxit) break;
         const int batch = std::min(kBatch, maxit - h->iter);
+        const int k0 = h->iter;
         for (int q = 0; q < batch; ++q) {
             {
                 Timed tm(hc::K_CG_DIRECTION, s, (first ? 16.0 : 24.0) * n);
-                HC_TRY(hc::launch_cg_direction(w, cur, first, nx, ny, nz, til, d->sink, s),
+                HC_TRY(hc::launch_cg_direction(w, cur, first, k0 + q, nx, ny, nz, til, d->sink,
+                                               s),
                        "cg_direction launch");
                 tm.done();
             }
             {
                 Timed tm(hc::K_CG_UPDATE, s, 40.0 * n);
-                HC_TRY(hc::launch_cg_update(x, w, cur, nx, ny, nz, til, d->sink, s),
+                HC_TRY(hc::launch_cg_update(x, w, cur, k0 + q, nx, ny, nz, til, d->sink, s),
                        "cg_update launch");
                 tm.done();
             }
             cur ^= 1;
             first = 0;
         }
+        HC_TRY(hc::launch_cg_settle(w, k0 + batch, nx, ny, nz, til, s), "cg_settle launch");
         if ((rc = read_scalars())) return rc;
     }
     if (!true_done) {

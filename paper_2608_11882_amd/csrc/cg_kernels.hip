@@ -25,9 +25,19 @@
 // full-depth z-blocks are unrolled so that loads stay in flight.
 //
 // Reductions are deterministic: every block reduces its own partial in a
-// fixed tree; the last block to arrive (arrival ticket) adds the partials
-// in index order and computes the scalars on the device, so no iteration
-// needs the host, which only polls the convergence state between batches.
+// fixed tree and stores it with a plain store.  The iteration's two
+// reductions are finished by the kernel that needs them: every block of the
+// next kernel adds the previous kernel's partials in index order with the
+// same tree (so all blocks hold the same bits), computes alpha or beta and
+// the convergence test itself, and block 0 records the scalars.  A kernel
+// boundary on one stream orders every store before every later load, so no
+// fence and no arrival counter is needed inside the iteration: on gfx950 an
+// agent-scope release writes back the XCD's L2 and serializes per block,
+// which cost more than the sweep itself at a few thousand blocks.  No
+// iteration needs the host, which only polls the convergence state between
+// batches (after a one-block kernel that finishes the last reduction).  The
+// residual kernels, run once per solve or restart, keep a last-block
+// arrival ticket.
 
 #include "hc_internal.hpp"
 
@@ -328,6 +338,18 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
+// block_sum with the result in every thread.
+template <int NT>
+__device__ __forceinline__ double block_sum_all(double v) {
+    __shared__ double total;
+    const double s = block_sum<NT>(v);
+    if (threadIdx.x == 0) total = s;
+    __syncthreads();
+    const double t = total;
+    __syncthreads();
+    return t;
+}
+
 __device__ __forceinline__ void store_agent(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -337,6 +359,11 @@ __device__ __forceinline__ double load_agent(const double *p) {
 __device__ __forceinline__ int load_state(const CGScalars *sc) {
     return __hip_atomic_load(&sc->state, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+}
+// Block 0 of a kernel may end the solve while later blocks of the same
+// kernel read the state at their start; they would all end it alike.
+__device__ __forceinline__ void store_state(CGScalars *sc, int v) {
+    __hip_atomic_store(&sc->state, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Publish this block's partials; true in the block that arrives last, after
@@ -363,6 +390,75 @@ __device__ __forceinline__ double gather(const double *partial, int nsum, int q)
     for (int b = threadIdx.x; b < (int)gridDim.x; b += NT)
         t += load_agent(&partial[(long long)b * nsum + q]);
     return block_sum<NT>(t);
+}
+
+// The same fixed-order sum of the nb partials a previous kernel stored,
+// taken in every block of a later one (result in every thread).
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double *part, int nb) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nb; b += NT) t += part[b];
+    return block_sum_all<NT>(t);
+}
+
+// Iteration k's direction scalars.  On the first iteration of a (re)start
+// rho_k is the residual kernel's r.r and beta is 0; otherwise rho_k is the
+// sum of the last update's partials (part_u), tested here for convergence
+// and finiteness, and beta = rho_k / rho_(k-1).  rho_k goes to slot k&1 for
+// the update and the next direction.  False when the solve is over.
+template <int NT>
+__device__ __forceinline__ bool direction_scalars(CGScalars *sc, const double *part_u, int nb,
+                                                  int k, int first, double *beta) {
+    if (load_state(sc) != 0) return false;
+    if (first) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->rslot[k & 1] = sc->rho;
+        *beta = 0.0;
+        return true;
+    }
+    const double rho = sum_partials<NT>(part_u, nb);
+    const double rho_old = sc->rslot[(k + 1) & 1];
+    int state = 0;
+    if (!isfinite(rho))
+        state = -7;
+    else if (sqrt(rho) <= sc->thresh)
+        state = 1;
+    const double b = rho / rho_old;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rslot[k & 1] = rho;
+        sc->rho = rho;
+        if (state == 0) sc->beta = b;
+        if (state != 0) store_state(sc, state);
+    }
+    *beta = b;
+    return state == 0;
+}
+
+// Iteration k's step length alpha = rho_k / (p'.Ap'), p'.Ap' the sum of the
+// direction's partials (part_d); breakdown (<= 0) and non-finite values end
+// the solve.  Counts the iteration (iter = k + 1) when it goes on.
+template <int NT>
+__device__ __forceinline__ bool update_scalars(CGScalars *sc, const double *part_d, int nb,
+                                               int k, double *alpha) {
+    if (load_state(sc) != 0) return false;
+    const double pap = sum_partials<NT>(part_d, nb);
+    const double rho = sc->rslot[k & 1];
+    int state = 0;
+    if (!isfinite(pap))
+        state = -7;
+    else if (pap <= 0.0)
+        state = -6;
+    const double a = rho / pap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pap = pap;
+        if (state == 0) {
+            sc->alpha = a;
+            sc->iter = k + 1;
+        } else {
+            store_state(sc, state);
+        }
+    }
+    *alpha = a;
+    return state == 0;
 }
 
 __global__ __launch_bounds__(64) void cg_init(CGScalars *sc, double tol, double inner_tol,
@@ -623,59 +719,49 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_ir_residual(
     }
 }
 
+// Iteration k (k = iterations completed before it).  partial: the
+// direction's partials at [0, nb), the update's at [nb, 2 nb).
 template <class T, int VEC, int WX, int BY, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void cg_direction(
     const T *__restrict__ r, const T *__restrict__ pold, T *__restrict__ pnew, double *partial,
-    CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int first) {
+    CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int first, int k) {
     constexpr int NT = 64 * WX * BY;
-    if (load_state(sc) != 0) return;  // converged or failed: nothing to do
+    const int nb = (int)gridDim.x;
+    double beta;
+    if (!direction_scalars<NT>(sc, partial + nb, nb, k, first, &beta)) return;
     const long long plane = (long long)nx * ny;
-    DirectionField<T> f{r, first ? r : pold, plane, first ? T(0) : (T)sc->beta, first};
+    DirectionField<T> f{r, first ? r : pold, plane, first ? T(0) : (T)beta, first};
     DirectionEpi<T, VEC> epi{pnew, plane};
     box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
-    double v[1];
-    v[0] = block_sum<NT>(epi.acc);
-    if (arrive(sc, partial, 1, v)) {
-        const double pap = gather<NT>(partial, 1, 0);
-        if (threadIdx.x == 0) {
-            sc->pap = pap;
-            if (!isfinite(pap))
-                sc->state = -7;
-            else if (pap <= 0.0)
-                sc->state = -6;
-            else
-                sc->alpha = sc->rho / pap;
-            sc->ticket = 0u;
-        }
-    }
+    const double v = block_sum<NT>(epi.acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
 template <class T, int VEC, int WX, int BY, int ZB>
 __global__ __launch_bounds__(64 * WX * BY) void cg_update(
     T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, double *partial,
-    CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink) {
+    CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int k) {
     constexpr int NT = 64 * WX * BY;
-    if (load_state(sc) != 0) return;
+    const int nb = (int)gridDim.x;
+    double alpha;
+    if (!update_scalars<NT>(sc, partial, nb, k, &alpha)) return;
     const long long plane = (long long)nx * ny;
     PlainField<T> f{p, plane};
-    UpdateEpi<T, VEC> epi{x, r, plane, (T)sc->alpha};
+    UpdateEpi<T, VEC> epi{x, r, plane, (T)alpha};
     box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
-    double v[1];
-    v[0] = block_sum<NT>(epi.acc);
-    if (arrive(sc, partial, 1, v)) {
-        const double rho_new = gather<NT>(partial, 1, 0);
-        if (threadIdx.x == 0) {
-            sc->iter += 1;
-            if (!isfinite(rho_new)) {
-                sc->state = -7;
-            } else {
-                if (sqrt(rho_new) <= sc->thresh) sc->state = 1;
-                sc->beta = rho_new / sc->rho;
-                sc->rho = rho_new;
-            }
-            sc->ticket = 0u;
-        }
-    }
+    const double v = block_sum<NT>(epi.acc);
+    if (threadIdx.x == 0) partial[nb + blockIdx.x] = v;
+}
+
+// One block of the same thread count: finish the last update's reduction
+// (the next direction kernel's scalars for iteration k) so that the host
+// sees the convergence state.  The direction kernel repeats it with the
+// same result.
+template <int NT>
+__global__ __launch_bounds__(NT) void cg_settle(CGScalars *sc, const double *partial, int nb,
+                                                int k) {
+    double beta;
+    (void)direction_scalars<NT>(sc, partial + nb, nb, k, 0, &beta);
 }
 
 template <class T, int VEC, int WX, int BY, int ZB>
@@ -798,6 +884,7 @@ CGWorkF32 cg_ir_work_carve(void *base, int nx, int ny, int nz) {
         const long long nb = cg_blocks(nx, ny, nz, t);                            \
         if (nb <= 0 || nb > INT_MAX) return hipErrorInvalidConfiguration;         \
         const dim3 grid((unsigned)nb), block(64 * t.wx * t.by);                   \
+        (void)grid;                                                               \
         const int key = HC_CG_KEY(t.vec, t.wx, t.by, t.zdepth);                   \
         bool done = false;                                                        \
         LIST(HC_CG_ONE_##KER)                                                     \
@@ -822,13 +909,18 @@ CGWorkF32 cg_ir_work_carve(void *base, int nx, int ny, int nz) {
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
         cg_direction<ELEM, V, W, B, Z><<<grid, block, 0, s>>>(                    \
             w.r, w.p[cur], w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd,      \
-            sink, first);                                                         \
+            sink, first, k);                                                      \
         done = true;                                                              \
     }
 #define HC_CG_ONE_UPD(V, W, B, Z)                                                 \
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
         cg_update<ELEM, V, W, B, Z><<<grid, block, 0, s>>>(                       \
-            x, w.r, w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd, sink);      \
+            x, w.r, w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd, sink, k);   \
+        done = true;                                                              \
+    }
+#define HC_CG_ONE_SETTLE(V, W, B, Z)                                              \
+    if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
+        cg_settle<64 * W * B><<<1, block, 0, s>>>(w.sc, w.partial, (int)nb, k);   \
         done = true;                                                              \
     }
 #define HC_CG_ONE_LAP(V, W, B, Z)                                                 \
@@ -857,15 +949,20 @@ hipError_t launch_cg_ir_residual(const double *b, const double *x, const CGWorkF
 }
 
 #define ELEM double
-hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int nx,
+hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int k, int nx,
                                int ny, int nz, const CGTiling &t, double *sink,
                                hipStream_t s) {
     HC_CG_DISPATCH(HC_CG_SHAPES, DIR);
 }
 
-hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx, int ny,
+hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int nx, int ny,
                             int nz, const CGTiling &t, double *sink, hipStream_t s) {
     HC_CG_DISPATCH(HC_CG_SHAPES, UPD);
+}
+
+hipError_t launch_cg_settle(const CGWork &w, int k, int nx, int ny, int nz, const CGTiling &t,
+                            hipStream_t s) {
+    HC_CG_DISPATCH(HC_CG_SHAPES, SETTLE);
 }
 
 hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
@@ -875,15 +972,21 @@ hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
 #undef ELEM
 
 #define ELEM float
-hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int nx, int ny,
-                                   int nz, const CGTiling &t, double *sink, hipStream_t s) {
+hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int k, int nx,
+                                   int ny, int nz, const CGTiling &t, double *sink,
+                                   hipStream_t s) {
     HC_CG_DISPATCH(HC_CG_SHAPES_F32, DIR);
 }
 
-hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int nx, int ny, int nz,
+hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int k, int nx, int ny, int nz,
                                 const CGTiling &t, double *sink, hipStream_t s) {
     float *const x = w.d;
     HC_CG_DISPATCH(HC_CG_SHAPES_F32, UPD);
+}
+
+hipError_t launch_cg_settle_f32(const CGWorkF32 &w, int k, int nx, int ny, int nz,
+                                const CGTiling &t, hipStream_t s) {
+    HC_CG_DISPATCH(HC_CG_SHAPES_F32, SETTLE);
 }
 
 hipError_t launch_lap7_f32(const float *x, float *y, int nx, int ny, int nz, const CGTiling &t,

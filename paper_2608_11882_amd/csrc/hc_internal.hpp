@@ -171,9 +171,10 @@ struct CGScalars {
     double rtrue2;    // |b - A x|^2 of the last true-residual pass
     double inner_tol; // refinement: relative reduction of each inner solve
     double floor_frac;// refinement: inner solves stop at floor_frac * tol ||b||
+    double rslot[2];  // r.r of iteration k in slot k & 1 (device use)
     int iter;         // completed iterations
     int state;        // 0 running, 1 converged, -6 breakdown, -7 non-finite
-    unsigned ticket;  // arrival counter of the reductions (0 between kernels)
+    unsigned ticket;  // arrival counter of the residual kernels (0 between kernels)
     unsigned pad;
 };
 
@@ -223,11 +224,17 @@ constexpr int kSinkDoubles = 2048;
 hipError_t launch_cg_residual(const double *b, const double *x, const CGWork &w,
                               int nx, int ny, int nz, int store_r,
                               const CGTiling &t, double *sink, hipStream_t s);
-hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int nx,
+// Iteration k (iterations completed before it) of the direction and update
+// kernels; after a batch, launch_cg_settle(k) with k the next iteration
+// finishes the last update's reduction so that the scalars show whether the
+// solve has converged.
+hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int k, int nx,
                                int ny, int nz, const CGTiling &t, double *sink,
                                hipStream_t s);
-hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int nx, int ny,
+hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int nx, int ny,
                             int nz, const CGTiling &t, double *sink, hipStream_t s);
+hipError_t launch_cg_settle(const CGWork &w, int k, int nx, int ny, int nz, const CGTiling &t,
+                            hipStream_t s);
 hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
                            const CGTiling &t, double *sink, hipStream_t s);
 // refinement kernels (t from the binary32 shape list, except the residual,
@@ -235,10 +242,13 @@ hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
 hipError_t launch_cg_ir_residual(const double *b, const double *x, const CGWorkF32 &w, int nx,
                                  int ny, int nz, const CGTiling &t, double *sink,
                                  hipStream_t s);
-hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int nx, int ny,
-                                   int nz, const CGTiling &t, double *sink, hipStream_t s);
-hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int nx, int ny, int nz,
+hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int k, int nx,
+                                   int ny, int nz, const CGTiling &t, double *sink,
+                                   hipStream_t s);
+hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int k, int nx, int ny, int nz,
                                 const CGTiling &t, double *sink, hipStream_t s);
+hipError_t launch_cg_settle_f32(const CGWorkF32 &w, int k, int nx, int ny, int nz,
+                                const CGTiling &t, hipStream_t s);
 hipError_t launch_lap7_f32(const float *x, float *y, int nx, int ny, int nz, const CGTiling &t,
                            double *sink, hipStream_t s);
 hipError_t launch_ir_axpy(double *x, const float *d, long long n, hipStream_t s);
