@@ -343,7 +343,7 @@ int hc_heat_tiling_for(int dtype, int nx, const void *u, const void *u_new,
  * cg_kernels.hip (HC_CG_SHAPES); others return HC_EINVAL.  Results are
  * deterministic for a given shape; the summation tree of the dot products
  * (and so the last bits of the iterates) depends on it.  Default: vec 2,
- * wx 2, by 8, zdepth 32, xcd 8.
+ * wx 1, by 4, zdepth 16, xcd 8.
  */
 int hc_cg_set_tiling(int vec, int wx, int by, int zdepth, int xcd);
 void hc_cg_get_tiling(int *vec, int *wx, int *by, int *zdepth, int *xcd);

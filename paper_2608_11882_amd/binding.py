@@ -445,10 +445,10 @@ def vk2_tiling_for(u, u_new, kappa, rhs) -> dict:
     return dict(zip(_TILE_KEYS, (x.value for x in v)))
 
 
-DEFAULT_CG_TILING = dict(vec=2, wx=2, by=8, zdepth=32, xcd=8)
+DEFAULT_CG_TILING = dict(vec=2, wx=1, by=4, zdepth=16, xcd=8)
 
 
-def set_cg_tiling(vec: int = 2, wx: int = 2, by: int = 8, zdepth: int = 32, xcd: int = 8) -> None:
+def set_cg_tiling(vec: int = 2, wx: int = 1, by: int = 4, zdepth: int = 16, xcd: int = 8) -> None:
     """Tile shape of the CG kernels and of lap7_apply."""
     _check(load().hc_cg_set_tiling(int(vec), int(wx), int(by), int(zdepth), int(xcd)))
 

@@ -220,7 +220,10 @@ int current_time_block() {
     return g_time_block;
 }
 
-hc::CGTiling g_cg_tiling = {2, 2, 8, 32, 8};
+// Tile shape of the binary64 CG kernels: 256 x 4 tiles of 2-node lanes,
+// z-blocks of 16 planes (2048 blocks at 256^3; the fastest built shape
+// there on MI355X).
+hc::CGTiling g_cg_tiling = {2, 1, 4, 16, 8};
 
 // Tile shape of the refinement's binary32 inner solve: 256 x 8 tiles of
 // 4-node (16-byte) lanes, z-blocks of 32 planes (the fastest built shape at
