@@ -298,7 +298,7 @@ def ir_section(hc, b, xs, it64, ms64):
     }
 
 
-def batch_section(hc, dev):
+def batch_section(hc, dev, sequential_solves=True, shape=None):
     """The batched configuration, outside the timed region: 256 FP32
     problems with edges U{32..192} per axis, r ~ U[0.05, 0.16], U[0,1]
     fields, 200 steps.  The batch is autotuned on its own states, then timed
@@ -332,24 +332,17 @@ def batch_section(hc, dev):
             out.append(e0.elapsed_time(e1))
         return statistics.median(out)
 
-    log("batch: autotune")
-    tuned_ms = batch.autotune(u0, trial_steps=4)
+    if shape is None:
+        log("batch: autotune")
+        tuned_ms = batch.autotune(u0, trial_steps=4)
+    else:
+        batch.set_tiling(*shape)
+        tuned_ms = float("nan")
     # a pass moves one step's bytes; two steps per pass make steps / 2 passes
     spp = batch.steps_per_pass()
     algo = (steps // spp + steps % spp) * batch.step_bytes
     ms_graph = timed(lambda: batch.step(u, un, steps, graph=True))
     ms_direct = timed(lambda: batch.step(u, un, steps, graph=False))
-    log("batch: sequential single-problem solves")
-    # each problem on its own, in a contiguous array of its own (a packed
-    # problem's rows are padded, so its view in the batch is strided)
-    seq_u = [torch.from_numpy(f).to(dev) for f in fields]
-    seq_un = [torch.empty_like(a) for a in seq_u]
-
-    def sequential(mode):
-        for p, (a, b) in enumerate(zip(seq_u, seq_un)):
-            hc.heat_step(a, b, float(rs[p]), steps, mode=mode)
-    ms_plain = timed(lambda: sequential("plain"), reps=1)
-    ms_fused = timed(lambda: sequential("fused"), reps=1)
     res = {
         "problems": len(dims),
         "steps": steps,
@@ -357,8 +350,8 @@ def batch_section(hc, dev):
         "algo_bytes_per_step": batch.step_bytes,
         "tiling": batch.get_tiling(),
         "steps_per_pass": spp,
-        "autotune_ms_per_step": round(tuned_ms, 4),
-        "autotune_candidates": len(batch.tune_results()),
+        "autotune_ms_per_step": round(tuned_ms, 4) if shape is None else None,
+        "autotune_candidates": len(batch.tune_results()) if shape is None else 0,
         "graph": {"ms": round(ms_graph, 3), "glups": round(lups / (ms_graph / 1e3) / 1e9, 2),
                   "algo_hbm_gbs": round(algo / (ms_graph / 1e3) / 1e9, 1),
                   "pct_of_hbm_peak": round(100 * algo / (ms_graph / 1e3) / 1e9 / PEAK_HBM_GBS, 2),
@@ -366,12 +359,24 @@ def batch_section(hc, dev):
                       round(steps * batch.step_bytes / (ms_graph / 1e3) / 1e9, 1)},
         "direct_launches": {"ms": round(ms_direct, 3),
                             "glups": round(lups / (ms_direct / 1e3) / 1e9, 2)},
-        "sequential_plain": {"ms": round(ms_plain, 3),
-                             "glups": round(lups / (ms_plain / 1e3) / 1e9, 2)},
-        "sequential_fused": {"ms": round(ms_fused, 3),
-                             "glups": round(lups / (ms_fused / 1e3) / 1e9, 2)},
     }
-    res["speedup_vs_sequential_plain"] = round(ms_plain / ms_graph, 2)
+    if sequential_solves:
+        log("batch: sequential single-problem solves")
+        # each problem on its own, in a contiguous array of its own (a packed
+        # problem's rows are padded, so its view in the batch is strided)
+        seq_u = [torch.from_numpy(f).to(dev) for f in fields]
+        seq_un = [torch.empty_like(a) for a in seq_u]
+
+        def sequential(mode):
+            for p, (a, b) in enumerate(zip(seq_u, seq_un)):
+                hc.heat_step(a, b, float(rs[p]), steps, mode=mode)
+        ms_plain = timed(lambda: sequential("plain"), reps=1)
+        ms_fused = timed(lambda: sequential("fused"), reps=1)
+        res["sequential_plain"] = {"ms": round(ms_plain, 3),
+                                   "glups": round(lups / (ms_plain / 1e3) / 1e9, 2)}
+        res["sequential_fused"] = {"ms": round(ms_fused, 3),
+                                   "glups": round(lups / (ms_fused / 1e3) / 1e9, 2)}
+        res["speedup_vs_sequential_plain"] = round(ms_plain / ms_graph, 2)
     batch.close()
     return res
 
@@ -483,6 +488,13 @@ def main():
                     help="CPU time budget of the oracle baseline (0 skips it)")
     ap.add_argument("--heat-steps", type=int, default=1000, help=argparse.SUPPRESS)
     ap.add_argument("--precision", type=int, default=1, help=argparse.SUPPRESS)
+    # "batch": only the batched configuration; "batch-kernels": the same
+    # without the 256 sequential single-problem solves (for counter passes)
+    ap.add_argument("--section", choices=("all", "batch", "batch-kernels"), default="all",
+                    help=argparse.SUPPRESS)
+    # the batch's shape (vec,threads,zdepth,pf,xcd,width_class,grid,item_depth)
+    # instead of the autotuner's pick, for those sections
+    ap.add_argument("--batch-shape", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
@@ -499,6 +511,15 @@ def main():
     hc.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.section != "all":
+        shape = None
+        if args.batch_shape:
+            shape = tuple(int(v) for v in args.batch_shape.split(","))
+            if len(shape) != 8:
+                ap.error("--batch-shape takes 8 comma-separated integers")
+        res = batch_section(hc, dev, sequential_solves=args.section == "batch", shape=shape)
+        print(json.dumps({"batch_256_f32": res}), flush=True)
+        return
 
     hcfg, ccfg = inputs.HEAT_LARGE, inputs.CG_LARGE
     n, r, nsteps = hcfg["n"], hcfg["r"], args.heat_steps

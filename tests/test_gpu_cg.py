@@ -203,3 +203,44 @@ def test_every_cg_shape_spmv_bitwise_and_converges(gpu):
                 assert st == 0 and rel <= 1e-10 and abs(it - ref.iters) <= 3, (shape, xcd, it)
     finally:
         gpu.set_cg_tiling()
+
+
+def test_non_finite_data_is_reported(gpu):
+    """A NaN in b or an infinite initial guess ends the solve with
+    HC_ENONFINITE (the residual kernel's test), for plain CG and for the
+    refinement; the library stays usable afterwards."""
+    n = 24
+    note("cg non-finite b / x0")
+    b = oracle.lap7_apply(inputs.manufactured_solution(n, seed=12))
+    bad = b.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(gpu.HeatCGError) as e:
+        gpu_cg(gpu, bad, 1e-10, 100)
+    assert e.value.code == -7
+    x0 = np.zeros_like(b)
+    x0[1, 2, 3] = np.inf
+    with pytest.raises(gpu.HeatCGError) as e:
+        gpu_cg(gpu, b, 1e-10, 100, x0=x0)
+    assert e.value.code == -7
+    bt = torch.from_numpy(bad).cuda()
+    with pytest.raises(gpu.HeatCGError) as e:
+        gpu.cg_solve_ir(bt, torch.zeros_like(bt), 1e-10, 100)
+    assert e.value.code == -7
+    st, it, rel, _ = gpu_cg(gpu, b, 1e-10, 2000)
+    assert st == 0 and rel <= 1e-10
+
+
+@pytest.mark.parametrize("maxit", [15, 16, 17, 33])
+def test_iteration_budget_across_host_polls(gpu, maxit):
+    """The host polls the device scalars every 16 iterations; a budget that
+    ends just before, at or after a poll stops at exactly maxit, and the
+    iterate equals the one reached by an unlimited run after as many
+    iterations (the oracle's, within the summation-order tolerance)."""
+    n = 40
+    note("cg maxit=%d" % maxit)
+    b = oracle.lap7_apply(inputs.manufactured_solution(n, seed=13))
+    st, it, rel, x = gpu_cg(gpu, b, 1e-12, maxit)
+    assert st == 1 and it == maxit
+    ref = oracle.cg(b, 1e-30, maxit)
+    assert ref.iters == maxit
+    assert np.max(np.abs(x - ref.x)) <= 1e-9 * np.max(np.abs(ref.x))
