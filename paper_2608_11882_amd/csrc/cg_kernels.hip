@@ -361,9 +361,17 @@ __device__ __forceinline__ int load_state(const CGScalars *sc) {
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 // Block 0 of a kernel may end the solve while later blocks of the same
-// kernel read the state at their start; they would all end it alike.
+// kernel start (every block would end it alike from the same partials).
 __device__ __forceinline__ void store_state(CGScalars *sc, int v) {
     __hip_atomic_store(&sc->state, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The state read once per block, so that all of its wavefronts take the
+// same branch even when block 0 changes it meanwhile.
+__device__ __forceinline__ int block_state(const CGScalars *sc) {
+    __shared__ int st;
+    if (threadIdx.x == 0) st = load_state(sc);
+    __syncthreads();
+    return st;
 }
 
 // Publish this block's partials; true in the block that arrives last, after
@@ -409,7 +417,7 @@ __device__ __forceinline__ double sum_partials(const double *part, int nb) {
 template <int NT>
 __device__ __forceinline__ bool direction_scalars(CGScalars *sc, const double *part_u, int nb,
                                                   int k, int first, double *beta) {
-    if (load_state(sc) != 0) return false;
+    if (block_state(sc) != 0) return false;
     if (first) {
         if (blockIdx.x == 0 && threadIdx.x == 0) sc->rslot[k & 1] = sc->rho;
         *beta = 0.0;
@@ -439,7 +447,7 @@ __device__ __forceinline__ bool direction_scalars(CGScalars *sc, const double *p
 template <int NT>
 __device__ __forceinline__ bool update_scalars(CGScalars *sc, const double *part_d, int nb,
                                                int k, double *alpha) {
-    if (load_state(sc) != 0) return false;
+    if (block_state(sc) != 0) return false;
     const double pap = sum_partials<NT>(part_d, nb);
     const double rho = sc->rslot[k & 1];
     int state = 0;
