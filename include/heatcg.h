@@ -265,8 +265,8 @@ int cg_solve(const double *b, double *x, int n, double tol, int maxit);
  * (work may be NULL: the library's own is used) and stream.
  *  work_bytes  >= cg_workspace_bytes(nx, ny, nz) when work != NULL.
  *  iters, true_relres  optional outputs (may be NULL).
- * Blocks until done (the convergence test reads 64 bytes per batch of
- * iterations back to the host).
+ * Blocks until done (the host reads the solver's scalars, about a hundred
+ * bytes, back once per batch of 16 iterations to test convergence).
  */
 int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol,
                 int maxit, void *work, size_t work_bytes, hc_stream_t stream,
