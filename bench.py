@@ -500,6 +500,14 @@ def main():
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    shape = None
+    if args.batch_shape:
+        try:
+            shape = tuple(int(v) for v in args.batch_shape.split(","))
+        except ValueError:
+            shape = ()
+        if len(shape) != 8:
+            ap.error("--batch-shape takes 8 comma-separated integers")
 
     import numpy as np
     import torch
@@ -512,11 +520,6 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.section != "all":
-        shape = None
-        if args.batch_shape:
-            shape = tuple(int(v) for v in args.batch_shape.split(","))
-            if len(shape) != 8:
-                ap.error("--batch-shape takes 8 comma-separated integers")
         res = batch_section(hc, dev, sequential_solves=args.section == "batch", shape=shape)
         print(json.dumps({"batch_256_f32": res}), flush=True)
         return

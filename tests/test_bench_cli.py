@@ -28,3 +28,12 @@ def test_traffic_records_match_the_kernel_sources():
         assert (bench.measured_traffic(tb) is not None) == (
             rec["kernel_source_sha256"] == bench.kernel_source_hash(bench.INTERIOR[tb][2]))
         assert rec["hbm_bytes_per_launch"] > 0.9 * rec["algorithmic_bytes_per_launch"]
+
+
+def test_batch_shape_is_checked_before_any_gpu_work():
+    for bad in ("4,512,16", "4,512,16,2,8,-1,0,x"):
+        res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--section",
+                              "batch-kernels", "--batch-shape", bad],
+                             capture_output=True, text=True, timeout=120)
+        assert res.returncode == 2
+        assert "--batch-shape takes 8" in res.stderr and res.stdout == ""
