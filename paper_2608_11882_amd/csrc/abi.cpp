@@ -1858,8 +1858,8 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
     const size_t bytes = (size_t)b->total * hc::dtype_bytes(b->dtype);
     if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // candidates: every built shape, with whole-column, 64-plane and
-    // zdepth-plane entries, one block per entry or a persistent grid
+    // candidates: every built shape, with whole-column, one-z-block and
+    // 64-plane entries, one block per entry or a persistent grid
     int ncu = 256;
     {
         hipDeviceProp_t prop;
@@ -1873,7 +1873,7 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
         // each problem's best-fitting width, with every order, run length
         // and grid; then every width for all problems, in one setting
         for (int x : {0, 8})
-            for (int dep : {0, 64})
+            for (int dep : {0, t.zdepth, 64})
                 for (int g : {0, 2 * ncu}) {
                     t.xcd = x;
                     t.cls = -1;
