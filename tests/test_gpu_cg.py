@@ -244,3 +244,30 @@ def test_iteration_budget_across_host_polls(gpu, maxit):
     ref = oracle.cg(b, 1e-30, maxit)
     assert ref.iters == maxit
     assert np.max(np.abs(x - ref.x)) <= 1e-9 * np.max(np.abs(ref.x))
+
+
+def test_workspace_contents_do_not_matter(gpu):
+    """Partial sums and scalar slots are written before they are read: a
+    caller workspace full of NaN bit patterns gives the same bits as a
+    zeroed one, for plain CG and for the refinement."""
+    n = 30
+    note("cg with a NaN-filled workspace")
+    b = torch.from_numpy(oracle.lap7_apply(inputs.manufactured_solution(n, seed=14))).cuda()
+    outs = []
+    for fill in (0, 0xFF):
+        work = torch.full((gpu.cg_workspace_bytes(n, n, n),), fill, dtype=torch.uint8,
+                          device="cuda")
+        x = torch.zeros_like(b)
+        st, it, rel = gpu.cg_solve(b, x, 1e-10, 2000, work=work)
+        assert st == 0 and rel <= 1e-10
+        outs.append((it, x.cpu()))
+    assert outs[0][0] == outs[1][0] and torch.equal(outs[0][1], outs[1][1])
+    outs = []
+    for fill in (0, 0xFF):
+        work = torch.full((gpu.cg_ir_workspace_bytes(n, n, n),), fill, dtype=torch.uint8,
+                          device="cuda")
+        x = torch.zeros_like(b)
+        st, it, outer, rel = gpu.cg_solve_ir(b, x, 1e-10, 2000, work=work)
+        assert st == 0 and rel <= 1e-10
+        outs.append((it, outer, x.cpu()))
+    assert outs[0][:2] == outs[1][:2] and torch.equal(outs[0][2], outs[1][2])
