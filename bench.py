@@ -304,7 +304,9 @@ def batch_section(hc, dev, sequential_solves=True, shape=None):
     fields, 200 steps.  The batch is autotuned on its own states, then timed
     as one captured graph of 200 persistent launches (median of 3), beside
     the same 200 steps as direct launches and 256 sequential single-problem
-    solves (plain one-thread-per-node launches, and the fused z-march)."""
+    solves (plain one-thread-per-node launches, and the fused z-march).
+    With `shape` the batch takes that setting instead of the autotuner's;
+    sequential_solves=False leaves out the sequential solves."""
     import numpy as np
     import torch
     from paper_2608_11882_amd import inputs
