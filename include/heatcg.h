@@ -263,10 +263,19 @@ int cg_solve(const double *b, double *x, int n, double tol, int maxit);
 /*
  * cg_solve_ex -- cg_solve on an nx x ny x nz box, with a caller workspace
  * (work may be NULL: the library's own is used) and stream.
+ *  work        NULL, or device memory of the current device, 256-byte
+ *              aligned (else HC_EINVAL: the solver's scalar block and
+ *              partial sums, some updated atomically, sit at multiples of
+ *              256 bytes from it), not overlapping b or x.
  *  work_bytes  >= cg_workspace_bytes(nx, ny, nz) when work != NULL.
  *  iters, true_relres  optional outputs (may be NULL).
  * Blocks until done (the host reads the solver's scalars, about a hundred
  * bytes, back once per batch of 16 iterations to test convergence).
+ * Solves on one device are serialized: the library's workspace and the
+ * host buffer the scalars are read into are shared per device, so a call
+ * holds a per-device lock until it returns (a second host thread's solve
+ * on the same device waits; solves on different devices run side by
+ * side).
  */
 int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol,
                 int maxit, void *work, size_t work_bytes, hc_stream_t stream,
@@ -372,7 +381,9 @@ const char *hc_strerror(int code);
  *  inner_tol  relative reduction of each inner solve, < 1; <= 0 selects
  *             1e-5.
  *  work       NULL (the library's cached workspace) or at least
- *             cg_ir_workspace_bytes(nx, ny, nz) bytes of device memory.
+ *             cg_ir_workspace_bytes(nx, ny, nz) bytes of device memory,
+ *             256-byte aligned (else HC_EINVAL).  Serialized per device
+ *             with the other solves, as cg_solve_ex.
  *  iters, outer, true_relres  optional outputs: inner iterations, outer
  *             steps, binary64 ||b - A x|| / ||b|| of the returned x.
  * Blocks until done.  Returns HC_OK, HC_ENOTCONV (maxit reached, or an

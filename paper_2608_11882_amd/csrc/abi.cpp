@@ -270,6 +270,9 @@ struct DevState {
     size_t cg_work_size = 0;
     hc::CGScalars *host_sc = nullptr;  // pinned
     double *sink = nullptr;  // store target of lanes outside a CG box
+    // Held for the whole of a CG solve: the library's workspace, host_sc
+    // and sink are shared by every solve on this device.
+    std::mutex cg_mu;
 };
 
 constexpr int kMaxDev = 64;
@@ -329,8 +332,10 @@ hipEvent_t pool_event() {
 // Brackets one launch with timing events while profiling is enabled.
 class Timed {
   public:
-    Timed(KernelKind kind, hipStream_t s, double bytes, long long launches = 1)
+    Timed(KernelKind kind, hipStream_t s, double bytes, long long launches = 1,
+          bool allowed = true)
         : kind_(kind), s_(s), bytes_(bytes), launches_(launches) {
+        if (!allowed) return;
         std::lock_guard<std::mutex> g(g_prof_mu);
         if (!g_prof_on) return;
         if (g_prof_seen[kind]++ % g_prof_every != 0) return;
@@ -741,14 +746,15 @@ int validate_heat(const void *u, const void *un, int nx, int ny, int nz, double 
     return HC_OK;
 }
 
+// The CG driver.  `sink` (kSinkDoubles doubles of device memory) takes the
+// stores of lanes outside the box; `h` (host memory) receives the device
+// scalars at every poll; `timing` allows the kernel timing of hc_prof_*.
 int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int maxit, void *work,
-           hipStream_t s, int *iters_out, double *relres_out) {
-    DevState *d = nullptr;
-    int rc = device_state(&d);
-    if (rc) return rc;
+           hipStream_t s, double *sink, hc::CGScalars *h, bool timing, int *iters_out,
+           double *relres_out) {
+    int rc = HC_OK;
     const hc::CGWork w = hc::cg_work_carve(work, nx, ny, nz);
     const hc::CGTiling til = cg_tiling_for(nx, b, x, w.r);
-    hc::CGScalars *h = d->host_sc;
     const double n = (double)nx * ny * nz;
 
     auto read_scalars = [&]() -> int {
@@ -757,8 +763,8 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         return HC_OK;
     };
     auto residual = [&](int store_r) -> int {
-        Timed tm(hc::K_CG_RESIDUAL, s, (store_r ? 24.0 : 16.0) * n);
-        HC_TRY(hc::launch_cg_residual(b, x, w, nx, ny, nz, store_r, til, d->sink, s),
+        Timed tm(hc::K_CG_RESIDUAL, s, (store_r ? 24.0 : 16.0) * n, 1, timing);
+        HC_TRY(hc::launch_cg_residual(b, x, w, nx, ny, nz, store_r, til, sink, s),
                "cg_residual launch");
         tm.done();
         return HC_OK;
@@ -807,15 +813,15 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         const int k0 = h->iter;
         for (int q = 0; q < batch; ++q) {
             {
-                Timed tm(hc::K_CG_DIRECTION, s, (first ? 16.0 : 24.0) * n);
-                HC_TRY(hc::launch_cg_direction(w, cur, first, k0 + q, nx, ny, nz, til, d->sink,
+                Timed tm(hc::K_CG_DIRECTION, s, (first ? 16.0 : 24.0) * n, 1, timing);
+                HC_TRY(hc::launch_cg_direction(w, cur, first, k0 + q, nx, ny, nz, til, sink,
                                                s),
                        "cg_direction launch");
                 tm.done();
             }
             {
-                Timed tm(hc::K_CG_UPDATE, s, 40.0 * n);
-                HC_TRY(hc::launch_cg_update(x, w, cur, k0 + q, nx, ny, nz, til, d->sink, s),
+                Timed tm(hc::K_CG_UPDATE, s, 40.0 * n, 1, timing);
+                HC_TRY(hc::launch_cg_update(x, w, cur, k0 + q, nx, ny, nz, til, sink, s),
                        "cg_update launch");
                 tm.done();
             }
@@ -1195,17 +1201,21 @@ size_t cg_workspace_bytes(int nx, int ny, int nz) {
 }
 
 // The caller's workspace (checked), or the library's cached one (grown to
-// `need` bytes on demand).
-int cg_workspace(const double *b, const double *x, size_t bytes, size_t need, void **work) {
+// `need` bytes on demand).  Called with d->cg_mu held.
+int cg_workspace(DevState *d, const double *b, const double *x, size_t bytes, size_t need,
+                 void **work) {
     int rc = HC_OK;
     if (*work) {
+        // the carve puts the scalar block and the partial sums (read and
+        // written with 8-byte accesses, some of them atomic) at multiples of
+        // 256 bytes from the base
+        if (reinterpret_cast<uintptr_t>(*work) % 256 != 0)
+            return fail(HC_EINVAL, "work must be 256-byte aligned");
         if ((rc = check_device_buffer(*work, need, "work"))) return rc;
         if (overlaps(*work, need, b, bytes) || overlaps(*work, need, x, bytes))
             return fail(HC_EALIAS, "workspace overlaps b or x");
         return HC_OK;
     }
-    DevState *d = nullptr;
-    if ((rc = device_state(&d))) return rc;
     std::lock_guard<std::mutex> g(g_dev_mu);
     if (d->cg_work_size < need) {
         if (d->cg_work) {
@@ -1245,10 +1255,14 @@ int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol, 
         return fail(HC_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
     if ((rc = check_device_buffer(b, bytes, "b"))) return rc;
     if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
-    if ((rc = cg_workspace(b, x, bytes, need, &work))) return rc;
+    DevState *d = nullptr;
+    if ((rc = device_state(&d))) return rc;
+    std::lock_guard<std::mutex> solve_lock(d->cg_mu);
+    if ((rc = cg_workspace(d, b, x, bytes, need, &work))) return rc;
     int it = 0;
     double rel = 0.0;
-    rc = cg_run(b, x, nx, ny, nz, tol, maxit, work, reinterpret_cast<hipStream_t>(stream), &it, &rel);
+    rc = cg_run(b, x, nx, ny, nz, tol, maxit, work, reinterpret_cast<hipStream_t>(stream),
+                d->sink, d->host_sc, true, &it, &rel);
     g_cg_iters = it;
     g_cg_relres = rel;
     if (iters) *iters = it;
@@ -1289,7 +1303,10 @@ int cg_solve_ir(const double *b, double *x, int nx, int ny, int nz, double tol, 
         return fail(HC_EINVAL, "workspace of %zu bytes, %zu needed", work_bytes, need);
     if ((rc = check_device_buffer(b, bytes, "b"))) return rc;
     if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
-    if ((rc = cg_workspace(b, x, bytes, need, &work))) return rc;
+    DevState *d = nullptr;
+    if ((rc = device_state(&d))) return rc;
+    std::lock_guard<std::mutex> solve_lock(d->cg_mu);
+    if ((rc = cg_workspace(d, b, x, bytes, need, &work))) return rc;
     int it = 0, out = 0;
     double rel = 0.0;
     rc = cg_run_ir(b, x, nx, ny, nz, tol, maxit, inner_tol, work,

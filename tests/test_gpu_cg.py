@@ -146,27 +146,104 @@ def test_caller_workspace_and_plain_entry_point(gpu):
     assert torch.equal(xt, x2)
 
 
-def test_large_config_converges_to_manufactured_solution(gpu):
+def check_against_oracle(x, it, rel, ref, xs, b, tol, kappa):
+    """The acceptance rule for CG parity (several results are correct)."""
+    assert ref.status == 0 and ref.relres_true <= tol
+    assert rel <= tol
+    assert abs(it - ref.iters) <= max(3, int(0.01 * ref.iters)), (it, ref.iters)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    err_ref = np.linalg.norm(ref.x - xs) / np.linalg.norm(xs)
+    assert err <= kappa * tol, (err, kappa * tol)
+    assert err <= 10 * err_ref + 1e-13, (err, err_ref)
+    rel_cpu = np.linalg.norm(b - oracle.lap7_apply(x)) / np.linalg.norm(b)
+    assert abs(rel_cpu - rel) <= 1e-3 * rel + 1e-16
+    return err, err_ref
+
+
+def test_large_config_against_oracle(gpu):
+    """The full-size system (256^3, x* ~ U[-1, 1] with seed 4, b = A x*, tol
+    1e-10) solved on the GPU and by the oracle: same acceptance rule as the
+    small boxes.  The default tile launches 2048 blocks here, so every block
+    folds eight partial sums per thread when it finishes a reduction."""
     cfg = inputs.CG_LARGE
     n = cfg["n"]
-    note("cg 256^3 tol 1e-10 (full size)")
+    note("cg 256^3 tol 1e-10 (full size) against the oracle")
     xs = inputs.manufactured_solution(n, seed=cfg["seed"])
-    xst = torch.from_numpy(xs).cuda()
-    bt = torch.empty_like(xst)
-    gpu.lap7_apply(xst, bt)
-    xt = torch.zeros_like(bt)
-    st, it, rel = gpu.cg_solve(bt, xt, cfg["tol"], cfg["maxit"])
-    assert st == 0 and rel <= cfg["tol"]
-    lam_min = 12 * np.sin(np.pi / (2 * (n + 1))) ** 2
-    kappa = (12 - lam_min) / lam_min
-    err = (torch.linalg.norm(xt - xst) / torch.linalg.norm(xst)).item()
-    assert err <= kappa * cfg["tol"]
-    # iteration count: sqrt(kappa) growth from smaller boxes; a few hundred to 2000
-    assert 300 < it < 2000, it
-    # b was built on the GPU: check a sample of it against the oracle's operator
-    b_cpu = bt.cpu().numpy()
-    sub = oracle.lap7_apply(xs[:40])  # planes 0..38 only see planes 0..39
-    assert np.array_equal(b_cpu[:39], sub[:39])
+    b = oracle.lap7_apply(xs)
+    st, it, rel, x = gpu_cg(gpu, b, cfg["tol"], cfg["maxit"])
+    assert st == 0
+    note("cg 256^3: GPU %d iterations, relres %.3g; running the oracle" % (it, rel))
+    ref = oracle.cg(b, cfg["tol"], cfg["maxit"])
+    lam = eigenvalues(n, n, n)
+    err, err_ref = check_against_oracle(x, it, rel, ref, xs, b, cfg["tol"],
+                                        lam.max() / lam.min())
+    note("cg 256^3: oracle %d iterations; error %.3g (oracle %.3g)" % (ref.iters, err, err_ref))
+
+
+def test_more_blocks_than_threads_against_oracle(gpu):
+    """256 x 256 x 48 at the default tile (128 x 4 nodes, z-blocks of 16):
+    384 blocks of 256 threads, so a reduction's partials are folded two per
+    thread before the block tree."""
+    nx, ny, nz = 256, 256, 48
+    note("cg %dx%dx%d (384 blocks) against the oracle" % (nx, ny, nz))
+    tl = gpu.get_cg_tiling()
+    blocks = (-(-nx // (64 * tl["vec"] * tl["wx"]))) * (-(-ny // tl["by"])) * \
+        (-(-nz // tl["zdepth"]))
+    assert blocks > 64 * tl["wx"] * tl["by"], blocks
+    xs = inputs.manufactured_solution(nx, ny, nz, seed=21)
+    b = oracle.lap7_apply(xs)
+    st, it, rel, x = gpu_cg(gpu, b, 1e-10, 5000)
+    assert st == 0
+    ref = oracle.cg(b, 1e-10, 5000)
+    lam = eigenvalues(nx, ny, nz)
+    check_against_oracle(x, it, rel, ref, xs, b, 1e-10, lam.max() / lam.min())
+
+
+def test_misaligned_workspace_is_rejected(gpu):
+    """A caller workspace must be 256-byte aligned; an offset view is
+    refused before any launch (x is left as it was)."""
+    n = 20
+    note("cg with a misaligned caller workspace")
+    b = torch.from_numpy(oracle.lap7_apply(inputs.manufactured_solution(n, seed=15))).cuda()
+    work = torch.empty(gpu.cg_workspace_bytes(n, n, n) + 256, dtype=torch.uint8, device="cuda")
+    assert work.data_ptr() % 256 == 0
+    x = torch.full_like(b, 3.0)
+    for off in (8, 128):
+        with pytest.raises(gpu.HeatCGError) as e:
+            gpu.cg_solve(b, x, 1e-10, 100, work=work[off:])
+        assert e.value.code == -1 and "aligned" in e.value.message
+        with pytest.raises(gpu.HeatCGError) as e:
+            gpu.cg_solve_ir(b, x, 1e-10, 100, work=work[off:])
+        assert e.value.code == -1
+    torch.cuda.synchronize()
+    assert bool((x == 3.0).all())
+    st, it, rel = gpu.cg_solve(b, torch.zeros_like(b), 1e-10, 500, work=work[256:])
+    assert st == 0 and rel <= 1e-10
+
+
+def test_concurrent_solves_on_one_device(gpu):
+    """Two host threads solving at once on the library's workspace: solves
+    on one device are serialized, so both give the single-thread bits."""
+    import threading
+    note("cg from two host threads")
+    bs = [oracle.lap7_apply(inputs.manufactured_solution(n, seed=16 + n)) for n in (40, 56)]
+    want = [gpu_cg(gpu, b, 1e-10, 3000) for b in bs]
+    out = [None, None]
+
+    def run(q):
+        torch.cuda.set_device(0)
+        with torch.cuda.stream(torch.cuda.Stream()):
+            out[q] = gpu_cg(gpu, bs[q], 1e-10, 3000)
+            torch.cuda.synchronize()
+
+    for _ in range(3):
+        th = [threading.Thread(target=run, args=(q,)) for q in (0, 1)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        for q in (0, 1):
+            assert out[q][:2] == want[q][:2] and np.array_equal(out[q][3], want[q][3])
 
 
 def built_cg_shapes():
