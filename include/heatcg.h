@@ -284,6 +284,35 @@ int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol,
 /* Bytes of device workspace cg_solve_ex needs (0 for invalid sizes). */
 size_t cg_workspace_bytes(int nx, int ny, int nz);
 
+/*
+ * cg_solve_noalloc -- cg_solve_ex for callers that cannot allocate device
+ * memory (code next to HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same solver and kernels, with the same
+ * results bit for bit as cg_solve_ex with the same tile shape, but its
+ * workspace is a fixed array of HC_CG_NOALLOC_BYTES bytes of device memory
+ * that the library's code object holds on every GPU it runs on until the
+ * process ends.  The call allocates nothing: no hipMalloc, hipFree,
+ * hipHostMalloc, stream or event creation (kernel timing through hc_prof_*
+ * is not taken for it).
+ *
+ *  b, x, nx, ny, nz, tol, maxit, stream, iters, true_relres  as cg_solve_ex.
+ *  Size limit: cg_workspace_bytes(nx, ny, nz) + 16384 (the store target of
+ *  lanes outside the box) must not exceed HC_CG_NOALLOC_BYTES, else
+ *  HC_EINVAL before any device work (a 128^3 box needs about 51 MB, the
+ *  largest cube is 140^3).
+ *
+ * Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents; nothing in it is read before the call writes it.  The
+ * library holds a per-device lock for the whole call, so calls from several
+ * host threads of one process run one after another; calls that overlap on
+ * one GPU without that lock (another copy of the library loaded in the same
+ * process) would race on the array.  Blocks until done; same statuses as
+ * cg_solve_ex.
+ */
+#define HC_CG_NOALLOC_BYTES (64u << 20)
+int cg_solve_noalloc(const double *b, double *x, int nx, int ny, int nz, double tol,
+                     int maxit, hc_stream_t stream, int *iters, double *true_relres);
+
 /* Iteration count and true relative residual of this thread's last CG. */
 void hc_cg_last_info(int *iters, double *true_relres);
 

@@ -20,13 +20,15 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "lap7_apply_f32", "set_cg_ir_tiling", "get_cg_ir_tiling", "DEFAULT_CG_IR_TILING",
            "Batch", "heat_vk_step", "set_vk_tiling", "get_vk_tiling", "vk_tiling_for",
            "set_time_block", "get_time_block", "set_tiling2", "get_tiling2", "tiling2_for",
-           "set_vk2_tiling", "get_vk2_tiling", "vk2_tiling_for"]
+           "set_vk2_tiling", "get_vk2_tiling", "vk2_tiling_for", "cg_solve_noalloc",
+           "CG_NOALLOC_BYTES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
 
 HC_OK, HC_ENOTCONV = 0, 1
 HC_F64, HC_F32, HC_BF16 = 0, 1, 2
+CG_NOALLOC_BYTES = 64 << 20  # HC_CG_NOALLOC_BYTES of heatcg.h
 MODES = {"split": 0, "fused": 1, "plain": 2}
 KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain": 3,
            "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8,
@@ -68,6 +70,7 @@ def load():
         "cg_solve": (i, [vp, vp, i, d, i]),
         "cg_solve_ex": (i, [vp, vp, i, i, i, d, i, vp, sz, vp, ip, dp]),
         "cg_workspace_bytes": (sz, [i, i, i]),
+        "cg_solve_noalloc": (i, [vp, vp, i, i, i, d, i, vp, ip, dp]),
         "hc_cg_last_info": (None, [ip, dp]),
         "hc_lap7_apply": (i, [vp, vp, i, i, i, vp]),
         "hc_copy_probe": (i, [vp, vp, sz, vp]),
@@ -234,6 +237,26 @@ def cg_solve(b, x, tol: float, maxit: int, work=None, stream=None):
                                    nx, ny, nz, float(tol), int(maxit), wptr, wbytes,
                                    _stream_handle(b, stream), ctypes.byref(it),
                                    ctypes.byref(rel)))
+    return st, it.value, rel.value
+
+
+def cg_solve_noalloc(b, x, tol: float, maxit: int, stream=None):
+    """cg_solve on the library's fixed device workspace (no allocation);
+    boxes whose workspace exceeds CG_NOALLOC_BYTES raise HeatCGError.
+
+    Returns (status, iterations, true relative residual).
+    """
+    import torch
+    _require_cuda_3d(b, x)
+    if b.dtype != torch.float64:
+        raise TypeError("cg_solve_noalloc works in float64")
+    nz, ny, nx = b.shape
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    st = _check(load().cg_solve_noalloc(ctypes.c_void_p(b.data_ptr()),
+                                        ctypes.c_void_p(x.data_ptr()), nx, ny, nz, float(tol),
+                                        int(maxit), _stream_handle(b, stream), ctypes.byref(it),
+                                        ctypes.byref(rel)))
     return st, it.value, rel.value
 
 

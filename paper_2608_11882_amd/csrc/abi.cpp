@@ -16,6 +16,12 @@
 #include <string>
 #include <vector>
 
+// Device memory of cg_solve_noalloc, the entry point for callers that cannot
+// allocate: every GPU the library runs on holds its own copy until the
+// process ends.  In host code this name is not a device address; the
+// address is looked up once per device (scratch_slot) and used instead.
+static __device__ __align__(256) unsigned char scratch[HC_CG_NOALLOC_BYTES];
+
 namespace {
 
 using hc::KernelKind;
@@ -298,6 +304,39 @@ int device_state(DevState **out) {
         d.ready = true;
     }
     *out = &d;
+    return HC_OK;
+}
+
+// ---- the fixed workspace of cg_solve_noalloc ----------------------------------------
+// Its first kNoallocSinkBytes take the stores of lanes outside the box (the
+// CG kernels' sink), the rest is carved like a caller's CG workspace.
+constexpr size_t kNoallocSinkBytes = 256 * ((hc::kSinkDoubles * sizeof(double) + 255) / 256);
+
+struct ScratchSlot {
+    std::mutex mu;                 // held for a whole solve: one array per device
+    bool ready = false;
+    unsigned char *ptr = nullptr;  // the array's device address on this device
+    hc::CGScalars host;            // the solver's scalars, read back at every poll
+};
+ScratchSlot g_scratch_slot[kMaxDev];
+
+// The current device's slot; on its first use the device address of
+// `scratch` is looked up with that device current (no allocation).
+int scratch_slot(ScratchSlot **out) {
+    int dev = 0;
+    HC_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDev) return fail(HC_EINVAL, "device %d out of range", dev);
+    ScratchSlot &sl = g_scratch_slot[dev];
+    std::lock_guard<std::mutex> g(sl.mu);
+    if (!sl.ready) {
+        void *p = nullptr;
+        HC_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (scratch)");
+        if (p == nullptr || reinterpret_cast<uintptr_t>(p) % 256 != 0)
+            return fail(HC_EHIP, "the fixed CG workspace has no usable device address");
+        sl.ptr = static_cast<unsigned char *>(p);
+        sl.ready = true;
+    }
+    *out = &sl;
     return HC_OK;
 }
 
@@ -1272,6 +1311,38 @@ int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol, 
 
 int cg_solve(const double *b, double *x, int n, double tol, int maxit) {
     return cg_solve_ex(b, x, n, n, n, tol, maxit, nullptr, 0, nullptr, nullptr, nullptr);
+}
+
+int cg_solve_noalloc(const double *b, double *x, int nx, int ny, int nz, double tol, int maxit,
+                     hc_stream_t stream, int *iters, double *true_relres) {
+    g_msg.clear();
+    if (iters) *iters = 0;
+    if (true_relres) *true_relres = 0.0;
+    if (!b || !x) return fail(HC_EINVAL, "b and x must be non-NULL");
+    size_t bytes = 0;
+    int rc = check_dims(nx, ny, nz, 1, 8, &bytes);
+    if (rc) return rc;
+    if (!std::isfinite(tol) || tol <= 0.0) return fail(HC_EINVAL, "tol = %g must be > 0", tol);
+    if (maxit < 0) return fail(HC_EINVAL, "maxit = %d < 0", maxit);
+    if (overlaps(b, bytes, x, bytes)) return fail(HC_EALIAS, "b and x overlap");
+    const size_t need = kNoallocSinkBytes + hc::cg_work_bytes(nx, ny, nz);
+    if (need > (size_t)HC_CG_NOALLOC_BYTES)
+        return fail(HC_EINVAL, "a %d x %d x %d box needs %zu bytes of workspace; the fixed one "
+                    "holds %zu", nx, ny, nz, need, (size_t)HC_CG_NOALLOC_BYTES);
+    if ((rc = check_device_buffer(b, bytes, "b"))) return rc;
+    if ((rc = check_device_buffer(x, bytes, "x"))) return rc;
+    ScratchSlot *sl = nullptr;
+    if ((rc = scratch_slot(&sl))) return rc;
+    std::lock_guard<std::mutex> solve_lock(sl->mu);
+    double *sink = reinterpret_cast<double *>(sl->ptr);
+    void *work = sl->ptr + kNoallocSinkBytes;
+    int it = 0;
+    double rel = 0.0;
+    rc = cg_run(b, x, nx, ny, nz, tol, maxit, work, reinterpret_cast<hipStream_t>(stream), sink,
+                &sl->host, false, &it, &rel);
+    if (iters) *iters = it;
+    if (true_relres) *true_relres = rel;
+    return rc;
 }
 
 void hc_cg_last_info(int *iters, double *true_relres) {

@@ -1,0 +1,90 @@
+"""cg_solve_noalloc: the CG entry point that allocates nothing (its workspace
+is a fixed device array of the library), against cg_solve_ex on the
+library's allocated workspace.
+
+Both run the same kernels with the same tile shape, so the iterates and the
+iteration count must agree bit for bit; the solution is also held to the
+oracle's acceptance rule.  Two calls in a row, the second on a smaller box,
+check that the fixed array's leftover contents from the first call do not
+reach the second.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2608_11882_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print("[case] " + msg, flush=True)
+
+
+def noalloc_abi(hc, b, x, tol, maxit):
+    """cg_solve_noalloc through the C ABI on torch's current stream."""
+    nz, ny, nx = b.shape
+    it = ctypes.c_int(-1)
+    rel = ctypes.c_double(-1.0)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = hc.abi().cg_solve_noalloc(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                   nx, ny, nz, float(tol), int(maxit), stream,
+                                   ctypes.byref(it), ctypes.byref(rel))
+    return rc, it.value, rel.value
+
+
+def test_noalloc_matches_allocating_entry_point(gpu):
+    tol = 1e-10
+    for seed, (nx, ny, nz) in ((31, (96, 80, 72)), (32, (40, 36, 30))):
+        note("cg_solve_noalloc %dx%dx%d against cg_solve_ex" % (nx, ny, nz))
+        xs = inputs.manufactured_solution(nx, ny, nz, seed=seed)
+        b_np = oracle.lap7_apply(xs)
+        b = torch.from_numpy(b_np).cuda()
+        x_ref = torch.zeros_like(b)
+        st_ref, it_ref, rel_ref = gpu.cg_solve(b, x_ref, tol, 5000)
+        x = torch.zeros_like(b)
+        rc, it, rel = noalloc_abi(gpu, b, x, tol, 5000)
+        torch.cuda.synchronize()
+        assert rc == 0 and st_ref == 0
+        assert it == it_ref and rel == rel_ref
+        assert torch.equal(x, x_ref)
+        ref = oracle.cg(b_np, tol, 5000)
+        assert abs(it - ref.iters) <= max(3, int(0.01 * ref.iters))
+        xn = x.cpu().numpy()
+        err = np.linalg.norm(xn - xs) / np.linalg.norm(xs)
+        err_ref = np.linalg.norm(ref.x - xs) / np.linalg.norm(xs)
+        assert err <= 10 * err_ref + 1e-13
+
+
+def test_noalloc_limits_and_resume(gpu):
+    note("cg_solve_noalloc: size limit, maxit and resume")
+    # a box whose workspace exceeds the fixed array is refused before any launch
+    n = 141
+    assert gpu.cg_workspace_bytes(n, n, n) + 16384 > gpu.CG_NOALLOC_BYTES
+    b = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
+    x = torch.full_like(b, 2.0)
+    rc, it, rel = noalloc_abi(gpu, b, x, 1e-10, 10)
+    assert rc == -1 and it == 0
+    torch.cuda.synchronize()
+    assert bool((x == 2.0).all())
+    del b, x
+    # the largest cube fits and converges
+    n = 140
+    assert gpu.cg_workspace_bytes(n, n, n) + 16384 <= gpu.CG_NOALLOC_BYTES
+    xs = torch.from_numpy(inputs.manufactured_solution(n, seed=33)).cuda()
+    b = torch.empty_like(xs)
+    gpu.lap7_apply(xs, b)
+    x = torch.zeros_like(b)
+    st, it, rel = gpu.cg_solve_noalloc(b, x, 1e-10, 10000)
+    assert st == 0 and rel <= 1e-10
+    # maxit reached, then resumed from the returned iterate
+    n = 32
+    b = torch.from_numpy(oracle.lap7_apply(inputs.manufactured_solution(n, seed=34))).cuda()
+    x = torch.zeros_like(b)
+    rc, it, rel = noalloc_abi(gpu, b, x, 1e-10, 5)
+    assert rc == 1 and it == 5 and rel > 1e-10
+    rc, it, rel = noalloc_abi(gpu, b, x, 1e-10, 2000)
+    assert rc == 0 and rel <= 1e-10
