@@ -52,12 +52,18 @@ def _configure(lib):
     lib.oracle_cg.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
+    lib.oracle_last_loop_seconds.argtypes = []
+    lib.oracle_last_loop_seconds.restype = ctypes.c_double
     fp = ctypes.POINTER(ctypes.c_float)
     hp = ctypes.POINTER(ctypes.c_uint16)
     lib.oracle_heat_f32.argtypes = [fp, L, L, L, ctypes.c_float, L]
     lib.oracle_heat_f32.restype = ctypes.c_int
     lib.oracle_heat_bf16.argtypes = [hp, L, L, L, ctypes.c_float, L]
     lib.oracle_heat_bf16.restype = ctypes.c_int
+    lib.oracle_heat_bf16_offset.argtypes = [hp, hp, L, L, L, ctypes.c_float, L]
+    lib.oracle_heat_bf16_offset.restype = ctypes.c_int
     lib.oracle_bf16_round_array.argtypes = [fp, hp, L]
     lib.oracle_bf16_round_array.restype = None
     u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -124,6 +130,17 @@ def source_path() -> str:
 def threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    _load().oracle_set_threads(int(n))
+
+
+def last_loop_seconds() -> float:
+    """Wall time of the step loop of the last ``heat`` call, or of the
+    iteration loop of the last ``cg`` call (set-up and copies excluded)."""
+    return float(_load().oracle_last_loop_seconds())
 
 
 def _ptr(a: np.ndarray):
@@ -199,6 +216,24 @@ def heat_bf16_sr(u0_bits: np.ndarray, r: float, steps: int, seed: int, step0: in
     if rc != 0:
         raise MemoryError("oracle_heat_bf16_sr returned %d" % rc)
     return u
+
+
+def heat_bf16_offset(base_bits: np.ndarray, delta_bits: np.ndarray, r: float,
+                     steps: int) -> np.ndarray:
+    """bfloat16 storage as offsets from a fixed bfloat16 base: returns the
+    offsets after `steps` steps (the value is base + offset); see
+    ``oracle_heat_bf16_offset``."""
+    base = np.ascontiguousarray(base_bits, dtype=np.uint16)
+    d = np.ascontiguousarray(delta_bits, dtype=np.uint16).copy()
+    if base.shape != d.shape or base.ndim != 3:
+        raise ValueError("expected two 3-D arrays of one shape")
+    nz, ny, nx = d.shape
+    hp = ctypes.POINTER(ctypes.c_uint16)
+    st = _load().oracle_heat_bf16_offset(base.ctypes.data_as(hp), d.ctypes.data_as(hp), nx, ny,
+                                         nz, float(np.float32(r)), int(steps))
+    if st == -4:
+        raise MemoryError("oracle_heat_bf16_offset: out of memory")
+    return d
 
 
 def philox4x32_10(ctr, key) -> tuple:

@@ -27,6 +27,16 @@
 /* Number of OpenMP threads the loops below run on. */
 int oracle_threads(void) { return omp_get_max_threads(); }
 
+/* Thread count of the parallel loops that follow (the CPU baseline times
+ * the oracle at one thread and at every physical core). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+/* Wall time of the step loop (oracle_heat_f64) or of the iteration loop
+ * (oracle_cg) of the last call, set-up and copies excluded, the way the
+ * paper's timer brackets its time loop only (Methodology). */
+static double g_loop_seconds = 0.0;
+double oracle_last_loop_seconds(void) { return g_loop_seconds; }
+
 /* ------------------------------------------------------------------------ */
 /* Heat equation, constant coefficient                                       */
 /* ------------------------------------------------------------------------ */
@@ -78,12 +88,14 @@ int oracle_heat_f64(double *u, long nx, long ny, long nz, double r, long steps)
         return -4;
     memcpy(w, u, (size_t)n * sizeof(double)); /* boundary of w = boundary of u */
     double *a = u, *b = w;
+    const double t0 = omp_get_wtime();
     for (long s = 0; s < steps; ++s) {
         oracle_heat_sweep_f64(a, b, nx, ny, nz, r);
         double *t = a;
         a = b;
         b = t;
     }
+    g_loop_seconds = omp_get_wtime() - t0;
     if (a != u)
         memcpy(u, a, (size_t)n * sizeof(double));
     free(w);
@@ -214,6 +226,65 @@ int oracle_heat_bf16(uint16_t *u, long nx, long ny, long nz, float r, long steps
     }
     if (a != u)
         memcpy(u, a, (size_t)n * sizeof(uint16_t));
+    free(w);
+    return 0;
+}
+
+/*
+ * bfloat16 storage as offsets from a fixed bfloat16 base (the other remedy
+ * for the stagnation of nearest rounding; not in the paper): a node's value
+ * is u = base + delta, both stored in bfloat16 and added in binary32.  A
+ * step forms u at the node and its six neighbours that way, applies the
+ * binary32 step above, and stores the new offset rounded to the nearest
+ * bfloat16: delta' = bf16(u' - base) (binary32 subtraction).  The base is
+ * never written; as the offsets stay small their ulp is far below the one
+ * of u, so the increments that nearest rounding drops on u are kept.  With
+ * base = 0 this is the bfloat16 step above.
+ */
+static float offset_value(const uint16_t *base, const uint16_t *delta, long p)
+{
+    return oracle_f32_from_bf16(base[p]) + oracle_f32_from_bf16(delta[p]);
+}
+
+void oracle_heat_sweep_bf16_offset(const uint16_t *base, const uint16_t *d,
+                                   uint16_t *dn, long nx, long ny, long nz, float r)
+{
+    const long sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 1; k < nz - 1; ++k)
+        for (long j = 1; j < ny - 1; ++j)
+            for (long i = 1; i < nx - 1; ++i) {
+                const long p = IDX(i, j, k, nx, ny);
+                const float c = offset_value(base, d, p);
+                const float nsum =
+                    ((offset_value(base, d, p - sx) + offset_value(base, d, p + sx)) +
+                     (offset_value(base, d, p - sy) + offset_value(base, d, p + sy))) +
+                    (offset_value(base, d, p - sz) + offset_value(base, d, p + sz));
+                const float lap = nsum - 6.0f * c;
+                const float un = c + r * lap;
+                dn[p] = oracle_bf16_from_f32(un - oracle_f32_from_bf16(base[p]));
+            }
+}
+
+int oracle_heat_bf16_offset(const uint16_t *base, uint16_t *delta, long nx, long ny, long nz,
+                            float r, long steps)
+{
+    const long n = nx * ny * nz;
+    if (steps <= 0)
+        return 0;
+    uint16_t *w = (uint16_t *)malloc((size_t)n * sizeof(uint16_t));
+    if (!w)
+        return -4;
+    memcpy(w, delta, (size_t)n * sizeof(uint16_t));
+    uint16_t *a = delta, *b = w;
+    for (long s = 0; s < steps; ++s) {
+        oracle_heat_sweep_bf16_offset(base, a, b, nx, ny, nz, r);
+        uint16_t *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != delta)
+        memcpy(delta, a, (size_t)n * sizeof(uint16_t));
     free(w);
     return 0;
 }
@@ -461,6 +532,7 @@ int oracle_cg(const double *b, double *x, long nx, long ny, long nz, double tol,
     if (hist)
         hist[0] = sqrt(rho) / bnorm;
 
+    const double t0 = omp_get_wtime();
     if (sqrt(rho) <= tol * bnorm) {
         status = 0;
     } else {
@@ -498,6 +570,7 @@ int oracle_cg(const double *b, double *x, long nx, long ny, long nz, double tol,
             rho = rho_new;
         }
     }
+    g_loop_seconds = omp_get_wtime() - t0;
 
     /* true residual b - A x */
     oracle_lap7_apply(x, q, nx, ny, nz);

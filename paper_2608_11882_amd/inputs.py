@@ -131,6 +131,16 @@ def to_bf16_bits(x) -> np.ndarray:
     return (y.astype(np.float32).view(np.uint32) >> np.uint32(16)).astype(np.uint16)
 
 
+def bf16_offset_split(u: np.ndarray):
+    """A float64 field as a bfloat16 base and a bfloat16 offset: base =
+    u rounded to the nearest bfloat16, offset = (u - base) rounded likewise
+    (the difference is exact in float64).  Returns the two uint16 arrays."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    base = to_bf16_bits(u)
+    widened = (base.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+    return base, to_bf16_bits(u - widened)
+
+
 def sine_field_lowp(nx: int, ny: int, nz: int, noise: float, seed: int, dtype: str):
     """sine_field(..., noise, seed) rounded once from float64 to "f32" or
     "bf16" (bfloat16 returned as uint16 bit patterns), plane by plane."""

@@ -37,6 +37,11 @@ PREC_PINS = [
     prec_pins.test_bf16_error_against_f64_within_bound_and_stagnation,
 ]
 
+OFFSET_PINS = [
+    prec_pins.test_bf16_offset_with_zero_base_is_the_bf16_step,
+    prec_pins.test_bf16_offset_keeps_the_increments_nearest_rounding_drops,
+]
+
 SR_PINS = [
     sr_pins.test_philox_known_answer_vectors,
     sr_pins.test_rounding_is_exactly_unbiased_over_all_random_bits,
@@ -97,6 +102,10 @@ MUTATIONS = {
     "bf16_truncates": ("out = upper + 1u;", "out = upper;", PREC_PINS),
     "f32_dropped_weight": ("const float lap = nsum - 6.0f * c;\n                un[p] = c + r * lap;",
                            "const float lap = nsum - 5.0f * c;\n                un[p] = c + r * lap;", PREC_PINS),
+    "offset_base_not_subtracted": ("dn[p] = oracle_bf16_from_f32(un - oracle_f32_from_bf16(base[p]));",
+                                   "dn[p] = oracle_bf16_from_f32(un);", OFFSET_PINS),
+    "offset_value_without_base": ("return oracle_f32_from_bf16(base[p]) + oracle_f32_from_bf16(delta[p]);",
+                                  "return oracle_f32_from_bf16(delta[p]);", OFFSET_PINS),
     "bf16_step_sign": ("un[p] = oracle_bf16_from_f32(c + r * lap);", "un[p] = oracle_bf16_from_f32(c - r * lap);", PREC_PINS),
     "dropped_neighbour_weight": ("const double lap = nsum - 6.0 * c;", "const double lap = nsum - 4.0 * c;", HEAT_PINS),
     "sign_of_update": ("const double lap = nsum - 6.0 * c;\n                un[p] = c + r * lap;",

@@ -127,3 +127,44 @@ def test_bf16_error_against_f64_within_bound_and_stagnation():
     n = 34
     smooth = inputs.to_bf16_bits(inputs.sine_field(n, n, n) * 0.9)
     assert np.array_equal(oracle.heat_bf16(smooth, 0.001, 50), smooth)
+
+
+# ---- bfloat16 offsets from a bfloat16 base (the other stagnation remedy) ----------
+
+def _widen(bits):
+    return (np.asarray(bits, dtype=np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
+def test_bf16_offset_with_zero_base_is_the_bf16_step():
+    """With a zero base the value is the offset itself, u' - 0 is exact, and
+    the offset step is the bfloat16 step, bit for bit."""
+    u = inputs.to_bf16_bits(inputs.uniform_field(21, 18, 16, seed=40))
+    zero = np.zeros_like(u)
+    assert np.array_equal(oracle.heat_bf16_offset(zero, u, 0.15, 7), oracle.heat_bf16(u, 0.15, 7))
+
+
+def test_bf16_offset_split_reconstructs_the_field():
+    """base + offset reproduces the float64 field to bfloat16 precision of
+    the offset (the base holds the leading 8 bits, the offset the next 8)."""
+    u = inputs.sine_field(20, 19, 18, noise=1e-3, seed=41)
+    base, off = inputs.bf16_offset_split(u)
+    err = np.abs(_widen(base) + _widen(off) - u)
+    assert np.all(err <= 2.0 ** -8 * np.abs(u - _widen(base)))
+    assert np.max(err) <= 2.0 ** -16 * np.max(np.abs(u))
+
+
+def test_bf16_offset_keeps_the_increments_nearest_rounding_drops():
+    """The small configuration (66^3, sine mode + noise, r = 0.1, 100 steps)
+    against the FP64 oracle: nearest rounding of the value freezes the
+    decay (error ~ the decay, 7e-2 relative); offsets from the rounded
+    initial field keep it to ~1e-3, above binary32's 1e-7 because the
+    offsets themselves stall once they outgrow the per-step increments."""
+    cfg = inputs.HEAT_SMALL
+    u0 = inputs.sine_field(66, 66, 66, noise=1e-3, seed=cfg["seed"])
+    ref = oracle.heat(u0, cfg["r"], cfg["steps"])
+    base, off = inputs.bf16_offset_split(u0)
+    got = _widen(base) + _widen(oracle.heat_bf16_offset(base, off, cfg["r"], cfg["steps"]))
+    rn = _widen(oracle.heat_bf16(inputs.to_bf16_bits(u0), cfg["r"], cfg["steps"]))
+    rel = lambda a: np.linalg.norm(a - ref) / np.linalg.norm(ref)  # noqa: E731
+    assert rel(got) < 0.05 * rel(rn)
+    assert rel(got) < 3e-3 and rel(rn) > 3e-2
