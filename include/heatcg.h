@@ -161,7 +161,10 @@ int hc_heat_get_time_block(void);
 /*
  * Tile shape of the two-step sweep, per dtype (HC_F64, HC_F32, HC_BF16),
  * same fields and rules as hc_heat_set_tiling (all zeros: automatic); the
- * shapes built are listed in heat2_kernels.hip (HC_HEAT2_SHAPES_*).
+ * shapes built are listed in heat2_kernels.hip (HC_HEAT2_SHAPES_*).  Here
+ * xcd may also be -1: slab order, where each of the 8 XCDs sweeps one
+ * eighth of the tile rows (every x-tile of them) z-run by z-run, so the
+ * tiles that run side by side on an XCD are neighbours in x and y.
  * hc_heat2_tiling_for reports the shape a two-step sweep of these arrays
  * would run with.
  */
@@ -172,6 +175,20 @@ int hc_heat2_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth,
 int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new,
                         int *vec, int *wx, int *by, int *zdepth, int *pf,
                         int *xcd);
+
+/*
+ * Run length of the two-step constant-coefficient sweep, per dtype (HC_F64,
+ * HC_F32, HC_BF16): the planes of output each block of the Interior (or
+ * fused) kernel marches as one run, its register queues carried from one
+ * z-block to the next.  0 (the default) is the automatic choice: one
+ * z-block per block for HC_F64 and HC_F32, 128 planes for HC_BF16; other
+ * values are rounded up to a multiple of the tile's zdepth.  Results do
+ * not depend on it.
+ * hc_heat2_set_zrun returns HC_EINVAL for another dtype or a value outside
+ * [0, 2^20]; hc_heat2_get_zrun returns the setting (or HC_EINVAL).
+ */
+int hc_heat2_set_zrun(int dtype, int planes);
+int hc_heat2_get_zrun(int dtype);
 
 /*
  * heat_vk_step -- the paper's own equation: `steps` explicit steps of

@@ -21,6 +21,7 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "Batch", "heat_vk_step", "set_vk_tiling", "get_vk_tiling", "vk_tiling_for",
            "set_time_block", "get_time_block", "set_tiling2", "get_tiling2", "tiling2_for",
            "set_vk2_tiling", "get_vk2_tiling", "vk2_tiling_for", "cg_solve_noalloc",
+           "set_zrun2", "get_zrun2",
            "CG_NOALLOC_BYTES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -107,6 +108,8 @@ def load():
         "hc_heat2_set_tiling": (i, [i, i, i, i, i, i, i]),
         "hc_heat2_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
         "hc_heat2_tiling_for": (i, [i, i, vp, vp, ip, ip, ip, ip, ip, ip]),
+        "hc_heat2_set_zrun": (i, [i, i]),
+        "hc_heat2_get_zrun": (i, [i]),
         "hc_heat_vk2_set_tiling": (i, [i, i, i, i, i, i, i]),
         "hc_heat_vk2_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
         "hc_heat_vk2_tiling_for": (i, [i, i, vp, vp, vp, vp, ip, ip, ip, ip, ip, ip]),
@@ -390,6 +393,15 @@ def set_tiling2(vec: int | None = None, wx: int | None = None, by: int | None = 
             raise ValueError("give vec, wx, by and zdepth, or none of them")
         t = dict(vec=vec, wx=wx, by=by, zdepth=zdepth, pf=pf, xcd=xcd)
     _check(load().hc_heat2_set_tiling(DTYPES[dtype], *(int(t[k]) for k in _TILE_KEYS)))
+
+
+def set_zrun2(planes: int = 0, dtype: str = "f64") -> None:
+    """Output planes per block of the two-step sweep (0: automatic)."""
+    _check(load().hc_heat2_set_zrun(DTYPES[dtype], int(planes)))
+
+
+def get_zrun2(dtype: str = "f64") -> int:
+    return _check(load().hc_heat2_get_zrun(DTYPES[dtype]))
 
 
 def get_tiling2(dtype: str = "f64") -> dict:

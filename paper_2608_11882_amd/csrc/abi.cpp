@@ -180,14 +180,17 @@ hc::HeatTiling vk_tiling_for(int dtype, int nx, const void *const *arrays, int n
 // Steps per pass of the z-marching constant-coefficient sweeps (1 or 2;
 // two by default: a pass then moves half the bytes per step).  The
 // two-step sweep has tile shapes of its own, per storage precision; the
-// automatic candidates are the fastest of a sweep over the built ones at
-// 512^3 on MI355X (tiles 256 nodes wide, 4-8 rows, z-blocks of 32 planes).
+// automatic candidates are the fastest of sweeps over the built ones at
+// 512^3 and 1024^3 on MI355X (tiles 256 nodes wide, 8 rows, z-blocks of 32
+// planes, slab order: at 1024^3 it cuts the reads the rings miss in L2,
+// 5-10% faster than runs of 8 y-tiles per XCD; at 512^3 the two orders
+// measured alike).
 int g_time_block = 2;
 hc::HeatTiling g_tiling2[3] = {};
-const hc::HeatTiling kAuto2[3][4] = {
-    {{2, 2, 4, 32, 2, 8}, {2, 1, 8, 32, 2, 8}, {1, 4, 4, 16, 2, 8}, {}},
-    {{4, 1, 8, 32, 2, 8}, {4, 1, 4, 32, 2, 8}, {1, 4, 4, 16, 2, 8}, {}},
-    {{4, 1, 4, 32, 2, 8}, {4, 1, 8, 32, 2, 8}, {1, 4, 4, 16, 2, 8}, {}},
+const hc::HeatTiling kAuto2[3][5] = {
+    {{2, 2, 8, 32, 2, -1}, {2, 2, 4, 32, 2, -1}, {2, 1, 8, 32, 2, -1}, {1, 4, 4, 16, 2, 8}, {}},
+    {{4, 1, 8, 32, 2, -1}, {4, 2, 4, 32, 2, -1}, {4, 1, 4, 32, 2, -1}, {1, 4, 4, 16, 2, 8}, {}},
+    {{4, 1, 8, 32, 2, -1}, {4, 1, 4, 32, 2, -1}, {1, 4, 4, 16, 2, 8}, {}, {}},
 };
 
 hc::HeatTiling heat2_tiling_for(int dtype, int nx, const void *u, const void *un) {
@@ -219,6 +222,28 @@ hc::HeatTiling heat2_tiling_for(int dtype, int nx, const void *u, const void *un
                         (reinterpret_cast<uintptr_t>(un) % lane_bytes)))
         til = {1, 4, 4, 16, 2, til.xcd};
     return til;
+}
+
+// Planes of output per block of the two-step constant-coefficient sweep
+// (its Interior and fused kernels march them as one run), set per dtype;
+// 0 is the automatic choice kAutoZrun, where 0 means one z-block per block.
+// Measured on MI355X at 512^3 and 1024^3: for FP64 and FP32 runs of two to
+// four z-blocks were no faster than one and longer runs slower; the
+// bfloat16 sweep, bound by its vector ALU work, gains 5-8% from runs of 128
+// planes (fewer pipeline fills, each of which computes two planes of
+// u^(t+1) twice).
+int g_heat2_zrun[3] = {0, 0, 0};
+constexpr int kAutoZrun[3] = {0, 0, 128};
+
+int heat2_zrun(int dtype, const hc::HeatTiling &t) {
+    int zr;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        zr = g_heat2_zrun[dtype];
+    }
+    if (zr <= 0) zr = kAutoZrun[dtype];
+    const int zb = t.zdepth;
+    return zr <= 0 ? zb : (zr + zb - 1) / zb * zb;
 }
 
 int current_time_block() {
@@ -551,7 +576,9 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
             for (int q = 0; q < parts; ++q) {
                 int a, b;
                 slab(nz, parts, q, &a, &b);
-                if (b - a + 1 >= 5) push_range(tin2, a + 2, b - 2, til2.zdepth);
+                if (b - a + 1 >= 5)
+                    push_range(tin2, a + 2, b - 2,
+                               vk ? til2.zdepth : heat2_zrun(dtype, til2));
             }
             for (int q = 0; q < parts; ++q) {
                 int a, b;
@@ -564,7 +591,7 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                 }
             }
         } else {
-            push_range(tin2, 1, nz - 2, til2.zdepth);
+            push_range(tin2, 1, nz - 2, vk ? til2.zdepth : heat2_zrun(dtype, til2));
         }
         if (hc::heat_tile_blocks(nx, ny, til2, tin2) > 2147483647LL ||
             hc::heat_tile_blocks(nx, ny, til2, tbd2) > 2147483647LL)
@@ -1528,7 +1555,7 @@ int hc_heat2_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int pf, 
                     "two-step tile shape (vec %d, wx %d, by %d, zdepth %d, pf %d) is not built "
                     "for dtype %d",
                     vec, wx, by, zdepth, pf, dtype);
-    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    if (xcd < -1 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [-1, 64]", xcd);
     std::lock_guard<std::mutex> g(g_tiling_mu);
     g_tiling2[dtype] = t;
     return HC_OK;
@@ -1550,6 +1577,24 @@ int hc_heat2_get_tiling(int dtype, int *vec, int *wx, int *by, int *zdepth, int 
     if (pf) *pf = t.pf;
     if (xcd) *xcd = t.xcd;
     return HC_OK;
+}
+
+int hc_heat2_set_zrun(int dtype, int planes) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d has no two-step sweep", dtype);
+    if (planes < 0 || planes > (1 << 20)) return fail(HC_EINVAL, "zrun = %d out of range", planes);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_heat2_zrun[dtype] = planes;
+    return HC_OK;
+}
+
+int hc_heat2_get_zrun(int dtype) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32 && dtype != HC_BF16)
+        return fail(HC_EINVAL, "dtype %d has no two-step sweep", dtype);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    return g_heat2_zrun[dtype];
 }
 
 int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new, int *vec, int *wx,
@@ -1583,7 +1628,7 @@ int hc_heat_vk2_set_tiling(int dtype, int vec, int wx, int by, int zdepth, int p
                     "two-step variable-coefficient tile shape (vec %d, wx %d, by %d, zdepth %d, "
                     "pf %d) is not built for dtype %d",
                     vec, wx, by, zdepth, pf, dtype);
-    if (xcd < 0 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [0, 64]", xcd);
+    if (xcd < -1 || xcd > 64) return fail(HC_EINVAL, "xcd = %d outside [-1, 64]", xcd);
     std::lock_guard<std::mutex> g(g_tiling_mu);
     g_vk2_tiling[dtype] = t;
     return HC_OK;

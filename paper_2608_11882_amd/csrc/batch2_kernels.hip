@@ -12,12 +12,12 @@
 namespace hc {
 namespace {
 
-// LDS values of the two-step tile of class CLS: the u^t plane with its
+// LDS values of the two-step tile of class CLS: two u^t planes with their
 // two-node ring, and two u^(t+1) planes with a one-node ring and a sink.
 template <int VEC, int NT, int CLS>
 constexpr int class_lds_u() {
     using WC = WidthClass<NT, CLS>;
-    return WC::valid ? (WC::rows + 4) * (VEC * WC::lanes + 4) : 1;
+    return WC::valid ? 2 * (WC::rows + 4) * (VEC * WC::lanes + 4) : 1;
 }
 template <int VEC, int NT, int CLS>
 constexpr int class_lds_a() {

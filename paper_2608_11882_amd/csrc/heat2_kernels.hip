@@ -16,7 +16,7 @@ namespace {
         const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,        \
         int ny, int nz, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {            \
         using G = TileGeom2<VEC, 64 * WX, BY>;                                              \
-        __shared__ typename P::C tu[G::U_ELEMS];                                            \
+        __shared__ typename P::C tu[2 * G::U_ELEMS];                                        \
         __shared__ typename P::C ta[2 * G::A_ELEMS];                                        \
         const auto g = block_tile2<VEC, 64 * WX, BY>(nx, ny, nz, zt, ntx, nty, xcd, ZB);    \
         heat_tile_sweep2<P, VEC, 64 * WX, BY, PF, ZB>(u, un, r, g, tu, ta);                 \

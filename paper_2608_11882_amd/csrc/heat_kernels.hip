@@ -102,7 +102,8 @@ int tile_width(const HeatTiling &t) { return 64 * t.vec * t.wx; }
 long long heat_tile_blocks(int nx, int ny, const HeatTiling &t, const ZTable &zt) {
     const long long tx = tile_width(t);
     const long long ntx = (nx + tx - 1) / tx;
-    const long long nty = (ny - 2 + t.by - 1) / t.by;
+    long long nty = (ny - 2 + t.by - 1) / t.by;
+    if (t.xcd < 0) nty = 8 * ((nty + 7) / 8);  // slab order: whole slabs per XCD
     return ntx * nty * (long long)ztable_blocks(zt);
 }
 

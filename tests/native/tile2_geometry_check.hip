@@ -133,8 +133,39 @@ int check(int nx, int ny, int nz, int pitch = 0) {
     return bad;
 }
 
-int main() {
+// The z-plan of a run: every output plane of [kb, ke] is written, nothing
+// outside the interior planes [1, nz-2] is, and the march reads planes
+// within two of what it writes (plus its prefetch, clamped).
+static int check_run_plans() {
     int bad = 0;
+    for (int nz = 3; nz <= 140; ++nz)
+        for (int zb : {16, 32, 64})
+            for (int kb = 1; kb <= nz - 2; ++kb)
+                for (int ke = kb; ke <= nz - 2; ++ke) {
+                    const hc::RunPlan p = hc::run_plan(kb, ke, zb);
+                    std::vector<int> w(nz, 0);
+                    for (int k = p.start; k < p.start + p.m * zb; ++k) {
+                        if (k < 0 || k >= nz) { ++bad; continue; }
+                        ++w[k];
+                    }
+                    for (int k = p.rest; k <= ke; ++k) ++w[k];
+                    for (int k = 0; k < nz; ++k) {
+                        const bool in_run = k >= kb && k <= ke;
+                        if (in_run && w[k] != 1) ++bad;
+                        if (w[k] && (k < 1 || k > nz - 2)) ++bad;
+                        if (!in_run && w[k] && k > ke) ++bad;  // never past the run
+                    }
+                    if (p.m > 0 && p.start > kb) ++bad;
+                    if (bad && bad < 5)
+                        printf("run plan nz %d zb %d [%d, %d]: start %d m %d rest %d\n", nz, zb,
+                               kb, ke, p.start, p.m, p.rest);
+                }
+    printf("run plans: %d problems\n", bad);
+    return bad;
+}
+
+int main() {
+    int bad = check_run_plans();
     const int dims[][2] = {{3, 3}, {5, 4}, {130, 9}, {67, 33}, {264, 19}, {512, 512}, {1029, 6}, {64, 131}, {258, 40}, {520, 70}};
     for (auto &d : dims) {
         const int nx = d[0], ny = d[1], nz = 7;

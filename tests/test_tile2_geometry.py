@@ -44,6 +44,10 @@ def test_two_step_tile_geometry(tmp_path):
     # an inner-ring column is updated on the last row
     ("r1st[0] = (ri_u >= 1) && (ri_u <= nx - 2) && (rj_u <= ny - 2);",
      "r1st[0] = (ri_u >= 1) && (ri_u <= nx - 2) && (rj_u <= ny - 1);"),
+    # a run's march starts one plane late (its last plane is never written)
+    ("const int start = ke - m * zb + 1;", "const int start = ke - m * zb + 2;"),
+    # the early start is allowed to reach the Dirichlet plane 0
+    ("if (start >= 1) return {start, m, ke + 1};", "if (start >= 0) return {start, m, ke + 1};"),
 ])
 def test_checker_catches_a_planted_geometry_mistake(tmp_path, old, new):
     inc = tmp_path / "inc"
