@@ -71,47 +71,140 @@ def measured_traffic(time_block):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(u0_host, r, b_host, gpu_cg_iters, budget_s):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+# Per-point step time k-bar the paper measured on one GPU (tab:used-measurements):
+# FP64 heat with a variable coefficient and a source, OpenMP offload,
+# N = 512 .. 1280, 500 steps; k-bar = T / (steps (N-2)^3).  Context only:
+# another equation (>= 32 B per point) on other hardware.
+PAPER_KBAR = (("NVIDIA H100", 6.4042e-11), ("AMD MI250X, one GCD", 13.584e-11),
+              ("Intel Data Center GPU Max 1550", 4.6676e-11))
+
+
+def host_cpu():
+    """CPU model, sockets and the physical cores this process may run on."""
+    import subprocess
+    info = {"nproc": os.cpu_count(), "allowed_cpus": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        keys = {"Model name": ("model", str), "Socket(s)": ("sockets", int),
+                "Core(s) per socket": ("cores_per_socket", int),
+                "Thread(s) per core": ("threads_per_core", int)}
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys and k.strip() not in info:
+                name, conv = keys[k.strip()]
+                try:
+                    info[name] = conv(v.strip())
+                except ValueError:
+                    info[name] = v.strip()
+    except (OSError, subprocess.SubprocessError) as e:
+        info["lscpu_error"] = str(e)
+    cores = set()
+    for c in os.sched_getaffinity(0):
+        base = "/sys/devices/system/cpu/cpu%d/topology/" % c
+        try:
+            with open(base + "physical_package_id") as f1, open(base + "core_id") as f2:
+                cores.add((f1.read().strip(), f2.read().strip()))
+        except OSError:
+            cores.add(("cpu", str(c)))
+    info["physical_cores_allowed"] = len(cores)
+    return info
+
+
+def cpu_baseline(gpu_cg_iters, budget_s):
+    """The oracle's timing, run in a child process: this one has loaded
+    torch, whose OpenMP runtime pins the main thread once OMP_PROC_BIND is
+    set, so the child starts a fresh runtime with one thread per physical
+    core (OMP_PROC_BIND=close, OMP_PLACES=cores) and no GPU."""
+    import subprocess
+    env = dict(os.environ)
+    env["OMP_PROC_BIND"] = "close"
+    env["OMP_PLACES"] = "cores"
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child",
+                          "--cpu-seconds", repr(float(budget_s)),
+                          "--cpu-cg-iters", str(int(gpu_cg_iters))],
+                         env=env, stdout=subprocess.PIPE, timeout=max(600.0, 20 * budget_s))
+    if res.returncode != 0:
+        raise RuntimeError("CPU baseline child failed (status %d)" % res.returncode)
+    return json.loads(res.stdout.decode().strip().splitlines()[-1])
+
+
+def cpu_baseline_child(gpu_cg_iters, budget_s):
+    """The oracle, as it stands, on a bounded sample of the benchmark
+    workload (the same seeded 512^3 field and 256^3 system): at one thread
+    and at every physical core this process may use, the median of 3 runs
+    each, timing the step (or iteration) loop only, set-up and copies
+    excluded.  Runs without torch or a GPU."""
+    info = host_cpu()   # before the OpenMP runtime starts and binds threads
     import oracle
+    from paper_2608_11882_amd import inputs
+    hcfg, ccfg = inputs.HEAT_LARGE, inputs.CG_LARGE
+    u0_host = inputs.heat_large_f64(seed=hcfg["seed"], n=hcfg["n"])
+    r = hcfg["r"]
+    b_host = oracle.lap7_apply(inputs.manufactured_solution(ccfg["n"], seed=ccfg["seed"]))
+    ncore = max(1, info["physical_cores_allowed"])
     n = u0_host.shape[0]
     lups_per_step = (n - 2) ** 3
-    # a call also copies and allocates its arrays, so rates are marginal:
-    # the time of an s-step call minus that of a 2-step call, over s - 2
-    def timed(fn, *a):
-        t = time.perf_counter()
-        fn(*a)
-        return time.perf_counter() - t
 
-    oracle.heat(u0_host, r, 1)
-    t2 = timed(oracle.heat, u0_host, r, 2)
-    t6 = timed(oracle.heat, u0_host, r, 6)
-    per_step = max((t6 - t2) / 4.0, t2 / 50.0)
-    steps = max(6, int(0.6 * budget_s / per_step))
-    log("cpu baseline: heat %d steps on %d^3" % (steps, n))
-    heat_s = timed(oracle.heat, u0_host, r, steps)
-    glups = (steps - 2) * lups_per_step / max(heat_s - t2, 1e-9) / 1e9
-    oracle.cg(b_host, 1e-30, 1)
-    c1 = timed(oracle.cg, b_host, 1e-30, 1)
-    c3 = timed(oracle.cg, b_host, 1e-30, 3)
-    per_it = max((c3 - c1) / 2.0, c1 / 20.0)
-    iters = max(3, int(0.4 * budget_s / per_it))
-    log("cpu baseline: cg %d iterations on %d^3" % (iters, b_host.shape[0]))
-    cg_s = timed(oracle.cg, b_host, 1e-30, iters)
-    per_it = max(cg_s - c1, 1e-9) / (iters - 1)
+    def heat_runs(threads, steps):
+        oracle.set_threads(threads)
+        loops = []
+        for _ in range(3):
+            oracle.heat(u0_host, r, steps)
+            loops.append(oracle.last_loop_seconds())
+        return loops
+
+    def cg_runs(threads, iters):
+        oracle.set_threads(threads)
+        loops = []
+        for _ in range(3):
+            res = oracle.cg(b_host, 1e-30, iters)
+            assert res.iters == iters
+            loops.append(oracle.last_loop_seconds())
+        return loops
+
+    out = {}
+    for label, threads, share in (("one_thread", 1, 0.4), ("all_cores", ncore, 0.6)):
+        # size each run from one probe step / iteration
+        per_step = max(statistics.median(heat_runs(threads, 1)), 1e-4)
+        steps = max(1, int(0.5 * share * budget_s / (3 * per_step)))
+        log("cpu baseline: heat %d steps x3 on %d thread(s)" % (steps, threads))
+        hl = heat_runs(threads, steps)
+        per_it = max(statistics.median(cg_runs(threads, 1)), 1e-4)
+        iters = max(1, int(0.5 * share * budget_s / (3 * per_it)))
+        log("cpu baseline: cg %d iterations x3 on %d thread(s)" % (iters, threads))
+        cl = cg_runs(threads, iters)
+        hmed, cmed = statistics.median(hl), statistics.median(cl)
+        out[label] = {
+            "threads": threads,
+            "heat_glups": steps * lups_per_step / hmed / 1e9,
+            "heat_steps_per_run": steps,
+            "heat_loop_s": hl,
+            "cg_s_per_iteration": cmed / iters,
+            "cg_iterations_per_run": iters,
+            "cg_loop_s": cl,
+            "cg_time_to_tol_s_extrapolated": cmed / iters * gpu_cg_iters,
+        }
+    allc = out["all_cores"]
     return {
-        "value": glups,
+        "value": allc["heat_glups"],
         "unit": "GLUP/s",
-        "cores": oracle.threads(),
+        "cores": ncore,
         "kind": "oracle",
-        "sample": ("heat: %d steps (the workload runs 1000) on the same 512^3 FP64 field "
-                   "(%.3g LUP, %.1f s; rate net of the call's fixed cost, taken as the time "
-                   "of a 2-step call); cg: %d iterations on the same 256^3 system (%.1f s, "
-                   "%.3f s/iteration net of a 1-iteration call, so about %.0f s for the "
-                   "GPU's %d iterations to 1e-10)"
-                   % (steps, steps * lups_per_step, heat_s, iters, cg_s, per_it,
-                      per_it * gpu_cg_iters, gpu_cg_iters)),
-        "cg_s_per_iteration": per_it,
+        "sample": ("heat: %d of the workload's 1000 steps on the same 512^3 FP64 field; cg: %d "
+                   "iterations on the same 256^3 system (the time to 1e-10 is extrapolated to "
+                   "the GPU's %d iterations); median of 3 runs, step / iteration loop timed "
+                   "only; all %d physical cores (value) and one thread"
+                   % (allc["heat_steps_per_run"], allc["cg_iterations_per_run"], gpu_cg_iters,
+                      ncore)),
+        "omp": {"OMP_PROC_BIND": os.environ.get("OMP_PROC_BIND"),
+                "OMP_PLACES": os.environ.get("OMP_PLACES")},
+        "host": info,
+        "runs": out,
+        "paper_context_glups": {
+            hw: {"kbar_s": k, "glups": 1.0 / k / 1e9,
+                 "workload": "FP64 variable-coefficient heat with a source, OpenMP offload, "
+                             "one device, tab:used-measurements"}
+            for hw, k in PAPER_KBAR},
     }
 
 
@@ -481,23 +574,105 @@ def vk_section(hc, dev):
     return res
 
 
+def kernels_section(hc, dev):
+    """Each hot kernel a few times, for profiler passes (kernel traces and
+    counters): the copy probe over two 1 GiB buffers, the two-step heat
+    sweep (split form) on the 512^3 FP64 field and on 1024^3 fields in FP64,
+    FP32 and bfloat16, the variable-coefficient sweep on the paper's 512^3
+    test case (FP64), the batched configuration (FP32, its default shape),
+    and 48 iterations of CG on the 256^3 system.  Prints each case's name,
+    grid and launches in dispatch order."""
+    import numpy as np
+    import torch
+    from paper_2608_11882_amd import inputs
+    out = []
+
+    def case(name, fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append({"case": name, "ms": round(e0.elapsed_time(e1), 3)})
+        log("kernels: %s %.3f ms" % (name, out[-1]["ms"]))
+
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        case("copy_probe 2 x 1 GiB", lambda: hc.copy_probe(a, b))
+    del a, b
+    hcfg = inputs.HEAT_LARGE
+    u0 = torch.from_numpy(inputs.heat_large_f64(seed=hcfg["seed"], n=hcfg["n"])).to(dev)
+    un = torch.empty_like(u0)
+    case("heat f64 512^3 x20", lambda: hc.heat_step(u0, un, hcfg["r"], 20))
+    del u0, un
+    torch.cuda.empty_cache()
+    for dt in ("f64", "f32", "bf16"):
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
+        n = 1024
+        u = torch.rand((n, n, n), dtype=torch.float32, device=dev).to(tdt)
+        for sl in (u[0], u[-1], u[:, 0], u[:, -1], u[:, :, 0], u[:, :, -1]):
+            sl.zero_()
+        un = torch.empty_like(u)
+        case("heat %s 1024^3 x8" % dt, lambda: hc.heat_step(u, un, 0.15, 8))
+        del u, un
+        torch.cuda.empty_cache()
+    pb = inputs.paper_problem(inputs.VARCOEF["n"])
+    u = torch.from_numpy(pb["u0"]).to(dev)
+    kap = torch.from_numpy(pb["kappa"]).to(dev)
+    rhs = torch.from_numpy(pb["rhs"]).to(dev)
+    un = torch.empty_like(u)
+    case("varcoef f64 512^3 x8", lambda: hc.heat_vk_step(u, un, kap, rhs, pb["beta"], 8))
+    del u, kap, rhs, un
+    torch.cuda.empty_cache()
+    cfg = inputs.BATCHED
+    dims, rs, rng = inputs.batched_problems(cfg["count"], cfg["lo"], cfg["hi"], cfg["seed"],
+                                            cfg["r_lo"], cfg["r_hi"])
+    fields = inputs.batched_fields(dims, rng, dtype=np.float32)
+    batch = hc.Batch(dims, rs, "f32")
+    bu, bn = batch.empty(dev), batch.empty(dev)
+    for v, f in zip(batch.views(bu), fields):
+        v.copy_(torch.from_numpy(f))
+    case("batch f32 256 problems x8 (direct launches)",
+         lambda: batch.step(bu, bn, 8, graph=False))
+    batch.close()
+    del bu, bn
+    ccfg = inputs.CG_LARGE
+    m = ccfg["n"]
+    xs = torch.from_numpy(inputs.manufactured_solution(m, seed=ccfg["seed"])).to(dev)
+    bb = torch.empty_like(xs)
+    hc.lap7_apply(xs, bb)
+    x = torch.zeros_like(bb)
+    case("cg f64 256^3 48 iterations", lambda: hc.cg_solve(bb, x, 1e-30, 48))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
                     help="CPU time budget of the oracle baseline (0 skips it)")
     ap.add_argument("--heat-steps", type=int, default=1000, help=argparse.SUPPRESS)
     ap.add_argument("--precision", type=int, default=1, help=argparse.SUPPRESS)
     # "batch": only the batched configuration; "batch-kernels": the same
     # without the 256 sequential single-problem solves (for counter passes)
-    ap.add_argument("--section", choices=("all", "batch", "batch-kernels"), default="all",
-                    help=argparse.SUPPRESS)
+    # "kernels": each hot kernel a few times (kernels_section), for profiler
+    # passes
+    ap.add_argument("--section", choices=("all", "batch", "batch-kernels", "kernels"),
+                    default="all", help=argparse.SUPPRESS)
     # the batch's shape (vec,threads,zdepth,pf,xcd,width_class,grid,item_depth)
     # instead of the autotuner's pick, for those sections
     ap.add_argument("--batch-shape", default=None, help=argparse.SUPPRESS)
+    # the CPU baseline's child process (no torch, no GPU)
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-cg-iters", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_child:
+        print(json.dumps(cpu_baseline_child(args.cpu_cg_iters, args.cpu_seconds)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -521,6 +696,9 @@ def main():
     hc.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.section == "kernels":
+        print(json.dumps({"kernels": kernels_section(hc, dev)}), flush=True)
+        return
     if args.section != "all":
         res = batch_section(hc, dev, sequential_solves=args.section == "batch", shape=shape)
         print(json.dumps({"batch_256_f32": res}), flush=True)
@@ -643,8 +821,7 @@ def main():
 
     cpu = None
     if args.cpu_seconds > 0:
-        b_host = b.cpu().numpy()
-        cpu = cpu_baseline(u0_host, r, b_host, cg_iters, args.cpu_seconds)
+        cpu = cpu_baseline(cg_iters, args.cpu_seconds)
 
     tiling = hc.tiling_for(u, un) if tb == 1 else hc.tiling2_for(u, un)
     out = {
