@@ -180,8 +180,9 @@ int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new,
  * Run length of the two-step constant-coefficient sweep, per dtype (HC_F64,
  * HC_F32, HC_BF16): the planes of output each block of the Interior (or
  * fused) kernel marches as one run, its register queues carried from one
- * z-block to the next.  0 (the default) is the automatic choice: one
- * z-block per block for HC_F64 and HC_F32, 128 planes for HC_BF16; other
+ * z-block to the next.  0 (the default) is the automatic choice: 64
+ * planes for HC_F64 when a plane has at most 256 tiles (else one z-block),
+ * one z-block for HC_F32, 128 planes for HC_BF16; other
  * values are rounded up to a multiple of the tile's zdepth.  Results do
  * not depend on it.
  * hc_heat2_set_zrun returns HC_EINVAL for another dtype or a value outside

@@ -182,9 +182,9 @@ hc::HeatTiling vk_tiling_for(int dtype, int nx, const void *const *arrays, int n
 // two-step sweep has tile shapes of its own, per storage precision; the
 // automatic candidates are the fastest of sweeps over the built ones at
 // 512^3 and 1024^3 on MI355X (tiles 256 nodes wide, 8 rows, z-blocks of 32
-// planes, slab order: at 1024^3 it cuts the reads the rings miss in L2,
-// 5-10% faster than runs of 8 y-tiles per XCD; at 512^3 the two orders
-// measured alike).
+// planes, slab order: on some boxes it cut the reads the rings miss in L2
+// at 1024^3, 5-10% faster than runs of 8 y-tiles per XCD; elsewhere the two
+// orders measured within 1-2%).
 int g_time_block = 2;
 hc::HeatTiling g_tiling2[3] = {};
 const hc::HeatTiling kAuto2[3][5] = {
@@ -227,21 +227,27 @@ hc::HeatTiling heat2_tiling_for(int dtype, int nx, const void *u, const void *un
 // Planes of output per block of the two-step constant-coefficient sweep
 // (its Interior and fused kernels march them as one run), set per dtype;
 // 0 is the automatic choice kAutoZrun, where 0 means one z-block per block.
-// Measured on MI355X at 512^3 and 1024^3: for FP64 and FP32 runs of two to
-// four z-blocks were no faster than one and longer runs slower; the
-// bfloat16 sweep, bound by its vector ALU work, gains 5-8% from runs of 128
-// planes (fewer pipeline fills, each of which computes two planes of
-// u^(t+1) twice).
+// Measured on MI355X (interleaved A/B on one box): FP64 runs of two
+// z-blocks (64 planes) were 3% faster than one at 512^3, where a plane has
+// 128 tiles of 256 x 8 and a column 16 z-blocks, but 5% slower at 1024^3
+// (512 tiles a plane), so the automatic choice takes them only for planes
+// of at most 256 tiles; FP32 measured alike within noise; the bfloat16
+// sweep, bound by its vector ALU work, gains 5-8% from runs of 128 planes
+// (fewer pipeline fills, each of which computes two planes of u^(t+1)
+// twice).
 int g_heat2_zrun[3] = {0, 0, 0};
-constexpr int kAutoZrun[3] = {0, 0, 128};
 
-int heat2_zrun(int dtype, const hc::HeatTiling &t) {
+int heat2_zrun(int dtype, const hc::HeatTiling &t, int nx, int ny) {
     int zr;
     {
         std::lock_guard<std::mutex> g(g_tiling_mu);
         zr = g_heat2_zrun[dtype];
     }
-    if (zr <= 0) zr = kAutoZrun[dtype];
+    if (zr <= 0) {
+        const long long w = hc::tile_width(t);
+        const long long tiles = ((nx + w - 1) / w) * ((ny - 2 + t.by - 1) / t.by);
+        zr = dtype == hc::kDtypeBF16 ? 128 : (dtype == hc::kDtypeF64 && tiles <= 256) ? 64 : 0;
+    }
     const int zb = t.zdepth;
     return zr <= 0 ? zb : (zr + zb - 1) / zb * zb;
 }
@@ -578,7 +584,7 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                 slab(nz, parts, q, &a, &b);
                 if (b - a + 1 >= 5)
                     push_range(tin2, a + 2, b - 2,
-                               vk ? til2.zdepth : heat2_zrun(dtype, til2));
+                               vk ? til2.zdepth : heat2_zrun(dtype, til2, nx, ny));
             }
             for (int q = 0; q < parts; ++q) {
                 int a, b;
@@ -591,7 +597,7 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                 }
             }
         } else {
-            push_range(tin2, 1, nz - 2, vk ? til2.zdepth : heat2_zrun(dtype, til2));
+            push_range(tin2, 1, nz - 2, vk ? til2.zdepth : heat2_zrun(dtype, til2, nx, ny));
         }
         if (hc::heat_tile_blocks(nx, ny, til2, tin2) > 2147483647LL ||
             hc::heat_tile_blocks(nx, ny, til2, tbd2) > 2147483647LL)
