@@ -193,13 +193,19 @@ struct BoxGeom {
 
 // Walk the block's tile through its z-block.
 //
-//  field.template load<V>(k, off, out)  V field values (type T) from the
-//                        in-box node at byte offset `off` of plane k
-//                        (clamped offsets; loads unconditional)
+//  field.template fetch<V>(k, off, raw)  the loads behind V field values
+//                        at the in-box node at byte offset `off` of plane k
+//                        (clamped offsets; loads unconditional), into a
+//                        Field::Raw<V>
+//  field.template make<V>(raw, out)  the V values (type T) from them
 //  epi.prefetch(k, off)  the epilogue's own loads for a plane, as Epi::Pre
 //  epi.finish(ok, lane_in, k, off, sink, c, nsum, pre)  own nodes: field
 //                        values, ordered neighbour sums (type T),
 //                        prefetched values; ok[v] false off the box
+//  gate()                called by every thread once the first planes'
+//                        loads are out (the block's scalars, which `make`
+//                        and `finish` may use, are formed meanwhile); the
+//                        march ends at once, returning false, when it does
 //
 // ZPAD: the field's arrays carry one zero plane below plane 0 and one above
 // plane nz-1, so planes -1 and nz are read from memory and no plane index
@@ -208,11 +214,12 @@ struct BoxGeom {
 // UNROLL: take the unrolled path for full-depth z-blocks (false keeps the
 // plain loop, for kernels that run once or twice per solve).
 template <class T, int VEC, int WX, int BY, int ZB, bool ZPAD, bool UNROLL = true,
-          class Field, class Epi>
-__device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
-                                           double *sink, Field &field, Epi &epi) {
+          bool EARLY = false, class Field, class Epi, class Gate>
+__device__ __forceinline__ bool box_zmarch(int nx, int ny, int nz, int xcd, double *sink,
+                                           Field &field, Epi &epi, Gate &gate) {
     using G = BoxGeom<T, VEC, WX, BY>;
     using Pre = typename Epi::Pre;
+    using Raw = typename Field::template Raw<VEC>;
     static_assert(G::NT * VEC * sizeof(T) <= kSinkDoubles * sizeof(double),
                   "sink holds one slot per lane");
     __shared__ T tile[(BY + 2) * G::LD];
@@ -222,27 +229,37 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
     double *const lane_sink = reinterpret_cast<double *>(
         reinterpret_cast<char *>(sink) + (long long)threadIdx.x * VEC * sizeof(T));
 
+    auto kclamp = [&](int k) { return ZPAD ? k : max(0, min(k, nz - 1)); };
+    auto kinside = [&](int k) { return ZPAD || ((k >= 0) && (k < nz)); };
     // column values of plane k (0 outside the box)
-    auto col = [&](int k, T *o) {
-        const int kc = ZPAD ? k : max(0, min(k, nz - 1));
-        const bool kin = ZPAD || ((k >= 0) && (k < nz));
+    auto col_make = [&](int k, const Raw &raw, T *o) {
         T v[VEC];
-        field.template load<VEC>(kc, g.own_b, v);
+        field.template make<VEC>(raw, v);
+        const bool kin = kinside(k);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) o[e] = (kin && g.in[e]) ? v[e] : T(0);
     };
+    auto col = [&](int k, T *o) {
+        Raw raw;
+        field.template fetch<VEC>(kclamp(k), g.own_b, raw);
+        col_make(k, raw, o);
+    };
     // one aligned VEC-wide load in every lane; a column node is picked out
-    auto ringv = [&](int k, T *o) {
-        const int kc = ZPAD ? k : max(0, min(k, nz - 1));
-        const bool kin = ZPAD || ((k >= 0) && (k < nz));
+    auto ring_make = [&](int k, const Raw &raw, T *o) {
         T v[VEC];
-        field.template load<VEC>(kc, g.ring_b, v);
+        field.template make<VEC>(raw, v);
         T sel = v[0];
 #pragma unroll
         for (int e = 1; e < VEC; ++e) sel = (g.rsel == e) ? v[e] : sel;
         v[0] = sel;
+        const bool kin = kinside(k);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) o[e] = (kin && g.rin[e]) ? v[e] : T(0);
+    };
+    auto ringv = [&](int k, T *o) {
+        Raw raw;
+        field.template fetch<VEC>(kclamp(k), g.ring_b, raw);
+        ring_make(k, raw, o);
     };
     auto put = [&](const T *c, const T *rv) {
 #pragma unroll
@@ -276,8 +293,16 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
         T q[ZB + 2][VEC];  // q[s]: column at plane kb-1+s
         T rg[ZB][VEC];     // ring values of plane kb+s
         Pre pre[ZB];
+        {
+            Raw q0[kPF + 2];
+            if (!EARLY && !gate()) return false;
 #pragma unroll
-        for (int s = 0; s < kPF + 2; ++s) col(kb - 1 + s, q[s]);
+            for (int s = 0; s < kPF + 2; ++s)
+                field.template fetch<VEC>(kclamp(kb - 1 + s), g.own_b, q0[s]);
+            if (EARLY && !gate()) return false;
+#pragma unroll
+            for (int s = 0; s < kPF + 2; ++s) col_make(kb - 1 + s, q0[s], q[s]);
+        }
 #pragma unroll
         for (int s = 0; s < kPF; ++s) ringv(kb + s, rg[s]);
 #pragma unroll
@@ -294,9 +319,10 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
             epi.finish(g.in, g.lane_in, kb + s, g.own_b, lane_sink, q[s + 1], ns, pre[s]);
             if (s + 2 + kPF <= ZB + 1) col(kb + s + 1 + kPF, q[s + 2 + kPF]);
         }
-        return;
+        return true;
     }
 
+    if (!gate()) return false;
     T zm[VEC], c[VEC], zp[VEC], rc[VEC];
     col(kb - 1, zm);
     col(kb, c);
@@ -321,6 +347,7 @@ __device__ __forceinline__ void box_zmarch(int nx, int ny, int nz, int xcd,
             rc[e] = rn[e];
         }
     }
+    return true;
 }
 
 // Fixed-order block sum; the result is valid in thread 0.
@@ -401,12 +428,39 @@ __device__ __forceinline__ double gather(const double *partial, int nsum, int q)
 }
 
 // The same fixed-order sum of the nb partials a previous kernel stored,
-// taken in every block of a later one (result in every thread).
+// taken in every block of a later one (result in every thread), and the
+// solve's state, read once for the block as block_state does.  A thread
+// issues its loads of partials eight at a time, so the block waits about one
+// memory latency per eight partials instead of one per partial (blocks on
+// the other XCDs wrote most of them, so they come from beyond this XCD's
+// L2); the adds keep the index order, so the sum's bits do not depend on
+// the unrolling.
 template <int NT>
-__device__ __forceinline__ double sum_partials(const double *part, int nb) {
+__device__ __forceinline__ double sum_partials(const CGScalars *sc, const double *part, int nb,
+                                               int *state) {
+    __shared__ double total;
+    __shared__ int st;
+    // the state's load goes out first, to wait alongside the partials'
+    const int s0 = threadIdx.x == 0 ? load_state(sc) : 0;
     double t = 0.0;
-    for (int b = threadIdx.x; b < nb; b += NT) t += part[b];
-    return block_sum_all<NT>(t);
+    int b = threadIdx.x;
+    for (; b + 7 * NT < nb; b += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[b + q * NT];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += v[q];
+    }
+    for (; b < nb; b += NT) t += part[b];
+    if (threadIdx.x == 0) st = s0;
+    // block_sum's first barrier orders the write of st before its reads
+    const double s = block_sum<NT>(t);
+    if (threadIdx.x == 0) total = s;
+    __syncthreads();
+    const double r = total;
+    *state = st;
+    __syncthreads();
+    return r;
 }
 
 // Iteration k's direction scalars.  On the first iteration of a (re)start
@@ -417,13 +471,15 @@ __device__ __forceinline__ double sum_partials(const double *part, int nb) {
 template <int NT>
 __device__ __forceinline__ bool direction_scalars(CGScalars *sc, const double *part_u, int nb,
                                                   int k, int first, double *beta) {
-    if (block_state(sc) != 0) return false;
     if (first) {
+        if (block_state(sc) != 0) return false;
         if (blockIdx.x == 0 && threadIdx.x == 0) sc->rslot[k & 1] = sc->rho;
         *beta = 0.0;
         return true;
     }
-    const double rho = sum_partials<NT>(part_u, nb);
+    int st0;
+    const double rho = sum_partials<NT>(sc, part_u, nb, &st0);
+    if (st0 != 0) return false;
     const double rho_old = sc->rslot[(k + 1) & 1];
     int state = 0;
     if (!isfinite(rho))
@@ -447,8 +503,9 @@ __device__ __forceinline__ bool direction_scalars(CGScalars *sc, const double *p
 template <int NT>
 __device__ __forceinline__ bool update_scalars(CGScalars *sc, const double *part_d, int nb,
                                                int k, double *alpha) {
-    if (block_state(sc) != 0) return false;
-    const double pap = sum_partials<NT>(part_d, nb);
+    int st0;
+    const double pap = sum_partials<NT>(sc, part_d, nb, &st0);
+    if (st0 != 0) return false;
     const double rho = sc->rslot[k & 1];
     int state = 0;
     if (!isfinite(pap))
@@ -493,8 +550,17 @@ struct PlainField {
     const T *__restrict__ x;
     long long plane;
     template <int V>
-    __device__ void load(int k, unsigned off, T *out) const {
-        load_vec<T, V>(node(x, plane, k, off), out);
+    struct Raw {
+        T x[V];
+    };
+    template <int V>
+    __device__ void fetch(int k, unsigned off, Raw<V> &o) const {
+        load_vec<T, V>(node(x, plane, k, off), o.x);
+    }
+    template <int V>
+    __device__ void make(const Raw<V> &o, T *out) const {
+#pragma unroll
+        for (int e = 0; e < V; ++e) out[e] = o.x[e];
     }
 };
 
@@ -507,13 +573,24 @@ struct DirectionField {
     T beta;
     int first;
     template <int V>
-    __device__ void load(int k, unsigned off, T *out) const {
-        T rv[V], pv[V];
-        load_vec<T, V>(node(r, plane, k, off), rv);
-        load_vec<T, V>(node(p, plane, k, off), pv);
-#pragma unroll
-        for (int e = 0; e < V; ++e) out[e] = first ? rv[e] : rv[e] + beta * pv[e];
+    struct Raw {
+        T r[V], p[V];
+    };
+    template <int V>
+    __device__ void fetch(int k, unsigned off, Raw<V> &o) const {
+        load_vec<T, V>(node(r, plane, k, off), o.r);
+        load_vec<T, V>(node(p, plane, k, off), o.p);
     }
+    template <int V>
+    __device__ void make(const Raw<V> &o, T *out) const {
+#pragma unroll
+        for (int e = 0; e < V; ++e) out[e] = first ? o.r[e] : o.r[e] + beta * o.p[e];
+    }
+};
+
+// The gate of kernels whose march needs no scalars.
+struct Open {
+    __device__ bool operator()() const { return true; }
 };
 
 struct NoPre {
@@ -664,7 +741,8 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_residual_f64(
     const long long plane = (long long)nx * ny;
     PlainField<double> f{x, plane};
     ResidualEpi<VEC> epi{b, r, plane};
-    box_zmarch<double, VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi);
+    Open open;
+    box_zmarch<double, VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi, open);
     double v[2];
     v[0] = block_sum<NT>(epi.rr);
     v[1] = block_sum<NT>(epi.bb);
@@ -700,7 +778,8 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_ir_residual(
     const long long plane = (long long)nx * ny;
     PlainField<double> f{x, plane};
     IRResidualEpi<VEC> epi{b, s, plane};
-    box_zmarch<double, VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi);
+    Open open;
+    box_zmarch<double, VEC, WX, BY, ZB, false, false>(nx, ny, nz, xcd, sink, f, epi, open);
     double v[3];
     v[0] = block_sum<NT>(epi.rr);
     v[1] = block_sum<NT>(epi.ss);
@@ -735,12 +814,18 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_direction(
     CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int first, int k) {
     constexpr int NT = 64 * WX * BY;
     const int nb = (int)gridDim.x;
-    double beta;
-    if (!direction_scalars<NT>(sc, partial + nb, nb, k, first, &beta)) return;
     const long long plane = (long long)nx * ny;
-    DirectionField<T> f{r, first ? r : pold, plane, first ? T(0) : (T)beta, first};
+    DirectionField<T> f{r, first ? r : pold, plane, T(0), first};
     DirectionEpi<T, VEC> epi{pnew, plane};
-    box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
+    // beta is formed while the first planes' loads are out
+    auto gate = [&]() {
+        double beta;
+        if (!direction_scalars<NT>(sc, partial + nb, nb, k, first, &beta)) return false;
+        f.beta = first ? T(0) : (T)beta;
+        return true;
+    };
+    if (!box_zmarch<T, VEC, WX, BY, ZB, true, true, true>(nx, ny, nz, xcd, sink, f, epi, gate))
+        return;
     const double v = block_sum<NT>(epi.acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
@@ -751,12 +836,17 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_update(
     CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int k) {
     constexpr int NT = 64 * WX * BY;
     const int nb = (int)gridDim.x;
-    double alpha;
-    if (!update_scalars<NT>(sc, partial, nb, k, &alpha)) return;
     const long long plane = (long long)nx * ny;
     PlainField<T> f{p, plane};
-    UpdateEpi<T, VEC> epi{x, r, plane, (T)alpha};
-    box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi);
+    UpdateEpi<T, VEC> epi{x, r, plane, T(0)};
+    // alpha is formed while the first planes' loads are out
+    auto gate = [&]() {
+        double alpha;
+        if (!update_scalars<NT>(sc, partial, nb, k, &alpha)) return false;
+        epi.alpha = (T)alpha;
+        return true;
+    };
+    if (!box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi, gate)) return;
     const double v = block_sum<NT>(epi.acc);
     if (threadIdx.x == 0) partial[nb + blockIdx.x] = v;
 }
@@ -778,7 +868,8 @@ __global__ __launch_bounds__(64 * WX * BY) void lap7(
     const long long plane = (long long)nx * ny;
     PlainField<T> f{x, plane};
     Lap7Epi<T, VEC> epi{y, plane};
-    box_zmarch<T, VEC, WX, BY, ZB, false>(nx, ny, nz, xcd, sink, f, epi);
+    Open open;
+    box_zmarch<T, VEC, WX, BY, ZB, false>(nx, ny, nz, xcd, sink, f, epi, open);
 }
 
 // x += d (binary64 += widened binary32), four nodes per thread
