@@ -255,6 +255,13 @@ int hc_heat_vk2_tiling_for(int dtype, int nx, const void *u, const void *u_new,
                            const void *kappa, const void *rhs, int *vec,
                            int *wx, int *by, int *zdepth, int *pf, int *xcd);
 
+/* Run length of the two-step variable-coefficient sweep, per dtype (HC_F64,
+ * HC_F32), with hc_heat2_set_zrun's meaning and errors: 0 (the default) is
+ * the automatic choice, 256 planes; other values are rounded up to a
+ * multiple of the tile's zdepth.  Results do not depend on it. */
+int hc_heat_vk2_set_zrun(int dtype, int planes);
+int hc_heat_vk2_get_zrun(int dtype);
+
 /*
  * cg_solve -- solve A x = b with Conjugate Gradient (the CG case study),
  * A the 7-point Laplacian 6 I - (face neighbours) on an n x n x n box with
@@ -574,8 +581,10 @@ const char *hc_last_error_message(void);
 
 /*
  * Kernel timing for measurement.  hc_prof_enable(every) with every >= 1
- * clears the counters and from then on brackets every `every`-th launch of
- * each kernel kind with HIP events on the stream it runs on (the events cost
+ * clears the counters and from then on brackets one launch in every `every`
+ * of each kernel kind (the middle one of each group, so that no timed CG
+ * launch follows the solver's periodic wait for the host) with HIP events
+ * on the stream it runs on (the events cost
  * a few microseconds of GPU time each, so sampling keeps the measured run
  * close to an unmeasured one), adding up the algorithmic bytes each timed
  * launch must move; every = 0 stops timing.  hc_prof_read waits for the

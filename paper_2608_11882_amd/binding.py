@@ -21,7 +21,7 @@ __all__ = ["HeatCGError", "load", "abi", "library_path", "heat_step", "heat_step
            "Batch", "heat_vk_step", "set_vk_tiling", "get_vk_tiling", "vk_tiling_for",
            "set_time_block", "get_time_block", "set_tiling2", "get_tiling2", "tiling2_for",
            "set_vk2_tiling", "get_vk2_tiling", "vk2_tiling_for", "cg_solve_noalloc",
-           "set_zrun2", "get_zrun2",
+           "set_zrun2", "get_zrun2", "set_vk2_zrun", "get_vk2_zrun",
            "CG_NOALLOC_BYTES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -113,6 +113,8 @@ def load():
         "hc_heat_vk2_set_tiling": (i, [i, i, i, i, i, i, i]),
         "hc_heat_vk2_get_tiling": (i, [i, ip, ip, ip, ip, ip, ip]),
         "hc_heat_vk2_tiling_for": (i, [i, i, vp, vp, vp, vp, ip, ip, ip, ip, ip, ip]),
+        "hc_heat_vk2_set_zrun": (i, [i, i]),
+        "hc_heat_vk2_get_zrun": (i, [i]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -468,6 +470,16 @@ def get_vk2_tiling(dtype: str = "f64") -> dict:
     v = [ctypes.c_int(0) for _ in range(6)]
     _check(load().hc_heat_vk2_get_tiling(DTYPES[dtype], *[ctypes.byref(x) for x in v]))
     return dict(zip(_TILE_KEYS, (x.value for x in v)))
+
+
+def set_vk2_zrun(planes: int = 0, dtype: str = "f64") -> None:
+    """Output planes per block of the two-step variable-coefficient sweep
+    (0: automatic)."""
+    _check(load().hc_heat_vk2_set_zrun(DTYPES[dtype], int(planes)))
+
+
+def get_vk2_zrun(dtype: str = "f64") -> int:
+    return _check(load().hc_heat_vk2_get_zrun(DTYPES[dtype]))
 
 
 def vk2_tiling_for(u, u_new, kappa, rhs) -> dict:

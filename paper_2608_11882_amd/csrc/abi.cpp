@@ -121,13 +121,18 @@ const hc::HeatTiling kVkAuto[2][4] = {
 };
 
 // Two-step variable-coefficient sweep: shapes of its own, per precision;
-// the automatic one is the fastest of a sweep over the built ones at 512^3
-// on MI355X (16-byte lanes, tiles 128 nodes wide and 4 rows tall, one plane
-// of loads ahead: the register queues of u and kappa are long).
+// the automatic one is the fastest of a sweep over the built ones (with run
+// lengths and block orders) at 512^3 on MI355X: 16-byte lanes, one plane of
+// loads ahead (the register queues of u and kappa are long: about 200
+// VGPRs, two wavefronts per SIMD), FP64 tiles 128 nodes wide and 8 rows
+// tall (512 threads, the most that two wavefronts per SIMD allow; half the
+// y-ring per node of 4-row tiles: 7% faster at runs of 256 planes); FP32
+// tiles 256 x 4 with two planes of loads ahead in slab order (19% faster
+// than the one-z-block, one-plane-ahead shape before the runs).
 hc::HeatTiling g_vk2_tiling[2] = {};
 const hc::HeatTiling kVk2Auto[2][2] = {
-    {{2, 1, 4, 32, 1, 8}, {}},
-    {{4, 1, 4, 32, 1, 8}, {}},
+    {{2, 1, 8, 32, 1, 8}, {}},
+    {{4, 1, 4, 32, 2, -1}, {}},
 };
 
 hc::HeatTiling vk2_tiling_for(int dtype, int nx, const void *const *arrays, int narrays) {
@@ -248,6 +253,24 @@ int heat2_zrun(int dtype, const hc::HeatTiling &t, int nx, int ny) {
         const long long tiles = ((nx + w - 1) / w) * ((ny - 2 + t.by - 1) / t.by);
         zr = dtype == hc::kDtypeBF16 ? 128 : (dtype == hc::kDtypeF64 && tiles <= 256) ? 64 : 0;
     }
+    const int zb = t.zdepth;
+    return zr <= 0 ? zb : (zr + zb - 1) / zb * zb;
+}
+
+// The same for the two-step variable-coefficient sweep (FP64, FP32).
+// Measured on MI355X at the paper's 512^3 case: FP64 (128 x 8 tiles) runs
+// of 256 planes 4.4% faster than one z-block, 128 planes 3.1%, whole
+// columns 2.7%; FP32 (256 x 4 tiles) 256 planes 11% faster, 128 planes 9%;
+// 256 planes is the automatic choice for both.
+int g_vk2_zrun[2] = {0, 0};
+
+int vk2_zrun(int dtype, const hc::HeatTiling &t) {
+    int zr;
+    {
+        std::lock_guard<std::mutex> g(g_tiling_mu);
+        zr = g_vk2_zrun[dtype];
+    }
+    if (zr <= 0) zr = 256;
     const int zb = t.zdepth;
     return zr <= 0 ? zb : (zr + zb - 1) / zb * zb;
 }
@@ -408,7 +431,10 @@ class Timed {
         if (!allowed) return;
         std::lock_guard<std::mutex> g(g_prof_mu);
         if (!g_prof_on) return;
-        if (g_prof_seen[kind]++ % g_prof_every != 0) return;
+        // the middle launch of every group of g_prof_every: the CG loop
+        // waits for the host after every 16th iteration, and a launch right
+        // after such a wait would time the host's enqueue too
+        if (g_prof_seen[kind]++ % g_prof_every != g_prof_every / 2) return;
         a_ = pool_event();
         b_ = pool_event();
         if (a_ && b_ && hipEventRecord(a_, s_) == hipSuccess) on_ = true;
@@ -572,7 +598,7 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     // nearest rounding, z-marching forms); a last odd step takes one pass
     const bool two = dtype != hc::kDtypeBF16SR && mode != HC_HEAT_PLAIN && steps >= 2 &&
                      current_time_block() == 2;
-    hc::HeatTiling til2 = {};
+    hc::HeatTiling til2 = {}, til2b = {};
     hc::ZTable tin2 = empty_table(), tbd2 = empty_table();
     double bytes_in2 = 0.0, bytes_bd2 = 0.0;
     if (two) {
@@ -584,7 +610,7 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                 slab(nz, parts, q, &a, &b);
                 if (b - a + 1 >= 5)
                     push_range(tin2, a + 2, b - 2,
-                               vk ? til2.zdepth : heat2_zrun(dtype, til2, nx, ny));
+                               vk ? vk2_zrun(dtype, til2) : heat2_zrun(dtype, til2, nx, ny));
             }
             for (int q = 0; q < parts; ++q) {
                 int a, b;
@@ -597,10 +623,18 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                 }
             }
         } else {
-            push_range(tin2, 1, nz - 2, vk ? til2.zdepth : heat2_zrun(dtype, til2, nx, ny));
+            push_range(tin2, 1, nz - 2, vk ? vk2_zrun(dtype, til2) : heat2_zrun(dtype, til2, nx, ny));
         }
+        // The Boundary kernel of the constant-coefficient split form sweeps
+        // its planes with 64 x 4 tiles of one-node lanes (256 threads, at most
+        // 64 VGPRs, 13 KB of LDS): such a block fits on a CU beside a block of
+        // the Interior kernel, so the Boundary kernel runs in what the
+        // Interior blocks leave free instead of holding whole CUs of its own
+        // while the two kernels share the chip.
+        if (!vk) til2b = {1, 1, 4, 16, 2, 8};
+        else til2b = til2;
         if (hc::heat_tile_blocks(nx, ny, til2, tin2) > 2147483647LL ||
-            hc::heat_tile_blocks(nx, ny, til2, tbd2) > 2147483647LL)
+            hc::heat_tile_blocks(nx, ny, til2b, tbd2) > 2147483647LL)
             return fail(HC_EINVAL, "grid too large for this tile shape");
         bytes_in2 = fields * tile_algo_bytes(tin2, nx, ny, nz, eb, 2);
         bytes_bd2 = fields * tile_algo_bytes(tbd2, nx, ny, nz, eb, 2);
@@ -610,9 +644,9 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     const hc::KernelKind k2_bd = vk ? hc::K_VK2_BOUNDARY : hc::K_HEAT2_BOUNDARY;
     auto tile2_launch = [&](hc::KernelKind kind, const hc::ZTable &zt, const void *a, void *b,
                             hipStream_t st) {
-        return vk ? hc::launch_heat_vk2_tile(dtype, kind, a, kap, rhs, b, nx, ny, nz, r, zt, til2,
-                                             st)
-                  : hc::launch_heat2_tile(dtype, kind, a, b, nx, ny, nz, r, zt, til2, st);
+        const hc::HeatTiling &t = kind == k2_bd ? til2b : til2;
+        return vk ? hc::launch_heat_vk2_tile(dtype, kind, a, kap, rhs, b, nx, ny, nz, r, zt, t, st)
+                  : hc::launch_heat2_tile(dtype, kind, a, b, nx, ny, nz, r, zt, t, st);
     };
 
     HC_TRY(hc::launch_copy_faces((int)eb, u, un, nx, ny, nz, s), "copy_faces launch");
@@ -1601,6 +1635,24 @@ int hc_heat2_get_zrun(int dtype) {
         return fail(HC_EINVAL, "dtype %d has no two-step sweep", dtype);
     std::lock_guard<std::mutex> g(g_tiling_mu);
     return g_heat2_zrun[dtype];
+}
+
+int hc_heat_vk2_set_zrun(int dtype, int planes) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d has no two-step variable-coefficient sweep", dtype);
+    if (planes < 0 || planes > (1 << 20)) return fail(HC_EINVAL, "zrun = %d out of range", planes);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    g_vk2_zrun[dtype] = planes;
+    return HC_OK;
+}
+
+int hc_heat_vk2_get_zrun(int dtype) {
+    g_msg.clear();
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_EINVAL, "dtype %d has no two-step variable-coefficient sweep", dtype);
+    std::lock_guard<std::mutex> g(g_tiling_mu);
+    return g_vk2_zrun[dtype];
 }
 
 int hc_heat2_tiling_for(int dtype, int nx, const void *u, const void *u_new, int *vec, int *wx,

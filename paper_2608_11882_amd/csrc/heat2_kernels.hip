@@ -10,9 +10,16 @@
 namespace hc {
 namespace {
 
+// Blocks of one-node lanes in 64 x 4 tiles are held to 64 VGPRs (eight
+// wavefronts per SIMD), so that one fits on a CU beside a block of the
+// widest shapes (1024 threads of at most 112 VGPRs each take 448 of a SIMD
+// lane's 512): the split form's Boundary kernel runs in that room.
+template <int VEC, int WX, int BY>
+constexpr int kMinWaves = (VEC == 1 && WX == 1 && BY == 4) ? 8 : 1;
+
 #define HC_HEAT2_KERNEL(NAME)                                                               \
     template <class P, int VEC, int WX, int BY, int PF, int ZB>                             \
-    __global__ __launch_bounds__(64 * WX * BY) void NAME(                                   \
+    __global__ __launch_bounds__(64 * WX * BY, (kMinWaves<VEC, WX, BY>)) void NAME(         \
         const typename P::S *__restrict__ u, typename P::S *__restrict__ un, int nx,        \
         int ny, int nz, typename P::C r, ZTable zt, int ntx, int nty, int xcd) {            \
         using G = TileGeom2<VEC, 64 * WX, BY>;                                              \
@@ -32,18 +39,20 @@ HC_HEAT2_KERNEL(heat2_fused)
 
 // Tile shapes built for the two-step sweep, per precision:
 // X(vec, wx, by, pf, zdepth).  (1, 4, 4, 2, 16) is the fallback for arrays
-// that do not allow wide lanes.
+// that do not allow wide lanes; (1, 1, 4, 2, 16) is the Boundary kernel's
+// shape in the split form.
 #define HC_HEAT2_SHAPES_F64(X)                                                    \
     X(1, 4, 4, 2, 16) X(2, 1, 8, 2, 32) X(2, 1, 16, 2, 16) X(2, 2, 4, 2, 32)     \
     X(2, 2, 8, 2, 16) X(2, 2, 8, 2, 32) X(2, 4, 4, 2, 16) X(2, 2, 4, 2, 64)      \
-    X(2, 2, 4, 3, 32) X(2, 1, 8, 2, 64) X(2, 1, 4, 2, 32)
+    X(2, 2, 4, 3, 32) X(2, 1, 8, 2, 64) X(2, 1, 4, 2, 32) X(1, 1, 4, 2, 16)
 #define HC_HEAT2_SHAPES_F32(X)                                                    \
     X(1, 4, 4, 2, 16) X(2, 2, 8, 2, 16) X(4, 1, 8, 2, 32) X(4, 1, 16, 2, 16)     \
     X(4, 2, 4, 2, 32) X(4, 2, 8, 2, 16) X(4, 2, 4, 2, 64) X(4, 1, 8, 2, 64)      \
-    X(4, 2, 4, 3, 32) X(4, 1, 4, 2, 32)
+    X(4, 2, 4, 3, 32) X(4, 1, 4, 2, 32) X(1, 1, 4, 2, 16)
 #define HC_HEAT2_SHAPES_BF16(X)                                                   \
     X(1, 4, 4, 2, 16) X(4, 1, 16, 2, 16) X(4, 1, 8, 2, 32) X(8, 1, 8, 2, 16)     \
-    X(8, 1, 4, 2, 32) X(4, 1, 8, 2, 64) X(4, 2, 4, 2, 32) X(4, 1, 4, 2, 32)
+    X(8, 1, 4, 2, 32) X(4, 1, 8, 2, 64) X(4, 2, 4, 2, 32) X(4, 1, 4, 2, 32)      \
+    X(1, 1, 4, 2, 16)
 
 #define HC_HEAT2_KEY(V, W, B, P, Z) ((((V * 8 + W) * 32 + B) * 8 + P) * 128 + Z)
 

@@ -17,8 +17,8 @@ namespace {
         const typename P::S *__restrict__ rhs, typename P::S *__restrict__ un, int nx,        \
         int ny, int nz, typename P::C beta, ZTable zt, int ntx, int nty, int xcd) {           \
         using G = TileGeom2<VEC, 64 * WX, BY>;                                                \
-        __shared__ typename P::C tu[G::U_ELEMS];                                              \
-        __shared__ typename P::C tk[2 * G::U_ELEMS];                                          \
+        __shared__ typename P::C tu[2 * G::U_ELEMS];                                          \
+        __shared__ typename P::C tk[4 * G::U_ELEMS];                                          \
         __shared__ typename P::C ta[2 * G::A_ELEMS];                                          \
         const auto g = block_tile2<VEC, 64 * WX, BY>(nx, ny, nz, zt, ntx, nty, xcd, ZB);      \
         vk_tile_sweep2<P, VEC, 64 * WX, BY, PF, ZB>(u, kap, rhs, un, beta, g, tu, tk, ta);    \

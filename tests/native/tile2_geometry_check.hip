@@ -170,7 +170,7 @@ int main() {
     for (auto &d : dims) {
         const int nx = d[0], ny = d[1], nz = 7;
         int b = 0;
-        b += check<1, 256, 4>(nx, ny, nz);
+        b += check<1, 256, 4>(nx, ny, nz); b += check<1, 64, 4>(nx, ny, nz);
         if (nx % 2 == 0) { b += check<2, 64, 8>(nx, ny, nz); b += check<2, 64, 16>(nx, ny, nz); b += check<2, 128, 4>(nx, ny, nz);
                            b += check<2, 128, 8>(nx, ny, nz); b += check<2, 256, 4>(nx, ny, nz); }
         if (nx % 4 == 0) { b += check<4, 64, 8>(nx, ny, nz); b += check<4, 64, 16>(nx, ny, nz); b += check<4, 128, 4>(nx, ny, nz); b += check<4, 128, 8>(nx, ny, nz); }

@@ -324,6 +324,18 @@ def test_time_block_and_two_step_tiling_settings(lib):
     assert tiling_for(0, 512, ctypes.c_void_p(0x100008), b)[0] == 1
 
 
+def test_run_length_settings(lib):
+    for setter, getter, dtypes in ((lib.hc_heat2_set_zrun, lib.hc_heat2_get_zrun, (0, 1, 2)),
+                                   (lib.hc_heat_vk2_set_zrun, lib.hc_heat_vk2_get_zrun, (0, 1))):
+        for dt in dtypes:
+            assert getter(dt) == 0
+            assert setter(dt, -1) == HC_EINVAL and setter(dt, (1 << 20) + 1) == HC_EINVAL
+            assert setter(dt, 96) == HC_OK and getter(dt) == 96
+            assert setter(dt, 0) == HC_OK and getter(dt) == 0
+        assert setter(3, 64) == HC_EINVAL and getter(3) == HC_EINVAL
+    assert lib.hc_heat_vk2_set_zrun(2, 64) == HC_EINVAL     # bfloat16: no variable kappa
+
+
 def test_every_automatic_shape_is_a_built_shape(lib):
     """The automatic tile shape of every sweep, for widths that allow each
     lane width, is one the library is built with (a launch would refuse any

@@ -117,6 +117,26 @@ def test_every_built_two_step_shape_bitwise(two_steps, dtype):
         hc.set_tiling2(dtype=dtype)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_run_lengths_bitwise(two_steps, dtype):
+    """Blocks that march runs of several z-blocks (queues carried across,
+    the first sub-block started early to end on the run's last plane), and
+    whole columns, give the single steps' bits."""
+    hc = two_steps
+    dims = (130, 21, 150)     # 146 Interior planes: runs of every length end ragged
+    u0 = start(dims, 31, dtype)
+    want = reference(u0, 0.13, 6, dtype)
+    try:
+        for zrun in (1, 40, 64, 96, 1 << 20):
+            for mode in ("split", "fused"):
+                note("heat2 %s run of %d planes %s" % (dtype, zrun, mode))
+                hc.set_zrun2(zrun, dtype=dtype)
+                got = run(hc, u0, 0.13, 6, dtype, mode=mode)
+                assert np.array_equal(got, want), (zrun, mode)
+    finally:
+        hc.set_zrun2(0, dtype=dtype)
+
+
 def test_settings_and_fallback(two_steps):
     hc = two_steps
     assert hc.get_time_block() == 2

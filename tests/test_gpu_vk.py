@@ -154,6 +154,29 @@ def test_every_built_two_step_shape_bitwise(gpu, dtype):
         gpu.set_time_block(saved)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_step_run_lengths_bitwise(gpu, dtype):
+    """Runs of several z-blocks per block (kappa's four LDS planes keep
+    their rotation across sub-blocks) and whole columns."""
+    saved = gpu.get_time_block()
+    gpu.set_time_block(2)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    dims = (130, 21, 150)
+    u0, kappa, rhs = random_case(dims, seed=37, dtype=npdt)
+    ref = oracle.heat_vk if dtype == "f64" else oracle.heat_vk_f32
+    want = ref(u0, kappa, rhs, 0.04, 6)
+    try:
+        for zrun in (1, 40, 64, 96, 1 << 20):
+            for mode in ("split", "fused"):
+                note("vk2 %s run of %d planes %s" % (dtype, zrun, mode))
+                gpu.set_vk2_zrun(zrun, dtype=dtype)
+                got = gpu_vk(gpu, u0, kappa, rhs, 0.04, 6, mode=mode)
+                assert np.array_equal(got, want), (zrun, mode)
+    finally:
+        gpu.set_vk2_zrun(0, dtype=dtype)
+        gpu.set_time_block(saved)
+
+
 def test_tiling_for_reports_a_built_shape_and_odd_rows_fall_back(gpu):
     t = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")  # noqa: E731
     a = [t(8, 8, 512) for _ in range(4)]
