@@ -54,7 +54,8 @@ __device__ __forceinline__ void sweep_class(const typename P::S *u, typename P::
                                             typename P::C *tile) {
     using WC = WidthClass<NT, CLS>;
     if constexpr (WC::valid) {
-        const TileGeom<VEC, WC::lanes, WC::rows> g(pr.nx, pr.pitch, pr.ny, w.tx, w.ty, w.kb, w.ke);
+        const TileGeom<VEC, WC::lanes, WC::rows> g((int)threadIdx.x, pr.nx, pr.pitch, pr.ny, w.tx,
+                                                   w.ty, w.kb, w.ke);
         heat_tile_sweep<P, VEC, WC::lanes, WC::rows, PF, ZB>(
             u + pr.offset, un + pr.offset, (typename P::C)pr.r, g, SRKey{}, tile);
     }

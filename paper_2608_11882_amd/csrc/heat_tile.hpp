@@ -269,13 +269,14 @@ struct TileGeom {
     bool rvec;  // ring element is a VEC-wide row piece (else one node)
     int rsel;   // the node's index within the aligned VEC-wide ring load
 
-    // Tile (tx, ty) of an nx x ny plane with rows `pitch` apart (x-tiles of
-    // TX nodes from x = 0, y-tiles of BY rows from y = 1), planes kb_..ke_.
-    __device__ __forceinline__ TileGeom(int nx, int pitch, int ny, int tx, int ty, int kb_,
-                                        int ke_) {
+    // Thread t of the block that sweeps tile (tx, ty) of an nx x ny plane
+    // with rows `pitch` apart (x-tiles of TX nodes from x = 0, y-tiles of BY
+    // rows from y = 1), planes kb_..ke_ (host-callable, so that the offsets
+    // can be checked on the CPU).
+    __host__ __device__ TileGeom(int t, int nx, int pitch, int ny, int tx, int ty, int kb_,
+                                 int ke_) {
         kb = kb_;
         ke = ke_;
-        const int t = threadIdx.x;
         const int gl = t % TXL;      // lane index within the tile row
         const int wy = t / TXL;      // tile row
         const int i0 = tx * TX;
@@ -338,7 +339,8 @@ __device__ __forceinline__ TileGeom<VEC, TXL, BY> block_tile(int nx, int ny, con
     int k0 = zt.kb[rg] + (z - zt.first[rg]) * zt.depth[rg];
     if (zt.depth[rg] == zb_full && zt.ke[rg] - zt.kb[rg] + 1 >= zb_full)
         k0 = min(k0, zt.ke[rg] - zb_full + 1);
-    return TileGeom<VEC, TXL, BY>(nx, nx, ny, tx, ty, k0, min(k0 + zt.depth[rg] - 1, zt.ke[rg]));
+    return TileGeom<VEC, TXL, BY>((int)threadIdx.x, nx, nx, ny, tx, ty, k0,
+                                  min(k0 + zt.depth[rg] - 1, zt.ke[rg]));
 }
 
 // LDS values a tile of this shape stages (the plane and its ring).

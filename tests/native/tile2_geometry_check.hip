@@ -179,7 +179,9 @@ int main() {
         bad += b;
     }
     // batch width classes (rows padded to 16 bytes)
-    const int bd[][2] = {{32, 32}, {33, 40}, {61, 35}, {100, 99}, {129, 50}, {192, 192}, {37, 191}, {150, 33}};
+    const int bd[][2] = {{32, 32}, {33, 40}, {61, 35}, {100, 99}, {129, 50}, {192, 192}, {37, 191}, {150, 33},
+                         {28, 21}, {40, 9}, {64, 13}, {130, 17}, {97, 66}, {96, 30},
+                         {31, 20}, {103, 12}, {67, 9}};
     for (auto &d : bd) {
         const int nx = d[0], ny = d[1], nz = 6;
         int b = 0;
