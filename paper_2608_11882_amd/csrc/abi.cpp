@@ -189,11 +189,13 @@ hc::HeatTiling vk_tiling_for(int dtype, int nx, const void *const *arrays, int n
 // 512^3 and 1024^3 on MI355X (tiles 256 nodes wide, 8 rows, z-blocks of 32
 // planes, slab order: on some boxes it cut the reads the rings miss in L2
 // at 1024^3, 5-10% faster than runs of 8 y-tiles per XCD; elsewhere the two
-// orders measured within 1-2%).
+// orders measured within 1-2%).  FP64's widest tile keeps one plane of
+// loads ahead (94 VGPRs against 105 with two; 1.5% faster at 512^3, 0.5% at
+// 1024^3, in interleaved A/B); FP32 and bfloat16 ran 3-28% slower so.
 int g_time_block = 2;
 hc::HeatTiling g_tiling2[3] = {};
 const hc::HeatTiling kAuto2[3][5] = {
-    {{2, 2, 8, 32, 2, -1}, {2, 2, 4, 32, 2, -1}, {2, 1, 8, 32, 2, -1}, {1, 4, 4, 16, 2, 8}, {}},
+    {{2, 2, 8, 32, 1, -1}, {2, 2, 4, 32, 2, -1}, {2, 1, 8, 32, 2, -1}, {1, 4, 4, 16, 2, 8}, {}},
     {{4, 1, 8, 32, 2, -1}, {4, 2, 4, 32, 2, -1}, {4, 1, 4, 32, 2, -1}, {1, 4, 4, 16, 2, 8}, {}},
     {{4, 1, 8, 32, 2, -1}, {4, 1, 4, 32, 2, -1}, {1, 4, 4, 16, 2, 8}, {}, {}},
 };

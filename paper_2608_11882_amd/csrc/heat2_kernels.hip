@@ -44,7 +44,8 @@ HC_HEAT2_KERNEL(heat2_fused)
 #define HC_HEAT2_SHAPES_F64(X)                                                    \
     X(1, 4, 4, 2, 16) X(2, 1, 8, 2, 32) X(2, 1, 16, 2, 16) X(2, 2, 4, 2, 32)     \
     X(2, 2, 8, 2, 16) X(2, 2, 8, 2, 32) X(2, 4, 4, 2, 16) X(2, 2, 4, 2, 64)      \
-    X(2, 2, 4, 3, 32) X(2, 1, 8, 2, 64) X(2, 1, 4, 2, 32) X(1, 1, 4, 2, 16)
+    X(2, 2, 4, 3, 32) X(2, 1, 8, 2, 64) X(2, 1, 4, 2, 32) X(1, 1, 4, 2, 16)     \
+    X(2, 2, 8, 1, 32)
 #define HC_HEAT2_SHAPES_F32(X)                                                    \
     X(1, 4, 4, 2, 16) X(2, 2, 8, 2, 16) X(4, 1, 8, 2, 32) X(4, 1, 16, 2, 16)     \
     X(4, 2, 4, 2, 32) X(4, 2, 8, 2, 16) X(4, 2, 4, 2, 64) X(4, 1, 8, 2, 64)      \
