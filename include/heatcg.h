@@ -552,9 +552,9 @@ int hc_batch_classes(hc_batch *b, int *classes);
 /*
  * hc_batch_autotune -- time every built block shape with each problem's
  * best-fitting width, hardware and XCD-grouped (8) order, whole-column,
- * one-z-block and 64-plane entries, one block per entry or a persistent
- * grid of 2 blocks
- * per compute unit, and with every width class for all problems, over
+ * one-z-block, 32- and 64-plane entries, one block per entry or a
+ * persistent grid of 2 blocks per compute unit, and with every width class
+ * for all problems, over
  * trial_steps (rounded up to even) steps of the states in u (on two
  * scratch buffers the call allocates and frees; u is not written), and
  * keep the fastest.  Blocks until done; *best_ms (may be NULL) receives

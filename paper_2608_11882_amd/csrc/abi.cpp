@@ -1063,6 +1063,13 @@ int batch_items(hc_batch *b) {
                     per_class[cls].push_back({p, (unsigned short)x, (unsigned short)y, kb, ke});
         }
     }
+    // longest runs first within a class (a problem's tiles of one run stay
+    // together, in y order): the short runs fill the tail of the launch,
+    // 3-4% faster than problem order on the uneven FP32 configuration
+    for (auto &v : per_class)
+        std::stable_sort(v.begin(), v.end(), [](const hc::BatchItem &a, const hc::BatchItem &c) {
+            return a.ke - a.kb > c.ke - c.kb;
+        });
     std::vector<hc::BatchItem> items;
     for (int c = 4; c >= 0; --c) {
         b->cls_first[c] = (int)items.size();
@@ -2051,8 +2058,8 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
     const size_t bytes = (size_t)b->total * hc::dtype_bytes(b->dtype);
     if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // candidates: every built shape, with whole-column, one-z-block and
-    // 64-plane entries, one block per entry or a persistent grid
+    // candidates: every built shape, with whole-column, one-z-block, 32-
+    // and 64-plane entries, one block per entry or a persistent grid
     int ncu = 256;
     {
         hipDeviceProp_t prop;
@@ -2066,12 +2073,14 @@ int hc_batch_autotune(hc_batch *b, const void *u, int trial_steps, hc_stream_t s
         // each problem's best-fitting width, with every order, run length
         // and grid; then every width for all problems, in one setting
         for (int x : {0, 8})
-            for (int dep : {0, t.zdepth, 64})
+            for (int dep : {0, t.zdepth, 32, 64}) {
+                if (dep == 32 && t.zdepth == 32) continue;  // listed as the z-block
                 for (int g : {0, 2 * ncu}) {
                     t.xcd = x;
                     t.cls = -1;
                     cand.push_back({t, g, dep});
                 }
+            }
         for (int c = 0; c <= 4; ++c)
             if (hc::batch_class_valid(t.threads, c)) {
                 t.xcd = 8;
