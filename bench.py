@@ -371,9 +371,11 @@ def ir_section(hc, b, xs, it64, ms64):
         times.append(e0.elapsed_time(e1))
     ms = st.median(times)
     n = b.numel()
-    # inner: 32 B per unknown and iteration; per outer step: residual
-    # (x, b read, s written: 20 B), x += d (20 B), clearing d (4 B)
-    algo = 32.0 * n * it + 44.0 * n * outer
+    # inner: 30 B per unknown and iteration on average (d's steps taken two
+    # at a time); per outer step: residual (x, b read, s written: 20 B),
+    # x += d (20 B), clearing d (4 B), and at most one waiting step of d
+    # (12 B, not counted)
+    algo = 30.0 * n * it + 44.0 * n * outer
     err = (torch.linalg.norm(x - xs) / torch.linalg.norm(xs)).item()
     return {
         "time_to_tol_s": round(ms / 1e3, 5),
@@ -867,7 +869,10 @@ def main():
             "true_relres": cg_rel,
             "status": sorted(statuses),
             "us_per_iteration": round(1e3 * statistics.median(cg_ms) / max(cg_iters, 1), 2),
-            "algo_hbm_gbs": round(64.0 * m ** 3 * cg_iters / (statistics.median(cg_ms) / 1e3) / 1e9, 1),
+            # 60 B per unknown and iteration on average (x's steps taken two
+            # at a time), plus one waiting 24 B step of x after an odd count
+            "algo_hbm_gbs": round((60.0 * cg_iters + 24.0 * (cg_iters % 2)) * m ** 3
+                                  / (statistics.median(cg_ms) / 1e3) / 1e9, 1),
             "direction_kernel_avg_us": round(1e3 * cga_ms / max(cga_n, 1), 2),
             "update_kernel_avg_us": round(1e3 * cgb_ms / max(cgb_n, 1), 2),
         },

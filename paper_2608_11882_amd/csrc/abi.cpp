@@ -785,6 +785,8 @@ int cg_run_ir(const double *b, double *x, int nx, int ny, int nz, double tol, in
         if (h->iter >= maxit || outer >= kMaxOuter || rnorm >= rprev) break;  // not converged
         rprev = rnorm;
         HC_TRY(hipMemsetAsync(w.d, 0, (size_t)n * sizeof(float), s), "hipMemsetAsync");
+        // d takes its steps two at a time, as x does in cg_run: iterations
+        // start, start+2, ... leave d alone and the next one applies both
         const int start = h->iter;
         int cur = 0, first = 1;
         while (h->state == 0 && h->iter < maxit) {
@@ -799,8 +801,10 @@ int cg_run_ir(const double *b, double *x, int nx, int ny, int nz, double tol, in
                     tm.done();
                 }
                 {
-                    Timed tm(hc::K_CG32_UPDATE, s, 20.0 * n);
-                    HC_TRY(hc::launch_cg_update_f32(w, cur, k0 + q, nx, ny, nz, t32, d->sink, s),
+                    const int xstep = ((k0 + q - start) & 1) ? 1 : 0;
+                    Timed tm(hc::K_CG32_UPDATE, s, (xstep ? 24.0 : 12.0) * n);
+                    HC_TRY(hc::launch_cg_update_f32(w, cur, k0 + q, xstep, nx, ny, nz, t32,
+                                                    d->sink, s),
                            "cg_update (binary32) launch");
                     tm.done();
                 }
@@ -812,6 +816,14 @@ int cg_run_ir(const double *b, double *x, int nx, int ny, int nz, double tol, in
             if ((rc = read_scalars())) return rc;
         }
         ++outer;
+        if ((h->iter - start) & 1) {
+            // the last completed inner iteration's step on d is still waiting;
+            // its direction vector is p[((j - start) & 1) ^ 1]
+            const int j = h->iter - 1;
+            HC_TRY(hc::launch_cg_xstep_f32(w.d, w.p[((j - start) & 1) ^ 1], w.sc, j,
+                                           (long long)n, s),
+                   "cg_xstep (binary32) launch");
+        }
         if (h->state == -7) {
             status = fail(HC_ENONFINITE, "non-finite inner scalar at iteration %d", h->iter);
             break;
@@ -898,12 +910,29 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         return HC_OK;
     }
 
+    // x takes its steps two at a time (see launch_cg_update): iterations
+    // j0, j0+2, ... of a (re)start at j0 leave x alone and the next one
+    // applies both steps; a step still waiting when the iteration stops is
+    // applied by xsettle before x is used.  The direction vector of
+    // iteration j is p[cur0 ^ ((j - j0) & 1) ^ 1], cur0 the index at j0.
     const int kBatch = 16;
     int cur = 0, first = 1, restarts = 0;
+    int j0 = 0, cur0 = 0, xdone = 0;
     bool true_done = false;
+    auto xsettle = [&]() -> int {
+        if (((h->iter - j0) & 1) && xdone != h->iter) {
+            const int j = h->iter - 1;
+            HC_TRY(hc::launch_cg_xstep(x, w.p[cur0 ^ ((j - j0) & 1) ^ 1], w.sc, j,
+                                       (long long)nx * ny * nz, s),
+                   "cg_xstep launch");
+            xdone = h->iter;
+        }
+        return HC_OK;
+    };
     for (;;) {
         if (h->state < 0) break;
         if (h->state == 1) {
+            if ((rc = xsettle())) return rc;
             if ((rc = residual(0))) return rc;
             if ((rc = read_scalars())) return rc;
             true_done = true;
@@ -912,6 +941,8 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
             ++restarts;
             true_done = false;
             first = 1;
+            j0 = h->iter;
+            cur0 = cur;
             if ((rc = residual(1))) return rc;
             if ((rc = read_scalars())) return rc;
             continue;
@@ -928,8 +959,9 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
                 tm.done();
             }
             {
-                Timed tm(hc::K_CG_UPDATE, s, 40.0 * n, 1, timing);
-                HC_TRY(hc::launch_cg_update(x, w, cur, k0 + q, nx, ny, nz, til, sink, s),
+                const int xstep = ((k0 + q - j0) & 1) ? 1 : 0;
+                Timed tm(hc::K_CG_UPDATE, s, (xstep ? 48.0 : 24.0) * n, 1, timing);
+                HC_TRY(hc::launch_cg_update(x, w, cur, k0 + q, xstep, nx, ny, nz, til, sink, s),
                        "cg_update launch");
                 tm.done();
             }
@@ -939,6 +971,7 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         HC_TRY(hc::launch_cg_settle(w, k0 + batch, nx, ny, nz, til, s), "cg_settle launch");
         if ((rc = read_scalars())) return rc;
     }
+    if ((rc = xsettle())) return rc;
     if (!true_done) {
         if ((rc = residual(0))) return rc;
         if ((rc = read_scalars())) return rc;

@@ -517,6 +517,7 @@ __device__ __forceinline__ bool update_scalars(CGScalars *sc, const double *part
         sc->pap = pap;
         if (state == 0) {
             sc->alpha = a;
+            sc->aslot[k & 1] = a;
             sc->iter = k + 1;
         } else {
             store_state(sc, state);
@@ -677,22 +678,37 @@ struct DirectionEpi {
     }
 };
 
-// x += alpha p', r -= alpha A p', and r.r of the new residual (accumulated
-// in binary64)
-template <class T, int VEC>
+// How an update kernel treats x.  x is not needed by the iteration itself
+// (only r and p are), so its steps can wait and be applied two at a time:
+// x is then read and written every second iteration, at the cost of one
+// more read of a direction vector (binary64: 36 instead of 40 bytes per
+// unknown and iteration on average).  The two steps are added one after the other, in
+// iteration order, so x takes the same values as with one step per
+// iteration.
+enum XStep {
+    kXDefer = 0,  // r only; this iteration's step on x waits
+    kXPair = 1,   // x += alpha_(k-1) p_(k-1), then x += alpha_k p_k
+};
+
+// x's step(s), r -= alpha A p', and r.r of the new residual (accumulated in
+// binary64)
+template <class T, int VEC, int XM>
 struct UpdateEpi {
     struct Pre {
-        T x[VEC], r[VEC];
+        T x[XM == kXPair ? VEC : 1], r[VEC], pp[XM == kXPair ? VEC : 1];
     };
     T *__restrict__ x;
     T *__restrict__ r;
+    const T *__restrict__ pprev;  // p_(k-1) (kXPair)
     long long plane;
     T alpha;
+    T aprev;  // alpha_(k-1) (kXPair)
     double acc = 0.0;
     __device__ Pre prefetch(int k, unsigned off) const {
         Pre p;
-        load_vec<T, VEC>(node(x, plane, k, off), p.x);
+        if (XM == kXPair) load_vec<T, VEC>(node(x, plane, k, off), p.x);
         load_vec<T, VEC>(node(r, plane, k, off), p.r);
+        if (XM == kXPair) load_vec<T, VEC>(node(pprev, plane, k, off), p.pp);
         return p;
     }
     __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
@@ -701,12 +717,15 @@ struct UpdateEpi {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const T q = T(6) * c[e] - ns[e];
-            xn[e] = p.x[e] + alpha * c[e];
+            if (XM == kXPair) {
+                const T xv = p.x[e] + aprev * p.pp[e];
+                xn[e] = xv + alpha * c[e];
+            }
             rn[e] = p.r[e] - alpha * q;
             if (ok[e]) acc += (double)rn[e] * (double)rn[e];
         }
         T *const sk = reinterpret_cast<T *>(sink);
-        store_vec<T, VEC>(lane_in ? node(x, plane, k, off) : sk, xn, false);
+        if (XM == kXPair) store_vec<T, VEC>(lane_in ? node(x, plane, k, off) : sk, xn, false);
         store_vec<T, VEC>(lane_in ? node(r, plane, k, off) : sk, rn, false);
     }
 };
@@ -830,20 +849,22 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_direction(
     if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
-template <class T, int VEC, int WX, int BY, int ZB>
+// pprev: p_(k-1), read with XM == kXPair only (its alpha is slot (k-1)&1).
+template <class T, int VEC, int WX, int BY, int ZB, int XM>
 __global__ __launch_bounds__(64 * WX * BY) void cg_update(
-    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, double *partial,
-    CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int k) {
+    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ pprev,
+    double *partial, CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int k) {
     constexpr int NT = 64 * WX * BY;
     const int nb = (int)gridDim.x;
     const long long plane = (long long)nx * ny;
     PlainField<T> f{p, plane};
-    UpdateEpi<T, VEC> epi{x, r, plane, T(0)};
+    UpdateEpi<T, VEC, XM> epi{x, r, pprev, plane, T(0), T(0)};
     // alpha is formed while the first planes' loads are out
     auto gate = [&]() {
         double alpha;
         if (!update_scalars<NT>(sc, partial, nb, k, &alpha)) return false;
         epi.alpha = (T)alpha;
+        if (XM == kXPair) epi.aprev = (T)sc->aslot[(k + 1) & 1];
         return true;
     };
     if (!box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi, gate)) return;
@@ -882,6 +903,23 @@ __global__ __launch_bounds__(256) void ir_axpy(double *__restrict__ x, const flo
             for (int e = 0; e < 4; ++e) x[i + e] = x[i + e] + (double)d[i + e];
         } else {
             for (long long e = i; e < n; ++e) x[e] = x[e] + (double)d[e];
+        }
+    }
+}
+
+// A step of x that waited: x += alpha_j p_j (alpha_j from slot j & 1), the
+// operation the update kernels apply to x, node by node.
+template <class T>
+__global__ __launch_bounds__(256) void cg_xstep(T *__restrict__ x, const T *__restrict__ p,
+                                                const CGScalars *sc, int j, long long n) {
+    const T a = (T)sc->aslot[j & 1];
+    const long long stride = (long long)gridDim.x * 256 * 2;
+    for (long long i = ((long long)blockIdx.x * 256 + threadIdx.x) * 2; i < n; i += stride) {
+        if (i + 2 <= n) {
+            x[i] = x[i] + a * p[i];
+            x[i + 1] = x[i + 1] + a * p[i + 1];
+        } else {
+            x[i] = x[i] + a * p[i];
         }
     }
 }
@@ -1013,8 +1051,14 @@ CGWorkF32 cg_ir_work_carve(void *base, int nx, int ny, int nz) {
     }
 #define HC_CG_ONE_UPD(V, W, B, Z)                                                 \
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
-        cg_update<ELEM, V, W, B, Z><<<grid, block, 0, s>>>(                       \
-            x, w.r, w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd, sink, k);   \
+        if (xstep == kXDefer)                                                     \
+            cg_update<ELEM, V, W, B, Z, kXDefer><<<grid, block, 0, s>>>(          \
+                x, w.r, w.p[cur ^ 1], w.p[cur], w.partial, w.sc, nx, ny, nz,      \
+                t.xcd, sink, k);                                                  \
+        else                                                                      \
+            cg_update<ELEM, V, W, B, Z, kXPair><<<grid, block, 0, s>>>(           \
+                x, w.r, w.p[cur ^ 1], w.p[cur], w.partial, w.sc, nx, ny, nz,      \
+                t.xcd, sink, k);                                                  \
         done = true;                                                              \
     }
 #define HC_CG_ONE_SETTLE(V, W, B, Z)                                              \
@@ -1054,9 +1098,19 @@ hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int k, int n
     HC_CG_DISPATCH(HC_CG_SHAPES, DIR);
 }
 
-hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int nx, int ny,
-                            int nz, const CGTiling &t, double *sink, hipStream_t s) {
+hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int xstep, int nx,
+                            int ny, int nz, const CGTiling &t, double *sink, hipStream_t s) {
+    if (xstep != kXDefer && xstep != kXPair) return hipErrorInvalidValue;
     HC_CG_DISPATCH(HC_CG_SHAPES, UPD);
+}
+
+hipError_t launch_cg_xstep(double *x, const double *p, const CGScalars *sc, int j, long long n,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 1023) / 1024;
+    if (nb > 8192) nb = 8192;
+    cg_xstep<double><<<(unsigned)nb, 256, 0, s>>>(x, p, sc, j, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_cg_settle(const CGWork &w, int k, int nx, int ny, int nz, const CGTiling &t,
@@ -1077,10 +1131,20 @@ hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int k
     HC_CG_DISPATCH(HC_CG_SHAPES_F32, DIR);
 }
 
-hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int k, int nx, int ny, int nz,
-                                const CGTiling &t, double *sink, hipStream_t s) {
+hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int k, int xstep, int nx, int ny,
+                                int nz, const CGTiling &t, double *sink, hipStream_t s) {
+    if (xstep != kXDefer && xstep != kXPair) return hipErrorInvalidValue;
     float *const x = w.d;
     HC_CG_DISPATCH(HC_CG_SHAPES_F32, UPD);
+}
+
+hipError_t launch_cg_xstep_f32(float *x, const float *p, const CGScalars *sc, int j, long long n,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 1023) / 1024;
+    if (nb > 8192) nb = 8192;
+    cg_xstep<float><<<(unsigned)nb, 256, 0, s>>>(x, p, sc, j, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_cg_settle_f32(const CGWorkF32 &w, int k, int nx, int ny, int nz,

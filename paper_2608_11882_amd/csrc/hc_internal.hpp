@@ -172,6 +172,7 @@ struct CGScalars {
     double inner_tol; // refinement: relative reduction of each inner solve
     double floor_frac;// refinement: inner solves stop at floor_frac * tol ||b||
     double rslot[2];  // r.r of iteration k in slot k & 1 (device use)
+    double aslot[2];  // alpha of iteration k in slot k & 1 (device use)
     int iter;         // completed iterations
     int state;        // 0 running, 1 converged, -6 breakdown, -7 non-finite
     unsigned ticket;  // arrival counter of the residual kernels (0 between kernels)
@@ -231,8 +232,15 @@ hipError_t launch_cg_residual(const double *b, const double *x, const CGWork &w,
 hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int k, int nx,
                                int ny, int nz, const CGTiling &t, double *sink,
                                hipStream_t s);
-hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int nx, int ny,
-                            int nz, const CGTiling &t, double *sink, hipStream_t s);
+// xstep: 0 leaves x alone (this iteration's step on x waits), 1 applies the
+// previous iteration's step and this one's (p_(k-1) is w.p[cur]), 2 this
+// one's only.
+hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int xstep, int nx,
+                            int ny, int nz, const CGTiling &t, double *sink, hipStream_t s);
+// x += alpha_j p over n nodes, alpha_j from sc's slot j & 1: a step of x
+// that waited (see launch_cg_update).
+hipError_t launch_cg_xstep(double *x, const double *p, const CGScalars *sc, int j, long long n,
+                           hipStream_t s);
 hipError_t launch_cg_settle(const CGWork &w, int k, int nx, int ny, int nz, const CGTiling &t,
                             hipStream_t s);
 hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
@@ -245,8 +253,10 @@ hipError_t launch_cg_ir_residual(const double *b, const double *x, const CGWorkF
 hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int k, int nx,
                                    int ny, int nz, const CGTiling &t, double *sink,
                                    hipStream_t s);
-hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int k, int nx, int ny, int nz,
-                                const CGTiling &t, double *sink, hipStream_t s);
+hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int k, int xstep, int nx, int ny,
+                                int nz, const CGTiling &t, double *sink, hipStream_t s);
+hipError_t launch_cg_xstep_f32(float *x, const float *p, const CGScalars *sc, int j, long long n,
+                               hipStream_t s);
 hipError_t launch_cg_settle_f32(const CGWorkF32 &w, int k, int nx, int ny, int nz,
                                 const CGTiling &t, hipStream_t s);
 hipError_t launch_lap7_f32(const float *x, float *y, int nx, int ny, int nz, const CGTiling &t,
