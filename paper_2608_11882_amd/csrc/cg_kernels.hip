@@ -290,34 +290,45 @@ __device__ __forceinline__ bool box_zmarch(int nx, int ny, int nz, int xcd, doub
     const int kb = g.kb, ke = g.ke;
 
     if (UNROLL && ke - kb + 1 == ZB) {
-        T q[ZB + 2][VEC];  // q[s]: column at plane kb-1+s
-        T rg[ZB][VEC];     // ring values of plane kb+s
+        // Odd z-blocks march downward: a z-block then reads its halo plane
+        // at the end of its march when the block below (same XCD, started
+        // together) reads it as its own last plane, and at its start when
+        // the block above does, so the halo reads tend to find the plane in
+        // L2 instead of going back to memory.  (zm + zp is the same sum
+        // either way, and the stencil has no other z order.)  pl(s): the
+        // plane of queue slot s, the march's s-th column from its start.
+        const bool down = ((kb / ZB) & 1) != 0;
+        const int k0 = down ? ke + 1 : kb - 1, dz = down ? -1 : 1;
+        auto pl = [&](int s) { return k0 + s * dz; };
+        T q[ZB + 2][VEC];  // q[s]: column at plane pl(s)
+        T rg[ZB][VEC];     // ring values of plane pl(s+1)
         Pre pre[ZB];
         {
             Raw q0[kPF + 2];
             if (!EARLY && !gate()) return false;
 #pragma unroll
             for (int s = 0; s < kPF + 2; ++s)
-                field.template fetch<VEC>(kclamp(kb - 1 + s), g.own_b, q0[s]);
+                field.template fetch<VEC>(kclamp(pl(s)), g.own_b, q0[s]);
             if (EARLY && !gate()) return false;
 #pragma unroll
-            for (int s = 0; s < kPF + 2; ++s) col_make(kb - 1 + s, q0[s], q[s]);
+            for (int s = 0; s < kPF + 2; ++s) col_make(pl(s), q0[s], q[s]);
         }
 #pragma unroll
-        for (int s = 0; s < kPF; ++s) ringv(kb + s, rg[s]);
+        for (int s = 0; s < kPF; ++s) ringv(pl(s + 1), rg[s]);
 #pragma unroll
-        for (int s = 0; s < kPFE && s < ZB; ++s) pre[s] = epi.prefetch(kb + s, g.own_b);
+        for (int s = 0; s < kPFE && s < ZB; ++s) pre[s] = epi.prefetch(pl(s + 1), g.own_b);
 #pragma unroll
         for (int s = 0; s < ZB; ++s) {
             __syncthreads();
             put(q[s + 1], rg[s]);
-            if (s + kPF < ZB) ringv(kb + s + kPF, rg[s + kPF]);
-            if (s + kPFE < ZB) pre[s + kPFE] = epi.prefetch(kb + s + kPFE, g.own_b);
+            if (s + kPF < ZB) ringv(pl(s + 1 + kPF), rg[s + kPF]);
+            if (s + kPFE < ZB) pre[s + kPFE] = epi.prefetch(pl(s + 1 + kPFE), g.own_b);
             __syncthreads();
             T ns[VEC];
             nsums(q[s], q[s + 1], q[s + 2], ns);
-            epi.finish(g.in, g.lane_in, kb + s, g.own_b, lane_sink, q[s + 1], ns, pre[s]);
-            if (s + 2 + kPF <= ZB + 1) col(kb + s + 1 + kPF, q[s + 2 + kPF]);
+            epi.finish(g.in, g.lane_in, pl(s + 1), g.own_b, lane_sink, q[s + 1], ns,
+                       pre[s]);
+            if (s + 2 + kPF <= ZB + 1) col(pl(s + 2 + kPF), q[s + 2 + kPF]);
         }
         return true;
     }
