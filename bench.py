@@ -755,6 +755,7 @@ def main():
     int_ms, int_n, int_bytes = hc.prof_read(kname)
     cga_ms, cga_n, cga_b = hc.prof_read("cg_direction")
     cgb_ms, cgb_n, cgb_b = hc.prof_read("cg_update")
+    cgx_ms, cgx_n, cgx_b = hc.prof_read("cg_update_x")
     hc.prof_enable(False)
 
     heat_ms = [e0.elapsed_time(e1) for e0, e1, _, _, _, _ in records]
@@ -874,7 +875,11 @@ def main():
             "algo_hbm_gbs": round((60.0 * cg_iters + 24.0 * (cg_iters % 2)) * m ** 3
                                   / (statistics.median(cg_ms) / 1e3) / 1e9, 1),
             "direction_kernel_avg_us": round(1e3 * cga_ms / max(cga_n, 1), 2),
-            "update_kernel_avg_us": round(1e3 * cgb_ms / max(cgb_n, 1), 2),
+            # the update kernel alternates between r only (x's step waits)
+            # and r plus x's last two steps
+            "update_kernel_avg_us": round(1e3 * (cgb_ms / max(cgb_n, 1) + cgx_ms / max(cgx_n, 1)) / 2, 2),
+            "update_r_only_avg_us": round(1e3 * cgb_ms / max(cgb_n, 1), 2),
+            "update_with_x_avg_us": round(1e3 * cgx_ms / max(cgx_n, 1), 2),
         },
         "precision": prec,
         "varcoef_512": varcoef,

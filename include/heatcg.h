@@ -597,12 +597,12 @@ enum hc_kernel_kind {
     HC_K_HEAT_FUSED = 2,
     HC_K_HEAT_PLAIN = 3,
     HC_K_CG_DIRECTION = 4, /* p = r + beta p, A p, p.Ap   */
-    HC_K_CG_UPDATE = 5,    /* r -= alpha A p, r.r; x's steps two at a time */
+    HC_K_CG_UPDATE = 5,    /* r -= alpha A p, r.r (x's step waits) */
     HC_K_CG_RESIDUAL = 6,  /* r = b - A x, r.r, b.b      */
     HC_K_LAP7 = 7,
     HC_K_COPY = 8,
     HC_K_CG32_DIRECTION = 9,  /* the same, binary32 (refinement) */
-    HC_K_CG32_UPDATE = 10,    /* s -= alpha A p, s.s; d's steps two at a time */
+    HC_K_CG32_UPDATE = 10,    /* s -= alpha A p, s.s (d's step waits) */
     HC_K_IR_RESIDUAL = 11,    /* r = b - A x, s = (float) r, sums */
     HC_K_IR_UPDATE = 12,      /* x += d                        */
     HC_K_BATCH = 13,          /* a batch step (graph: all steps) */
@@ -616,7 +616,9 @@ enum hc_kernel_kind {
     HC_K_VK2_INTERIOR = 21,   /* variable coefficient, two steps */
     HC_K_VK2_BOUNDARY = 22,
     HC_K_VK2_FUSED = 23,
-    HC_K_COUNT = 24
+    HC_K_CG_UPDATE_X = 24,    /* HC_K_CG_UPDATE and x's last two steps */
+    HC_K_CG32_UPDATE_X = 25,  /* HC_K_CG32_UPDATE and d's last two steps */
+    HC_K_COUNT = 26
 };
 int hc_prof_enable(int every);
 int hc_prof_read(int kind, double *total_ms, long long *launches,

@@ -36,7 +36,8 @@ KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain"
            "cg32_direction": 9, "cg32_update": 10, "ir_residual": 11, "ir_update": 12,
            "batch": 13, "vk_interior": 14, "vk_boundary": 15, "vk_fused": 16, "vk_plain": 17,
            "heat2_interior": 18, "heat2_boundary": 19, "heat2_fused": 20,
-           "vk2_interior": 21, "vk2_boundary": 22, "vk2_fused": 23}
+           "vk2_interior": 21, "vk2_boundary": 22, "vk2_fused": 23,
+           "cg_update_x": 24, "cg32_update_x": 25}
 
 _lib = None
 

@@ -802,7 +802,8 @@ int cg_run_ir(const double *b, double *x, int nx, int ny, int nz, double tol, in
                 }
                 {
                     const int xstep = ((k0 + q - start) & 1) ? 1 : 0;
-                    Timed tm(hc::K_CG32_UPDATE, s, (xstep ? 24.0 : 12.0) * n);
+                    Timed tm(xstep ? hc::K_CG32_UPDATE_X : hc::K_CG32_UPDATE, s,
+                             (xstep ? 24.0 : 12.0) * n);
                     HC_TRY(hc::launch_cg_update_f32(w, cur, k0 + q, xstep, nx, ny, nz, t32,
                                                     d->sink, s),
                            "cg_update (binary32) launch");
@@ -960,7 +961,8 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
             }
             {
                 const int xstep = ((k0 + q - j0) & 1) ? 1 : 0;
-                Timed tm(hc::K_CG_UPDATE, s, (xstep ? 48.0 : 24.0) * n, 1, timing);
+                Timed tm(xstep ? hc::K_CG_UPDATE_X : hc::K_CG_UPDATE, s,
+                         (xstep ? 48.0 : 24.0) * n, 1, timing);
                 HC_TRY(hc::launch_cg_update(x, w, cur, k0 + q, xstep, nx, ny, nz, til, sink, s),
                        "cg_update launch");
                 tm.done();

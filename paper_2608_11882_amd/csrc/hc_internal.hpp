@@ -63,7 +63,9 @@ enum KernelKind {
     K_VK2_INTERIOR = 21,
     K_VK2_BOUNDARY = 22,
     K_VK2_FUSED = 23,
-    K_COUNT = 24
+    K_CG_UPDATE_X = 24,
+    K_CG32_UPDATE_X = 25,
+    K_COUNT = 26
 };
 
 // ---- heat (heat_kernels.hip) ------------------------------------------------
