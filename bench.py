@@ -870,14 +870,14 @@ def main():
             "true_relres": cg_rel,
             "status": sorted(statuses),
             "us_per_iteration": round(1e3 * statistics.median(cg_ms) / max(cg_iters, 1), 2),
-            # 60 B per unknown and iteration on average (x's steps taken two
-            # at a time), plus one waiting 24 B step of x after an odd count
-            "algo_hbm_gbs": round((60.0 * cg_iters + 24.0 * (cg_iters % 2)) * m ** 3
+            # 58 B per unknown and iteration on average (x's steps taken four
+            # at a time), plus the waiting 24 B steps of x after the last group
+            "algo_hbm_gbs": round((58.0 * cg_iters + 24.0 * (cg_iters % 4)) * m ** 3
                                   / (statistics.median(cg_ms) / 1e3) / 1e9, 1),
             "direction_kernel_avg_us": round(1e3 * cga_ms / max(cga_n, 1), 2),
-            # the update kernel alternates between r only (x's step waits)
-            # and r plus x's last two steps
-            "update_kernel_avg_us": round(1e3 * (cgb_ms / max(cgb_n, 1) + cgx_ms / max(cgx_n, 1)) / 2, 2),
+            # the update kernel takes r only (x's step waits) on three
+            # iterations of four and r plus x's last four steps on the fourth
+            "update_kernel_avg_us": round(1e3 * (3 * cgb_ms / max(cgb_n, 1) + cgx_ms / max(cgx_n, 1)) / 4, 2),
             "update_r_only_avg_us": round(1e3 * cgb_ms / max(cgb_n, 1), 2),
             "update_with_x_avg_us": round(1e3 * cgx_ms / max(cgx_n, 1), 2),
         },

@@ -323,8 +323,8 @@ size_t cg_workspace_bytes(int nx, int ny, int nz);
  *  b, x, nx, ny, nz, tol, maxit, stream, iters, true_relres  as cg_solve_ex.
  *  Size limit: cg_workspace_bytes(nx, ny, nz) + 16384 (the store target of
  *  lanes outside the box) must not exceed HC_CG_NOALLOC_BYTES, else
- *  HC_EINVAL before any device work (a 128^3 box needs about 51 MB, the
- *  largest cube is 140^3).
+ *  HC_EINVAL before any device work (a 128^3 box needs about 85 MB, the
+ *  largest cube is 135^3).
  *
  * Every call on one GPU shares that GPU's array, which keeps the last
  * call's contents; nothing in it is read before the call writes it.  The
@@ -334,7 +334,7 @@ size_t cg_workspace_bytes(int nx, int ny, int nz);
  * process) would race on the array.  Blocks until done; same statuses as
  * cg_solve_ex.
  */
-#define HC_CG_NOALLOC_BYTES (64u << 20)
+#define HC_CG_NOALLOC_BYTES (96u << 20)
 int cg_solve_noalloc(const double *b, double *x, int nx, int ny, int nz, double tol,
                      int maxit, hc_stream_t stream, int *iters, double *true_relres);
 
@@ -616,7 +616,7 @@ enum hc_kernel_kind {
     HC_K_VK2_INTERIOR = 21,   /* variable coefficient, two steps */
     HC_K_VK2_BOUNDARY = 22,
     HC_K_VK2_FUSED = 23,
-    HC_K_CG_UPDATE_X = 24,    /* HC_K_CG_UPDATE and x's last two steps */
+    HC_K_CG_UPDATE_X = 24,    /* HC_K_CG_UPDATE and x's last four steps */
     HC_K_CG32_UPDATE_X = 25,  /* HC_K_CG32_UPDATE and d's last two steps */
     HC_K_COUNT = 26
 };

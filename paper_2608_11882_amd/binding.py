@@ -29,7 +29,7 @@ _LIB_PATH = os.path.join(_HERE, "libheatcg.so")
 
 HC_OK, HC_ENOTCONV = 0, 1
 HC_F64, HC_F32, HC_BF16 = 0, 1, 2
-CG_NOALLOC_BYTES = 64 << 20  # HC_CG_NOALLOC_BYTES of heatcg.h
+CG_NOALLOC_BYTES = 96 << 20  # HC_CG_NOALLOC_BYTES of heatcg.h
 MODES = {"split": 0, "fused": 1, "plain": 2}
 KERNELS = {"heat_interior": 0, "heat_boundary": 1, "heat_fused": 2, "heat_plain": 3,
            "cg_direction": 4, "cg_update": 5, "cg_residual": 6, "lap7": 7, "copy": 8,

@@ -785,7 +785,7 @@ int cg_run_ir(const double *b, double *x, int nx, int ny, int nz, double tol, in
         if (h->iter >= maxit || outer >= kMaxOuter || rnorm >= rprev) break;  // not converged
         rprev = rnorm;
         HC_TRY(hipMemsetAsync(w.d, 0, (size_t)n * sizeof(float), s), "hipMemsetAsync");
-        // d takes its steps two at a time, as x does in cg_run: iterations
+        // d takes its steps two at a time (x in cg_run four): iterations
         // start, start+2, ... leave d alone and the next one applies both
         const int start = h->iter;
         int cur = 0, first = 1;
@@ -891,10 +891,10 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         return HC_OK;
     };
 
-    // the zero planes around r, p0 and p1
+    // the zero planes around r and the four direction vectors
     {
         const size_t plane_bytes = (size_t)nx * ny * sizeof(double);
-        double *vecs[3] = {w.r, w.p[0], w.p[1]};
+        double *vecs[5] = {w.r, w.p[0], w.p[1], w.p[2], w.p[3]};
         for (double *v : vecs) {
             HC_TRY(hipMemsetAsync(v - (size_t)nx * ny, 0, plane_bytes, s), "hipMemsetAsync");
             HC_TRY(hipMemsetAsync(v + (size_t)nz * nx * ny, 0, plane_bytes, s), "hipMemsetAsync");
@@ -911,21 +911,22 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         return HC_OK;
     }
 
-    // x takes its steps two at a time (see launch_cg_update): iterations
-    // j0, j0+2, ... of a (re)start at j0 leave x alone and the next one
-    // applies both steps; a step still waiting when the iteration stops is
-    // applied by xsettle before x is used.  The direction vector of
-    // iteration j is p[cur0 ^ ((j - j0) & 1) ^ 1], cur0 the index at j0.
+    // x takes its steps four at a time (see launch_cg_update): after a
+    // (re)start at iteration j0 the update of iteration j applies the steps
+    // of j-3 .. j when j - j0 is 3 mod 4 and leaves x alone otherwise;
+    // steps still waiting when the iteration stops are applied by xsettle,
+    // in order, before x is used.  The direction vector of iteration j is
+    // p[j & 3].
     const int kBatch = 16;
-    int cur = 0, first = 1, restarts = 0;
-    int j0 = 0, cur0 = 0, xdone = 0;
+    int first = 1, restarts = 0;
+    int j0 = 0, xdone = 0;
     bool true_done = false;
     auto xsettle = [&]() -> int {
-        if (((h->iter - j0) & 1) && xdone != h->iter) {
-            const int j = h->iter - 1;
-            HC_TRY(hc::launch_cg_xstep(x, w.p[cur0 ^ ((j - j0) & 1) ^ 1], w.sc, j,
-                                       (long long)nx * ny * nz, s),
-                   "cg_xstep launch");
+        const int waiting = (h->iter - j0) & 3;
+        if (waiting && xdone != h->iter) {
+            for (int j = h->iter - waiting; j < h->iter; ++j)
+                HC_TRY(hc::launch_cg_xstep(x, w.p[j & 3], w.sc, j, (long long)nx * ny * nz, s),
+                       "cg_xstep launch");
             xdone = h->iter;
         }
         return HC_OK;
@@ -943,7 +944,6 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
             true_done = false;
             first = 1;
             j0 = h->iter;
-            cur0 = cur;
             if ((rc = residual(1))) return rc;
             if ((rc = read_scalars())) return rc;
             continue;
@@ -954,20 +954,18 @@ int cg_run(const double *b, double *x, int nx, int ny, int nz, double tol, int m
         for (int q = 0; q < batch; ++q) {
             {
                 Timed tm(hc::K_CG_DIRECTION, s, (first ? 16.0 : 24.0) * n, 1, timing);
-                HC_TRY(hc::launch_cg_direction(w, cur, first, k0 + q, nx, ny, nz, til, sink,
-                                               s),
+                HC_TRY(hc::launch_cg_direction(w, first, k0 + q, nx, ny, nz, til, sink, s),
                        "cg_direction launch");
                 tm.done();
             }
             {
-                const int xstep = ((k0 + q - j0) & 1) ? 1 : 0;
-                Timed tm(xstep ? hc::K_CG_UPDATE_X : hc::K_CG_UPDATE, s,
-                         (xstep ? 48.0 : 24.0) * n, 1, timing);
-                HC_TRY(hc::launch_cg_update(x, w, cur, k0 + q, xstep, nx, ny, nz, til, sink, s),
+                const int xsteps = ((k0 + q - j0) & 3) == 3 ? 4 : 0;
+                Timed tm(xsteps ? hc::K_CG_UPDATE_X : hc::K_CG_UPDATE, s,
+                         (xsteps ? 64.0 : 24.0) * n, 1, timing);
+                HC_TRY(hc::launch_cg_update(x, w, k0 + q, xsteps, nx, ny, nz, til, sink, s),
                        "cg_update launch");
                 tm.done();
             }
-            cur ^= 1;
             first = 0;
         }
         HC_TRY(hc::launch_cg_settle(w, k0 + batch, nx, ny, nz, til, s), "cg_settle launch");

@@ -528,7 +528,7 @@ __device__ __forceinline__ bool update_scalars(CGScalars *sc, const double *part
         sc->pap = pap;
         if (state == 0) {
             sc->alpha = a;
-            sc->aslot[k & 1] = a;
+            sc->aslot[k & 3] = a;
             sc->iter = k + 1;
         } else {
             store_state(sc, state);
@@ -690,36 +690,37 @@ struct DirectionEpi {
 };
 
 // How an update kernel treats x.  x is not needed by the iteration itself
-// (only r and p are), so its steps can wait and be applied two at a time:
-// x is then read and written every second iteration, at the cost of one
-// more read of a direction vector (binary64: 36 instead of 40 bytes per
-// unknown and iteration on average).  The two steps are added one after the other, in
-// iteration order, so x takes the same values as with one step per
-// iteration.
-enum XStep {
-    kXDefer = 0,  // r only; this iteration's step on x waits
-    kXPair = 1,   // x += alpha_(k-1) p_(k-1), then x += alpha_k p_k
-};
-
-// x's step(s), r -= alpha A p', and r.r of the new residual (accumulated in
-// binary64)
+// (only r and p are), so its steps can wait and be applied several at a
+// time: with XM steps at a time x is read and written every XM-th iteration,
+// at the cost of XM-1 more reads of direction vectors then (binary64: 34
+// instead of 40 bytes per unknown and iteration on average at XM = 4, 36 at
+// XM = 2).  The steps are added one after the other, in iteration order, so
+// x takes the same values as with one step per iteration.
+//
+// XM: 0 updates r only (this iteration's step on x waits); 2 or 4 first
+// applies the waiting steps of iterations k-XM+1 .. k-1, then this one's.
 template <class T, int VEC, int XM>
 struct UpdateEpi {
+    static_assert(XM == 0 || XM == 2 || XM == 4, "x steps: 0, 2 or 4");
+    static constexpr int NP = XM > 1 ? XM - 1 : 1;  // earlier direction vectors read
     struct Pre {
-        T x[XM == kXPair ? VEC : 1], r[VEC], pp[XM == kXPair ? VEC : 1];
+        T x[XM ? VEC : 1], r[VEC], pp[NP][XM ? VEC : 1];
     };
     T *__restrict__ x;
     T *__restrict__ r;
-    const T *__restrict__ pprev;  // p_(k-1) (kXPair)
+    const T *__restrict__ pprev[3];  // p_(k-1), p_(k-2), p_(k-3)
     long long plane;
     T alpha;
-    T aprev;  // alpha_(k-1) (kXPair)
+    T aprev[3];  // alpha_(k-1), alpha_(k-2), alpha_(k-3)
     double acc = 0.0;
     __device__ Pre prefetch(int k, unsigned off) const {
         Pre p;
-        if (XM == kXPair) load_vec<T, VEC>(node(x, plane, k, off), p.x);
+        if (XM) load_vec<T, VEC>(node(x, plane, k, off), p.x);
         load_vec<T, VEC>(node(r, plane, k, off), p.r);
-        if (XM == kXPair) load_vec<T, VEC>(node(pprev, plane, k, off), p.pp);
+        if (XM) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) load_vec<T, VEC>(node(pprev[i], plane, k, off), p.pp[i]);
+        }
         return p;
     }
     __device__ void finish(const bool *ok, bool lane_in, int k, unsigned off, double *sink,
@@ -728,15 +729,17 @@ struct UpdateEpi {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const T q = T(6) * c[e] - ns[e];
-            if (XM == kXPair) {
-                const T xv = p.x[e] + aprev * p.pp[e];
+            if (XM) {
+                T xv = p.x[e];
+#pragma unroll
+                for (int i = NP - 1; i >= 0; --i) xv = xv + aprev[i] * p.pp[i][e];
                 xn[e] = xv + alpha * c[e];
             }
             rn[e] = p.r[e] - alpha * q;
             if (ok[e]) acc += (double)rn[e] * (double)rn[e];
         }
         T *const sk = reinterpret_cast<T *>(sink);
-        if (XM == kXPair) store_vec<T, VEC>(lane_in ? node(x, plane, k, off) : sk, xn, false);
+        if (XM) store_vec<T, VEC>(lane_in ? node(x, plane, k, off) : sk, xn, false);
         store_vec<T, VEC>(lane_in ? node(r, plane, k, off) : sk, rn, false);
     }
 };
@@ -860,22 +863,28 @@ __global__ __launch_bounds__(64 * WX * BY) void cg_direction(
     if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
-// pprev: p_(k-1), read with XM == kXPair only (its alpha is slot (k-1)&1).
+// p1, p2, p3: p_(k-1), p_(k-2), p_(k-3), read as UpdateEpi<XM> needs
+// (their alphas are in slots (k-i) & 3).
 template <class T, int VEC, int WX, int BY, int ZB, int XM>
 __global__ __launch_bounds__(64 * WX * BY) void cg_update(
-    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ pprev,
-    double *partial, CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink, int k) {
+    T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *p1, const T *p2,
+    const T *p3, double *partial, CGScalars *sc, int nx, int ny, int nz, int xcd, double *sink,
+    int k) {
     constexpr int NT = 64 * WX * BY;
     const int nb = (int)gridDim.x;
     const long long plane = (long long)nx * ny;
     PlainField<T> f{p, plane};
-    UpdateEpi<T, VEC, XM> epi{x, r, pprev, plane, T(0), T(0)};
+    UpdateEpi<T, VEC, XM> epi{x, r, {p1, p2, p3}, plane, T(0), {T(0), T(0), T(0)}};
     // alpha is formed while the first planes' loads are out
     auto gate = [&]() {
         double alpha;
         if (!update_scalars<NT>(sc, partial, nb, k, &alpha)) return false;
         epi.alpha = (T)alpha;
-        if (XM == kXPair) epi.aprev = (T)sc->aslot[(k + 1) & 1];
+        if (XM) {
+#pragma unroll
+            for (int i = 0; i < UpdateEpi<T, VEC, XM>::NP; ++i)
+                epi.aprev[i] = (T)sc->aslot[(k - 1 - i) & 3];
+        }
         return true;
     };
     if (!box_zmarch<T, VEC, WX, BY, ZB, true>(nx, ny, nz, xcd, sink, f, epi, gate)) return;
@@ -918,12 +927,12 @@ __global__ __launch_bounds__(256) void ir_axpy(double *__restrict__ x, const flo
     }
 }
 
-// A step of x that waited: x += alpha_j p_j (alpha_j from slot j & 1), the
+// A step of x that waited: x += alpha_j p_j (alpha_j from slot j & 3), the
 // operation the update kernels apply to x, node by node.
 template <class T>
 __global__ __launch_bounds__(256) void cg_xstep(T *__restrict__ x, const T *__restrict__ p,
                                                 const CGScalars *sc, int j, long long n) {
-    const T a = (T)sc->aslot[j & 1];
+    const T a = (T)sc->aslot[j & 3];
     const long long stride = (long long)gridDim.x * 256 * 2;
     for (long long i = ((long long)blockIdx.x * 256 + threadIdx.x) * 2; i < n; i += stride) {
         if (i + 2 <= n) {
@@ -985,7 +994,7 @@ size_t cg_work_bytes(int nx, int ny, int nz) {
     const size_t plane = (size_t)nx * ny;
     const size_t vec = align256((size_t)(nz + 2) * plane * sizeof(double));
     const size_t part = align256((size_t)max_blocks(nx, ny, nz) * 2 * sizeof(double));
-    return 3 * vec + part + align256(sizeof(CGScalars));
+    return 5 * vec + part + align256(sizeof(CGScalars));
 }
 
 CGWork cg_work_carve(void *base, int nx, int ny, int nz) {
@@ -995,10 +1004,9 @@ CGWork cg_work_carve(void *base, int nx, int ny, int nz) {
     char *c = static_cast<char *>(base);
     CGWork w;
     w.r = reinterpret_cast<double *>(c) + plane;
-    w.p[0] = reinterpret_cast<double *>(c + vec) + plane;
-    w.p[1] = reinterpret_cast<double *>(c + 2 * vec) + plane;
-    w.partial = reinterpret_cast<double *>(c + 3 * vec);
-    w.sc = reinterpret_cast<CGScalars *>(c + 3 * vec + part);
+    for (int i = 0; i < 4; ++i) w.p[i] = reinterpret_cast<double *>(c + (1 + i) * vec) + plane;
+    w.partial = reinterpret_cast<double *>(c + 5 * vec);
+    w.sc = reinterpret_cast<CGScalars *>(c + 5 * vec + part);
     return w;
 }
 
@@ -1053,22 +1061,24 @@ CGWorkF32 cg_ir_work_carve(void *base, int nx, int ny, int nz) {
             b, x, w.r, w.partial, w.sc, nx, ny, nz, t.xcd, sink);                 \
         done = true;                                                              \
     }
+// (the launchers name pold / pnew, the direction vectors p_(k-1) / p_k, and
+// pp[0..2], p_(k-1) .. p_(k-3), for the update; XSTEPS is the update's x
+// step count when it applies them)
 #define HC_CG_ONE_DIR(V, W, B, Z)                                                 \
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
         cg_direction<ELEM, V, W, B, Z><<<grid, block, 0, s>>>(                    \
-            w.r, w.p[cur], w.p[cur ^ 1], w.partial, w.sc, nx, ny, nz, t.xcd,      \
-            sink, first, k);                                                      \
+            w.r, pold, pnew, w.partial, w.sc, nx, ny, nz, t.xcd, sink, first, k); \
         done = true;                                                              \
     }
 #define HC_CG_ONE_UPD(V, W, B, Z)                                                 \
     if (!done && key == HC_CG_KEY(V, W, B, Z)) {                                  \
-        if (xstep == kXDefer)                                                     \
-            cg_update<ELEM, V, W, B, Z, kXDefer><<<grid, block, 0, s>>>(          \
-                x, w.r, w.p[cur ^ 1], w.p[cur], w.partial, w.sc, nx, ny, nz,      \
+        if (xsteps == 0)                                                          \
+            cg_update<ELEM, V, W, B, Z, 0><<<grid, block, 0, s>>>(                \
+                x, w.r, pnew, pp[0], pp[1], pp[2], w.partial, w.sc, nx, ny, nz,   \
                 t.xcd, sink, k);                                                  \
         else                                                                      \
-            cg_update<ELEM, V, W, B, Z, kXPair><<<grid, block, 0, s>>>(           \
-                x, w.r, w.p[cur ^ 1], w.p[cur], w.partial, w.sc, nx, ny, nz,      \
+            cg_update<ELEM, V, W, B, Z, XSTEPS><<<grid, block, 0, s>>>(           \
+                x, w.r, pnew, pp[0], pp[1], pp[2], w.partial, w.sc, nx, ny, nz,   \
                 t.xcd, sink, k);                                                  \
         done = true;                                                              \
     }
@@ -1103,15 +1113,19 @@ hipError_t launch_cg_ir_residual(const double *b, const double *x, const CGWorkF
 }
 
 #define ELEM double
-hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int k, int nx,
-                               int ny, int nz, const CGTiling &t, double *sink,
-                               hipStream_t s) {
+#define XSTEPS 4
+hipError_t launch_cg_direction(const CGWork &w, int first, int k, int nx, int ny, int nz,
+                               const CGTiling &t, double *sink, hipStream_t s) {
+    const double *pold = w.p[(k - 1) & 3];
+    double *pnew = w.p[k & 3];
     HC_CG_DISPATCH(HC_CG_SHAPES, DIR);
 }
 
-hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int xstep, int nx,
-                            int ny, int nz, const CGTiling &t, double *sink, hipStream_t s) {
-    if (xstep != kXDefer && xstep != kXPair) return hipErrorInvalidValue;
+hipError_t launch_cg_update(double *x, const CGWork &w, int k, int xsteps, int nx, int ny,
+                            int nz, const CGTiling &t, double *sink, hipStream_t s) {
+    if (xsteps != 0 && xsteps != XSTEPS) return hipErrorInvalidValue;
+    const double *pnew = w.p[k & 3];
+    const double *pp[3] = {w.p[(k - 1) & 3], w.p[(k - 2) & 3], w.p[(k - 3) & 3]};
     HC_CG_DISPATCH(HC_CG_SHAPES, UPD);
 }
 
@@ -1133,19 +1147,28 @@ hipError_t launch_lap7_f64(const double *x, double *y, int nx, int ny, int nz,
                            const CGTiling &t, double *sink, hipStream_t s) {
     HC_CG_DISPATCH(HC_CG_SHAPES, LAP);
 }
+#undef XSTEPS
 #undef ELEM
 
+// The binary32 inner solve keeps two direction vectors (p[cur] the last,
+// p[cur ^ 1] the one formed now) and takes d's steps two at a time.
 #define ELEM float
+#define XSTEPS 2
 hipError_t launch_cg_direction_f32(const CGWorkF32 &w, int cur, int first, int k, int nx,
                                    int ny, int nz, const CGTiling &t, double *sink,
                                    hipStream_t s) {
+    const float *pold = w.p[cur];
+    float *pnew = w.p[cur ^ 1];
     HC_CG_DISPATCH(HC_CG_SHAPES_F32, DIR);
 }
 
 hipError_t launch_cg_update_f32(const CGWorkF32 &w, int cur, int k, int xstep, int nx, int ny,
                                 int nz, const CGTiling &t, double *sink, hipStream_t s) {
-    if (xstep != kXDefer && xstep != kXPair) return hipErrorInvalidValue;
+    if (xstep != 0 && xstep != 1) return hipErrorInvalidValue;
     float *const x = w.d;
+    const int xsteps = xstep ? XSTEPS : 0;
+    const float *pnew = w.p[cur ^ 1];
+    const float *pp[3] = {w.p[cur], nullptr, nullptr};
     HC_CG_DISPATCH(HC_CG_SHAPES_F32, UPD);
 }
 
@@ -1167,6 +1190,7 @@ hipError_t launch_lap7_f32(const float *x, float *y, int nx, int ny, int nz, con
                            double *sink, hipStream_t s) {
     HC_CG_DISPATCH(HC_CG_SHAPES_F32, LAP);
 }
+#undef XSTEPS
 #undef ELEM
 
 hipError_t launch_ir_axpy(double *x, const float *d, long long n, hipStream_t s) {

@@ -174,7 +174,7 @@ struct CGScalars {
     double inner_tol; // refinement: relative reduction of each inner solve
     double floor_frac;// refinement: inner solves stop at floor_frac * tol ||b||
     double rslot[2];  // r.r of iteration k in slot k & 1 (device use)
-    double aslot[2];  // alpha of iteration k in slot k & 1 (device use)
+    double aslot[4];  // alpha of iteration k in slot k & 3 (device use)
     int iter;         // completed iterations
     int state;        // 0 running, 1 converged, -6 breakdown, -7 non-finite
     unsigned ticket;  // arrival counter of the residual kernels (0 between kernels)
@@ -185,7 +185,7 @@ struct CGScalars {
 // below plane 0 and one above plane nz-1 (cleared by the driver).
 struct CGWork {
     double *r;
-    double *p[2];
+    double *p[4];      // the direction vector of iteration k is p[k & 3]
     double *partial;   // two doubles per block
     CGScalars *sc;
 };
@@ -231,15 +231,14 @@ hipError_t launch_cg_residual(const double *b, const double *x, const CGWork &w,
 // kernels; after a batch, launch_cg_settle(k) with k the next iteration
 // finishes the last update's reduction so that the scalars show whether the
 // solve has converged.
-hipError_t launch_cg_direction(const CGWork &w, int cur, int first, int k, int nx,
-                               int ny, int nz, const CGTiling &t, double *sink,
-                               hipStream_t s);
-// xstep: 0 leaves x alone (this iteration's step on x waits), 1 applies the
-// previous iteration's step and this one's (p_(k-1) is w.p[cur]), 2 this
-// one's only.
-hipError_t launch_cg_update(double *x, const CGWork &w, int cur, int k, int xstep, int nx,
-                            int ny, int nz, const CGTiling &t, double *sink, hipStream_t s);
-// x += alpha_j p over n nodes, alpha_j from sc's slot j & 1: a step of x
+hipError_t launch_cg_direction(const CGWork &w, int first, int k, int nx, int ny, int nz,
+                               const CGTiling &t, double *sink, hipStream_t s);
+// xsteps: how many of x's steps the update of iteration k applies: 0 (this
+// iteration's step waits) or 4 (those of iterations k-3 .. k, in that
+// order).  The direction of iteration k reads p[(k-1)&3] and writes p[k&3].
+hipError_t launch_cg_update(double *x, const CGWork &w, int k, int xsteps, int nx, int ny,
+                            int nz, const CGTiling &t, double *sink, hipStream_t s);
+// x += alpha_j p over n nodes, alpha_j from sc's slot j & 3: a step of x
 // that waited (see launch_cg_update).
 hipError_t launch_cg_xstep(double *x, const double *p, const CGScalars *sc, int j, long long n,
                            hipStream_t s);

@@ -307,7 +307,7 @@ def test_non_finite_data_is_reported(gpu):
     assert st == 0 and rel <= 1e-10
 
 
-@pytest.mark.parametrize("maxit", [1, 2, 3, 15, 16, 17, 33])
+@pytest.mark.parametrize("maxit", [1, 2, 3, 4, 5, 6, 7, 15, 16, 17, 33])
 def test_iteration_budget_across_host_polls(gpu, maxit):
     """The host polls the device scalars every 16 iterations; a budget that
     ends just before, at or after a poll stops at exactly maxit, and the

@@ -62,7 +62,7 @@ def test_noalloc_matches_allocating_entry_point(gpu):
 def test_noalloc_limits_and_resume(gpu):
     note("cg_solve_noalloc: size limit, maxit and resume")
     # a box whose workspace exceeds the fixed array is refused before any launch
-    n = 141
+    n = 136
     assert gpu.cg_workspace_bytes(n, n, n) + 16384 > gpu.CG_NOALLOC_BYTES
     b = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
     x = torch.full_like(b, 2.0)
@@ -72,7 +72,7 @@ def test_noalloc_limits_and_resume(gpu):
     assert bool((x == 2.0).all())
     del b, x
     # the largest cube fits and converges
-    n = 140
+    n = 135
     assert gpu.cg_workspace_bytes(n, n, n) + 16384 <= gpu.CG_NOALLOC_BYTES
     xs = torch.from_numpy(inputs.manufactured_solution(n, seed=33)).cuda()
     b = torch.empty_like(xs)
