@@ -48,7 +48,7 @@ namespace hc {
 namespace {
 
 constexpr int kPF = 2;   // planes of field loads in flight
-constexpr int kPFE = 1;  // planes ahead the epilogue's own loads are issued
+constexpr int kPFE = 1;  // planes ahead the epilogue's own loads are issued (Epi::kAhead)
 
 // Block order: the hardware deals workgroups to the 8 XCDs round-robin; with
 // g > 1, runs of g consecutive tiles (y-neighbours) are dealt to one XCD
@@ -316,13 +316,14 @@ __device__ __forceinline__ bool box_zmarch(int nx, int ny, int nz, int xcd, doub
 #pragma unroll
         for (int s = 0; s < kPF; ++s) ringv(pl(s + 1), rg[s]);
 #pragma unroll
-        for (int s = 0; s < kPFE && s < ZB; ++s) pre[s] = epi.prefetch(pl(s + 1), g.own_b);
+        for (int s = 0; s < Epi::kAhead && s < ZB; ++s) pre[s] = epi.prefetch(pl(s + 1), g.own_b);
 #pragma unroll
         for (int s = 0; s < ZB; ++s) {
             __syncthreads();
             put(q[s + 1], rg[s]);
             if (s + kPF < ZB) ringv(pl(s + 1 + kPF), rg[s + kPF]);
-            if (s + kPFE < ZB) pre[s + kPFE] = epi.prefetch(pl(s + 1 + kPFE), g.own_b);
+            if (s + Epi::kAhead < ZB)
+                pre[s + Epi::kAhead] = epi.prefetch(pl(s + 1 + Epi::kAhead), g.own_b);
             __syncthreads();
             T ns[VEC];
             nsums(q[s], q[s + 1], q[s + 2], ns);
@@ -615,6 +616,7 @@ struct NoPre {
 template <int VEC>
 struct ResidualEpi {
     using Pre = NoPre;
+    static constexpr int kAhead = kPFE;
     const double *__restrict__ b;
     double *__restrict__ r;
     long long plane;
@@ -643,6 +645,7 @@ struct ResidualEpi {
 template <int VEC>
 struct IRResidualEpi {
     using Pre = NoPre;
+    static constexpr int kAhead = kPFE;
     const double *__restrict__ b;
     float *__restrict__ s;
     long long plane;
@@ -673,6 +676,7 @@ struct IRResidualEpi {
 template <class T, int VEC>
 struct DirectionEpi {
     using Pre = NoPre;
+    static constexpr int kAhead = kPFE;
     T *__restrict__ pnew;
     long long plane;
     double acc = 0.0;
@@ -703,6 +707,7 @@ template <class T, int VEC, int XM>
 struct UpdateEpi {
     static_assert(XM == 0 || XM == 2 || XM == 4, "x steps: 0, 2 or 4");
     static constexpr int NP = XM > 1 ? XM - 1 : 1;  // earlier direction vectors read
+    static constexpr int kAhead = XM == 4 ? 2 : kPFE;
     struct Pre {
         T x[XM ? VEC : 1], r[VEC], pp[NP][XM ? VEC : 1];
     };
@@ -747,6 +752,7 @@ struct UpdateEpi {
 template <class T, int VEC>
 struct Lap7Epi {
     using Pre = NoPre;
+    static constexpr int kAhead = kPFE;
     T *__restrict__ y;
     long long plane;
     __device__ Pre prefetch(int, unsigned) const { return Pre{0}; }
