@@ -325,6 +325,27 @@ def test_iteration_budget_across_host_polls(gpu, maxit):
     assert np.max(np.abs(x - ref.x)) <= 1e-9 * np.max(np.abs(ref.x))
 
 
+def test_restarts_after_a_residual_gap(gpu):
+    """A tolerance below what binary64 can reach (1e-17) lets the recursive
+    residual meet it while the true residual cannot: the solver restarts
+    from its iterate three times, then reports HC_ENOTCONV before maxit.
+    Every restart begins a new group of x's waiting steps, so the returned
+    x must carry every step taken: its residual, computed here from the
+    returned x with the oracle's operator, is at the level binary64 allows
+    and is the one the solver reported."""
+    n = 20
+    note("cg with tol 1e-17: residual gap and restarts")
+    xs = inputs.manufactured_solution(n, seed=15)
+    b = oracle.lap7_apply(xs)
+    maxit = 5000
+    st, it, rel, x = gpu_cg(gpu, b, 1e-17, maxit)
+    assert st == 1 and it < maxit
+    mine = np.linalg.norm(b - oracle.lap7_apply(x)) / np.linalg.norm(b)
+    assert mine < 1e-13
+    assert abs(rel - mine) <= 1e-6 * mine
+    assert np.max(np.abs(x - xs)) <= 1e-11 * np.max(np.abs(xs))
+
+
 def test_workspace_contents_do_not_matter(gpu):
     """Partial sums and scalar slots are written before they are read: a
     caller workspace full of NaN bit patterns gives the same bits as a
