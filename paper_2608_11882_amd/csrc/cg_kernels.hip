@@ -707,6 +707,8 @@ template <class T, int VEC, int XM>
 struct UpdateEpi {
     static_assert(XM == 0 || XM == 2 || XM == 4, "x steps: 0, 2 or 4");
     static constexpr int NP = XM > 1 ? XM - 1 : 1;  // earlier direction vectors read
+    // the four-step form has five loads of its own per plane: they go out
+    // two planes ahead (measured 0.5% faster per iteration than one)
     static constexpr int kAhead = XM == 4 ? 2 : kPFE;
     struct Pre {
         T x[XM ? VEC : 1], r[VEC], pp[NP][XM ? VEC : 1];
