@@ -518,7 +518,8 @@ int hc_batch_layout(const hc_batch *b, long long *offsets, int *pitches,
  *            graph, joined to `stream` through events.
  * Each launch runs a persistent kernel whose blocks walk the work list of
  * (problem, x-tile, y-tile, run of planes) entries; with two steps per pass
- * (hc_batch_steps_per_pass) there is one launch per width class and pass.
+ * (hc_batch_steps_per_pass) there is one launch per width class and pass,
+ * each class's passes in a chain of their own on an internal stream.
  * Enqueued; does not wait.
  */
 int hc_batch_step(hc_batch *b, void *u, void *u_new, int steps, int use_graph,

@@ -1138,30 +1138,36 @@ void batch_drop_graph(hc_batch *b) {
     b->g_steps = -1;
 }
 
-// The step loop on stream s: `steps` launches alternating the buffers, then
-// the copy that leaves the result in u when steps is odd.
 // Steps per pass the batch takes with its current shape: two when the
 // library's setting asks for two and the shape is built for them.
 int batch_time_block(const hc_batch *b) {
     return current_time_block() == 2 && hc::batch2_tiling_supported(b->dtype, b->tiling) ? 2 : 1;
 }
 
+// The step loop on stream s: the passes alternate the buffers (a last odd
+// step takes one single-step launch), then a copy leaves the result in u
+// when it ended in u_new.
 int batch_enqueue(hc_batch *b, void *u, void *un, int steps, hipStream_t s) {
     const int eb = hc::dtype_bytes(b->dtype);
     const int tb = batch_time_block(b);
     void *a = u, *c = un;
-    for (int st = 0; st < steps;) {
-        if (tb == 2 && steps - st >= 2) {
-            // one launch per width class present; the classes run side by
-            // side, so their tails overlap
-            int used[5], nc = 0;
-            for (int k = 4; k >= 0; --k)
-                if (b->cls_count[k] > 0) used[nc++] = k;
-            if (nc > 1) {
-                HC_TRY(hipEventRecord(b->ev_fork, s), "hipEventRecord");
-                for (int i = 1; i < nc; ++i)
-                    HC_TRY(hipStreamWaitEvent(b->cstream[i - 1], b->ev_fork, 0), "hipStreamWaitEvent");
-            }
+    int st = 0;
+    if (tb == 2 && steps >= 2) {
+        // One launch per width class present and pass.  A class touches
+        // only its own problems, so each class runs its passes as a chain on
+        // a stream of its own: the chains run side by side from the first
+        // pass to the last and join once, so no pass waits for the slowest
+        // class of the pass before.
+        const int passes = steps / 2;
+        int used[5], nc = 0;
+        for (int k = 4; k >= 0; --k)
+            if (b->cls_count[k] > 0) used[nc++] = k;
+        if (nc > 1) {
+            HC_TRY(hipEventRecord(b->ev_fork, s), "hipEventRecord");
+            for (int i = 1; i < nc; ++i)
+                HC_TRY(hipStreamWaitEvent(b->cstream[i - 1], b->ev_fork, 0), "hipStreamWaitEvent");
+        }
+        for (int p = 0; p < passes; ++p) {
             for (int i = 0; i < nc; ++i) {
                 const int k = used[i];
                 hipStream_t ks = i == 0 ? s : b->cstream[i - 1];
@@ -1170,17 +1176,18 @@ int batch_enqueue(hc_batch *b, void *u, void *un, int steps, hipStream_t s) {
                                               b->grid, b->tiling, ks),
                        "heat_batch2 launch");
             }
-            for (int i = 1; i < nc; ++i) {
-                HC_TRY(hipEventRecord(b->ev_join[i - 1], b->cstream[i - 1]), "hipEventRecord");
-                HC_TRY(hipStreamWaitEvent(s, b->ev_join[i - 1], 0), "hipStreamWaitEvent");
-            }
-            st += 2;
-        } else {
-            HC_TRY(hc::launch_heat_batch(b->dtype, a, c, b->d_probs, b->d_items, b->nitems,
-                                         b->grid, b->tiling, s),
-                   "heat_batch launch");
-            ++st;
+            std::swap(a, c);
         }
+        for (int i = 1; i < nc; ++i) {
+            HC_TRY(hipEventRecord(b->ev_join[i - 1], b->cstream[i - 1]), "hipEventRecord");
+            HC_TRY(hipStreamWaitEvent(s, b->ev_join[i - 1], 0), "hipStreamWaitEvent");
+        }
+        st = 2 * passes;
+    }
+    for (; st < steps; ++st) {
+        HC_TRY(hc::launch_heat_batch(b->dtype, a, c, b->d_probs, b->d_items, b->nitems, b->grid,
+                                     b->tiling, s),
+               "heat_batch launch");
         std::swap(a, c);
     }
     if (a != u)
