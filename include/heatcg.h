@@ -306,7 +306,10 @@ int cg_solve_ex(const double *b, double *x, int nx, int ny, int nz, double tol,
                 int maxit, void *work, size_t work_bytes, hc_stream_t stream,
                 int *iters, double *true_relres);
 
-/* Bytes of device workspace cg_solve_ex needs (0 for invalid sizes). */
+/* Bytes of device workspace cg_solve_ex needs (0 for invalid sizes): the
+ * residual and four direction vectors, each with a zero plane below and
+ * above the box, per-block partial sums and the scalar block (about 676 MB
+ * at 256^3). */
 size_t cg_workspace_bytes(int nx, int ny, int nz);
 
 /*
