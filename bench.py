@@ -431,7 +431,7 @@ def batch_section(hc, dev, sequential_solves=True, shape=None):
 
     if shape is None:
         log("batch: autotune")
-        tuned_ms = batch.autotune(u0, trial_steps=4)
+        tuned_ms = batch.autotune(u0, trial_steps=20)
     else:
         batch.set_tiling(*shape)
         tuned_ms = float("nan")

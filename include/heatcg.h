@@ -560,9 +560,11 @@ int hc_batch_classes(hc_batch *b, int *classes);
  * persistent grid of 2 blocks per compute unit, and with every width class
  * for all problems, over
  * trial_steps (rounded up to even) steps of the states in u (on two
- * scratch buffers the call allocates and frees; u is not written), and
- * keep the fastest.  Blocks until done; *best_ms (may be NULL) receives
- * its time per step.  hc_batch_tune_result(b, i, shape8, ms) returns
+ * scratch buffers the call allocates and frees; u is not written), time the
+ * four fastest again over twice as many steps, twice each, and keep the
+ * fastest of those.  Blocks until done; *best_ms (may be NULL) receives its
+ * time per step in that second round (hc_batch_tune_result gives the first
+ * round's times).  hc_batch_tune_result(b, i, shape8, ms) returns
  * candidate i's setting {vec, threads, zdepth, pf, xcd, width_class, grid,
  * item_depth} and time per step; with i < 0 it returns the number of
  * candidates.

@@ -624,9 +624,10 @@ class Batch:
         """Steps one launch of this batch's shape advances (1 or 2)."""
         return _check(load().hc_batch_steps_per_pass(self._h))
 
-    def autotune(self, u, trial_steps: int = 4, stream=None) -> float:
-        """Time every candidate shape on copies of u; keep the fastest.
-        Returns its milliseconds per step."""
+    def autotune(self, u, trial_steps: int = 20, stream=None) -> float:
+        """Time every candidate shape on copies of u, the four fastest again
+        over twice the steps; keep the fastest of those.  Returns its
+        milliseconds per step."""
         best = ctypes.c_double(0.0)
         _check(load().hc_batch_autotune(self._h, ctypes.c_void_p(u.data_ptr()), int(trial_steps),
                                         _stream_handle(u, stream), ctypes.byref(best)))

@@ -173,9 +173,12 @@ def test_autotune_keeps_results_bitwise(gpu):
     best = batch.autotune(u, trial_steps=2)
     assert torch.equal(u, keep)                     # the tuner does not write u
     res = batch.tune_results()
-    assert len(res) >= 40 and best == min(ms for _, ms in res) and best > 0
+    assert len(res) >= 40 and best > 0
+    # the kept shape is one of the four fastest of the first round (those
+    # are timed again and the fastest of the second round is kept)
     t = batch.get_tiling()
-    assert any(sh == t for sh, _ in res)
+    kept = [ms for sh, ms in res if sh == t]
+    assert len(kept) == 1 and kept[0] <= sorted(ms for _, ms in res)[3]
     got = run_batch(gpu, batch, fields, 6)
     for p in range(len(dims)):
         assert np.array_equal(got[p], oracle.heat_f32(fields[p], rs[p], 6))
