@@ -997,7 +997,8 @@ static long long max_blocks(int nx, int ny, int nz) {
     return ((nx + 63) / 64LL) * ((ny + 3) / 4LL) * ((nz + 7) / 8LL);
 }
 
-// r, p0 and p1 each carry a zero plane below and above the box (see ZPAD).
+// r and the four direction vectors p0..p3 each carry a zero plane below and
+// above the box (see ZPAD).
 size_t cg_work_bytes(int nx, int ny, int nz) {
     const size_t plane = (size_t)nx * ny;
     const size_t vec = align256((size_t)(nz + 2) * plane * sizeof(double));
