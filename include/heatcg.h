@@ -117,6 +117,27 @@ int heat_step_ex(void *u, void *u_new, int nx, int ny, int nz, double r,
                  int steps, int dtype, int mode, int parts, hc_stream_t stream);
 
 /*
+ * heat_step_streams -- the split form (HC_HEAT_SPLIT) on two streams the
+ * caller chooses: the Interior kernels on s_int, the Boundary kernels on
+ * s_bnd, joined at every step (the asynchronous Interior / Boundary
+ * decomposition of the paper's stream versions, Pseudocodes
+ * alg:2gpu-stream and alg:boundary-kernel-async, on one device).
+ *
+ *  u, u_new, nx, ny, nz, r, steps, dtype, parts  as for heat_step_ex.
+ *  s_int  the work is ordered on it: the run starts after its earlier
+ *         work, and u holds the result once its work up to here is done.
+ *  s_bnd  a stream of the current device (else HC_EINVAL), or s_int
+ *         itself (the Boundary kernels then run before the Interior kernel
+ *         of each step).  It waits for s_int before the first step and at
+ *         the end of every step, so work the caller enqueues on it later
+ *         runs after the whole sweep.
+ * Enqueues and returns; validation and statuses as for heat_step_ex.
+ */
+int heat_step_streams(void *u, void *u_new, int nx, int ny, int nz, double r,
+                      int steps, int dtype, int parts, hc_stream_t s_int,
+                      hc_stream_t s_bnd);
+
+/*
  * heat_step_sr -- heat_step_ex for bfloat16 storage (HC_BF16 layout and
  * rules) with stochastic instead of nearest rounding.  Nearest rounding
  * drops every increment below half a bfloat16 ulp, so smooth fields stall;

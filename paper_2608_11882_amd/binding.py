@@ -68,6 +68,7 @@ def load():
     sig = {
         "heat_step": (i, [vp, vp, i, i, i, d, i]),
         "heat_step_ex": (i, [vp, vp, i, i, i, d, i, i, i, i, vp]),
+        "heat_step_streams": (i, [vp, vp, i, i, i, d, i, i, i, vp, vp]),
         "heat_step_sr": (i, [vp, vp, i, i, i, d, i, ctypes.c_uint64, ctypes.c_uint64, i, i, vp]),
         "cg_solve": (i, [vp, vp, i, d, i]),
         "cg_solve_ex": (i, [vp, vp, i, i, i, d, i, vp, sz, vp, ip, dp]),
@@ -168,15 +169,25 @@ def _require_cuda_3d(*ts):
 
 
 def heat_step(u, u_new, r: float, steps: int, mode: str = "split", parts: int = 1,
-              stream=None) -> None:
+              stream=None, bnd_stream=None) -> None:
     """Advance ``u`` by ``steps`` explicit 7-point steps (result in ``u``).
 
     ``u_new`` is scratch of the same shape.  Enqueued on ``stream`` (default:
-    torch's current stream); does not synchronize.
+    torch's current stream); does not synchronize.  With ``bnd_stream`` (a
+    torch stream, split mode only) the Boundary kernels run on it
+    (heat_step_streams).
     """
     _require_cuda_3d(u, u_new)
     nz, ny, nx = u.shape
     lib = load()
+    if bnd_stream is not None:
+        if mode != "split":
+            raise ValueError("a Boundary stream needs the split mode")
+        _check(lib.heat_step_streams(ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(u_new.data_ptr()), nx, ny, nz, float(r),
+                                     int(steps), _dtype_code(u), int(parts),
+                                     _stream_handle(u, stream), _stream_handle(u, bnd_stream)))
+        return
     _check(lib.heat_step_ex(ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(u_new.data_ptr()),
                             nx, ny, nz, float(r), int(steps), _dtype_code(u), MODES[mode],
                             int(parts), _stream_handle(u, stream)))

@@ -547,12 +547,17 @@ double tile_algo_bytes(const hc::ZTable &t, int nx, int ny, int nz, size_t elem,
 // The explicit sweep in any of its forms.  With kap == nullptr it is the
 // constant-coefficient step with r; otherwise the variable-coefficient step
 // with source rhs and beta = r (FP64 or FP32).
+// bnd (with own_bnd): the stream of the Boundary kernels in the split form,
+// else the library's internal stream; it joins s at every step through
+// events.
 int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int steps, int mode,
              int parts, unsigned long long seed, unsigned long long step0, hipStream_t s,
-             const void *kap = nullptr, const void *rhs = nullptr) {
+             const void *kap = nullptr, const void *rhs = nullptr, bool own_bnd = false,
+             hipStream_t bnd = nullptr) {
     DevState *d = nullptr;
     int rc = device_state(&d);
     if (rc) return rc;
+    hipStream_t const aux = own_bnd ? bnd : d->aux;
     const bool vk = kap != nullptr;
     const size_t eb = (size_t)hc::dtype_bytes(dtype);
     const void *arrays[4] = {u, un, kap, rhs};
@@ -655,7 +660,7 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
     const bool split = (mode == HC_HEAT_SPLIT) && (tbd.n > 0 || tbd2.n > 0);
     if (split) {
         HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
-        HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
+        HC_TRY(hipStreamWaitEvent(aux, d->ev_main, 0), "hipStreamWaitEvent");
     }
     void *a = u, *b = un;
     for (int st = 0; st < steps;) {
@@ -666,8 +671,8 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                 tm.done();
             } else {
                 {
-                    Timed tm(k2_bd, d->aux, bytes_bd2);
-                    HC_TRY(tile2_launch(k2_bd, tbd2, a, b, d->aux), "heat2_boundary launch");
+                    Timed tm(k2_bd, aux, bytes_bd2);
+                    HC_TRY(tile2_launch(k2_bd, tbd2, a, b, aux), "heat2_boundary launch");
                     tm.done();
                 }
                 if (tin2.n > 0) {
@@ -676,9 +681,9 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
                     tm.done();
                 }
                 HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
-                HC_TRY(hipEventRecord(d->ev_aux, d->aux), "hipEventRecord");
+                HC_TRY(hipEventRecord(d->ev_aux, aux), "hipEventRecord");
                 HC_TRY(hipStreamWaitEvent(s, d->ev_aux, 0), "hipStreamWaitEvent");
-                HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
+                HC_TRY(hipStreamWaitEvent(aux, d->ev_main, 0), "hipStreamWaitEvent");
             }
             std::swap(a, b);
             st += 2;
@@ -698,8 +703,8 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
             // the short Boundary kernel goes first, so it is long done when
             // the next step's Interior kernel waits for it
             {
-                Timed tm(k_bd, d->aux, bytes_bd);
-                HC_TRY(tile_launch(k_bd, tbd, a, b, step0 + st, d->aux), "heat_boundary launch");
+                Timed tm(k_bd, aux, bytes_bd);
+                HC_TRY(tile_launch(k_bd, tbd, a, b, step0 + st, aux), "heat_boundary launch");
                 tm.done();
             }
             if (tin.n > 0) {
@@ -709,9 +714,9 @@ int heat_run(int dtype, void *u, void *un, int nx, int ny, int nz, double r, int
             }
             // join: the next step needs both halves of this one, in both streams
             HC_TRY(hipEventRecord(d->ev_main, s), "hipEventRecord");
-            HC_TRY(hipEventRecord(d->ev_aux, d->aux), "hipEventRecord");
+            HC_TRY(hipEventRecord(d->ev_aux, aux), "hipEventRecord");
             HC_TRY(hipStreamWaitEvent(s, d->ev_aux, 0), "hipStreamWaitEvent");
-            HC_TRY(hipStreamWaitEvent(d->aux, d->ev_main, 0), "hipStreamWaitEvent");
+            HC_TRY(hipStreamWaitEvent(aux, d->ev_main, 0), "hipStreamWaitEvent");
         }
         std::swap(a, b);
         ++st;
@@ -1340,6 +1345,29 @@ int heat_vk_step(void *u, void *u_new, const void *kappa, const void *rhs, int n
     if ((rc = check_device_buffer(rhs, bytes, "rhs"))) return rc;
     return heat_run(dtype, u, u_new, nx, ny, nz, beta, steps, mode, parts, 0, 0,
                     reinterpret_cast<hipStream_t>(stream), kappa, rhs);
+}
+
+int heat_step_streams(void *u, void *u_new, int nx, int ny, int nz, double r, int steps,
+                      int dtype, int parts, hc_stream_t s_int, hc_stream_t s_bnd) {
+    g_msg.clear();
+    size_t bytes = 0;
+    int rc = validate_heat(u, u_new, nx, ny, nz, r, steps, dtype, HC_HEAT_SPLIT, parts, &bytes);
+    if (rc) return rc;
+    if (steps == 0) return HC_OK;
+    if ((rc = check_device_buffer(u, bytes, "u"))) return rc;
+    if ((rc = check_device_buffer(u_new, bytes, "u_new"))) return rc;
+    hipStream_t const si = reinterpret_cast<hipStream_t>(s_int);
+    hipStream_t const sb = reinterpret_cast<hipStream_t>(s_bnd);
+    if (sb != si) {
+        int dev = 0, sdev = 0;
+        HC_TRY(hipGetDevice(&dev), "hipGetDevice");
+        HC_TRY(hipStreamGetDevice(sb, &sdev), "hipStreamGetDevice (s_bnd)");
+        if (sdev != dev)
+            return fail(HC_EINVAL, "s_bnd belongs to device %d, the current device is %d", sdev,
+                        dev);
+    }
+    return heat_run(dtype, u, u_new, nx, ny, nz, r, steps, HC_HEAT_SPLIT, parts, 0, 0, si,
+                    nullptr, nullptr, true, sb);
 }
 
 int heat_step(double *u, double *u_new, int nx, int ny, int nz, double r, int steps) {

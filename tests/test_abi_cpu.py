@@ -67,6 +67,18 @@ def test_heat_step_validation_happens_before_device_work(lib, args, code):
         assert lib.hc_last_error_message().decode() != ""
 
 
+def test_heat_step_streams_validates_before_any_device_work(lib):
+    """Arguments are checked before the library touches a device or a
+    stream (these calls run without a GPU)."""
+    f = lib.heat_step_streams
+    s = ctypes.c_void_p(0)
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.2, 4, 0, 1, s, s) == HC_EUNSTABLE
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 4, 0, 0, s, s) == HC_EINVAL    # parts < 1
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 4, 9, 1, s, s) == HC_EINVAL    # dtype
+    assert f(FAKE_U, FAKE_U, 10, 10, 10, 0.1, 4, 0, 1, s, s) == HC_EALIAS
+    assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 0, 0, 1, s, s) == 0            # nothing to do
+
+
 def test_heat_step_ex_rejects_bad_mode_dtype_and_parts(lib):
     f = lib.heat_step_ex
     assert f(FAKE_U, FAKE_V, 10, 10, 10, 0.1, 1, 7, 0, 1, None) == HC_EINVAL      # dtype

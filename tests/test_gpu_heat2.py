@@ -82,6 +82,43 @@ def test_split_into_slabs_bitwise(two_steps, parts):
     assert np.array_equal(run(two_steps, u0, 0.12, 7, "f64", parts=parts), want)
 
 
+@pytest.mark.parametrize("dtype,parts,steps", [("f64", 1, 7), ("f64", 3, 6), ("f32", 2, 5),
+                                               ("bf16", 1, 4)])
+def test_caller_boundary_stream_bitwise(two_steps, dtype, parts, steps):
+    """heat_step_streams: the Boundary kernels on a stream of the caller's
+    (a second torch stream, or the Interior stream itself) give the oracle's
+    bits, and the result is complete once the Interior stream's work is
+    done (the run joins the two streams at every step, the last included)."""
+    dims = (67, 33, 41)
+    r = 0.14
+    u0 = start(dims, 11 + parts, dtype)
+    want = reference(u0, r, steps, dtype)
+    side = torch.cuda.Stream()
+    for which in ("second stream", "same stream"):
+        note("heat_step_streams %s parts=%d steps=%d, %s" % (dtype, parts, steps, which))
+        if dtype == "bf16":
+            u = torch.from_numpy(u0.view(np.int16)).cuda().view(torch.bfloat16)
+        else:
+            u = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+        un = torch.empty_like(u)
+        main = torch.cuda.current_stream()
+        bnd = side if which == "second stream" else main
+        torch.cuda.synchronize()
+        two_steps.heat_step(u, un, r, steps, parts=parts, stream=main, bnd_stream=bnd)
+        main.synchronize()                 # only the Interior stream
+        got = u.view(torch.int16).cpu().numpy().view(np.uint16) if dtype == "bf16" \
+            else u.cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(got, want), (dtype, parts, steps, which)
+
+
+def test_caller_boundary_stream_rejects_fused_mode(gpu):
+    u = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        gpu.heat_step(u, torch.empty_like(u), 0.1, 2, mode="fused",
+                      bnd_stream=torch.cuda.Stream())
+
+
 def built_shapes(hc, dtype):
     lib = hc.load()
     code = hc.DTYPES[dtype]
